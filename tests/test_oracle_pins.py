@@ -1,0 +1,257 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test checks a closed form, an invariant, a hand-computed matrix or an
+outside library routine for the DFT defined in the paper's Background ("FFT
+Basics"): X(k) = sum_n x(n) w_N^{nk}, w_N = exp(-2 i pi/N); backward flips the
+sign of the exponent; no normalisation.  A plausible slip in the oracle (a
+dropped term, a wrong sign, a wrong index, transposed operands) fails at least
+one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import metrics
+
+FWD, BWD = -1, +1
+PIECES = {
+    "naive": oracle.dft_naive,
+    "radix2": oracle.fft_radix2,
+    "mixed": oracle.fft_mixed,
+}
+
+
+def rand_c(seed, shape):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+# ------------------------------------------------------------ hand matrices
+def test_n1_is_identity():
+    x = np.array([[3.0 - 2.0j]])
+    for fn in PIECES.values():
+        assert np.array_equal(fn(x, FWD), x)
+        assert np.array_equal(fn(x, BWD), x)
+
+
+def test_n2_hand_matrix():
+    x = np.array([[1.5 + 0.5j, -2.0 + 3.0j]])
+    F2 = np.array([[1, 1], [1, -1]])
+    for fn in PIECES.values():
+        assert np.allclose(fn(x, FWD)[0], F2 @ x[0], atol=0, rtol=1e-15)
+        assert np.allclose(fn(x, BWD)[0], F2 @ x[0], atol=0, rtol=1e-15)
+
+
+def test_n4_hand_matrix_forward_and_backward():
+    # forward rows (1,1,1,1), (1,-i,-1,i), (1,-1,1,-1), (1,i,-1,-i)
+    F4 = np.array([[1, 1, 1, 1], [1, -1j, -1, 1j], [1, -1, 1, -1], [1, 1j, -1, -1j]])
+    x = rand_c(1, (3, 4))
+    for name, fn in PIECES.items():
+        y = fn(x, FWD)
+        assert np.allclose(y, x @ F4.T, rtol=0, atol=1e-14), name
+        yb = fn(x, BWD)
+        assert np.allclose(yb, x @ np.conj(F4).T, rtol=0, atol=1e-14), name
+
+
+def test_n3_hand_matrix():
+    w = complex(-0.5, -math.sqrt(3) / 2)  # exp(-2 i pi/3)
+    F3 = np.array([[1, 1, 1], [1, w, w * w], [1, w * w, w ** 4]])
+    x = rand_c(2, (2, 3))
+    for name in ("naive", "mixed"):
+        assert np.allclose(PIECES[name](x, FWD), x @ F3.T, rtol=0, atol=1e-14), name
+
+
+# --------------------------------------------------------------- the roots
+def test_unit_root_exact_quarter_points():
+    for n in (4, 8, 16, 1024, 6000, 15360):
+        assert oracle.unit_root(0, n, FWD) == 1
+        assert oracle.unit_root(n // 4, n, FWD) == -1j
+        assert oracle.unit_root(n // 2, n, FWD) == -1
+        assert oracle.unit_root(3 * n // 4, n, FWD) == 1j
+        assert oracle.unit_root(n // 4, n, BWD) == 1j
+        assert oracle.unit_root(n, n, FWD) == 1
+        assert oracle.unit_root(-1, n, FWD) == oracle.unit_root(n - 1, n, FWD)
+
+
+@pytest.mark.parametrize("n", [8, 12, 1000, 4096])
+def test_unit_root_matches_exp_and_is_on_circle(n):
+    for m in range(0, n, max(1, n // 97)):
+        w = oracle.unit_root(m, n, FWD)
+        ref = complex(math.cos(2 * math.pi * m / n), -math.sin(2 * math.pi * m / n))
+        assert abs(w - ref) < 4e-16 * max(1, 2 * math.pi * m / n)
+        assert abs(abs(w) - 1.0) < 3e-16
+
+
+# ------------------------------------------------------------ closed forms
+@pytest.mark.parametrize("piece", list(PIECES))
+@pytest.mark.parametrize("n", [8, 64, 256])
+def test_impulse_and_shifted_impulse(piece, n):
+    fn = PIECES[piece]
+    x = np.zeros((1, n), complex)
+    x[0, 0] = 1
+    assert np.allclose(fn(x, FWD), np.ones((1, n)), atol=1e-15, rtol=0)
+    n0 = 3
+    x = np.zeros((1, n), complex)
+    x[0, n0] = 1
+    k = np.arange(n)
+    expect = np.exp(-2j * np.pi * n0 * k / n)
+    assert np.allclose(fn(x, FWD)[0], expect, atol=1e-14, rtol=0)
+    assert np.allclose(fn(x, BWD)[0], np.conj(expect), atol=1e-14, rtol=0)
+
+
+@pytest.mark.parametrize("piece", list(PIECES))
+@pytest.mark.parametrize("n", [16, 128, 1024])
+def test_constant_and_tone(piece, n):
+    fn = PIECES[piece]
+    y = fn(np.ones((1, n), complex), FWD)[0]
+    e = np.zeros(n)
+    e[0] = n
+    assert np.allclose(y, e, atol=1e-11 * n, rtol=0)
+    k0 = 5
+    tone = np.exp(2j * np.pi * k0 * np.arange(n) / n)[None, :]
+    y = fn(tone, FWD)[0]
+    e = np.zeros(n, complex)
+    e[k0] = n
+    assert np.allclose(y, e, atol=1e-11 * n, rtol=0)
+    # the backward transform of the same tone peaks at -k0
+    y = fn(tone, BWD)[0]
+    e = np.zeros(n, complex)
+    e[(-k0) % n] = n
+    assert np.allclose(y, e, atol=1e-11 * n, rtol=0)
+
+
+@pytest.mark.parametrize("piece", list(PIECES))
+def test_parseval_linearity_shift(piece):
+    fn = PIECES[piece]
+    n = 256
+    x = rand_c(3, (4, n))
+    z = rand_c(4, (4, n))
+    X = fn(x, FWD)
+    assert np.allclose(np.sum(abs(X) ** 2, -1), n * np.sum(abs(x) ** 2, -1), rtol=1e-13)
+    a, b = 0.7 - 0.2j, -1.3 + 0.4j
+    assert np.allclose(fn(a * x + b * z, FWD), a * X + b * fn(z, FWD), atol=1e-12)
+    s = 7
+    Xs = fn(np.roll(x, s, axis=-1), FWD)
+    k = np.arange(n)
+    assert np.allclose(Xs, X * np.exp(-2j * np.pi * s * k / n), atol=1e-11)
+
+
+@pytest.mark.parametrize("piece", list(PIECES))
+def test_hermitian_for_real_input(piece):
+    n = 128
+    x = np.random.default_rng(5).standard_normal((2, n)).astype(complex)
+    X = PIECES[piece](x, FWD)
+    k = np.arange(n)
+    assert np.allclose(X[:, (-k) % n], np.conj(X), atol=1e-12)
+
+
+@pytest.mark.parametrize("piece", list(PIECES))
+def test_double_forward_reverses_and_roundtrip(piece):
+    fn = PIECES[piece]
+    n = 64
+    x = rand_c(6, (3, n))
+    y = fn(fn(x, FWD), FWD)
+    idx = (-np.arange(n)) % n
+    assert np.allclose(y, n * x[:, idx], atol=1e-12)
+    assert np.allclose(fn(fn(x, FWD), BWD), n * x, atol=1e-12)
+
+
+def test_convolution_theorem():
+    n = 64
+    x, h = rand_c(7, (n,)), rand_c(8, (n,))
+    conv = np.array([sum(x[m] * h[(k - m) % n] for m in range(n)) for k in range(n)])
+    X, H, C = (oracle.fft_radix2(v[None], FWD)[0] for v in (x, h, conv))
+    assert np.allclose(C, X * H, atol=1e-11)
+
+
+# ----------------------------------------------- agreement between pieces
+@pytest.mark.parametrize("n", [2 ** k for k in range(0, 13)])
+def test_radix2_and_mixed_agree_with_definition(n):
+    x = rand_c(10 + n, (2, n))
+    ref = oracle.dft_naive(x, FWD)
+    scale = np.max(np.abs(ref))
+    for fn in (oracle.fft_radix2, oracle.fft_mixed):
+        assert np.max(np.abs(fn(x, FWD) - ref)) <= 1e-12 * scale
+        assert np.max(np.abs(fn(x, BWD) - oracle.dft_naive(x, BWD))) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("n", [3, 5, 6, 7, 12, 15, 60, 1000])
+def test_mixed_agrees_with_definition_non_pow2(n):
+    x = rand_c(20 + n, (2, n))
+    ref = oracle.dft_naive(x, FWD)
+    assert np.max(np.abs(oracle.fft_mixed(x, FWD) - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("n", [16, 1000, 3072, 4096, 6000, 15360, 2 ** 16])
+def test_against_numpy_pocketfft(n):
+    # an outside FP64 implementation, used only here as a check
+    x = rand_c(30 + n, (2, n))
+    for sign, ref in ((FWD, np.fft.fft(x)), (BWD, np.fft.ifft(x) * n)):
+        y = oracle.fft(x, sign)
+        assert np.max(np.abs(y - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_radix2_rejects_non_pow2():
+    with pytest.raises(ValueError):
+        oracle.fft_radix2(np.ones((1, 6), complex))
+
+
+# ------------------------------------------------------------------ 2-D
+def test_fft2d_separable_outer_product():
+    P, R = 16, 32
+    a, b = rand_c(40, (P,)), rand_c(41, (R,))
+    y = oracle.fft2d(np.outer(a, b)[None], FWD)[0]
+    A = oracle.fft_radix2(a[None], FWD)[0]
+    B = oracle.fft_radix2(b[None], FWD)[0]
+    assert np.allclose(y, np.outer(A, B), atol=1e-11)
+    yb = oracle.fft2d(y[None], BWD)[0]
+    assert np.allclose(yb / (P * R), np.outer(a, b), atol=1e-13)
+    assert np.allclose(y, np.fft.fft2(np.outer(a, b)), atol=1e-11)
+
+
+def test_fft2d_non_square_and_mixed():
+    x = rand_c(42, (2, 12, 20))
+    assert np.allclose(oracle.fft2d(x, FWD), np.fft.fft2(x), atol=1e-11)
+
+
+# ------------------------------------------------------------- transpose
+def test_transpose_is_exact_and_involutive():
+    x = rand_c(50, (3, 7, 11))
+    t = oracle.transpose(x)
+    assert t.shape == (3, 11, 7)
+    assert np.array_equal(t, np.swapaxes(x, -1, -2))
+    assert np.array_equal(oracle.transpose(t), x)
+
+
+# ------------------------------------------------------------- four-step
+@pytest.mark.parametrize("n1,n2", [(4, 8), (16, 16), (32, 64), (64, 16)])
+def test_fourstep_identity_equals_direct(n1, n2):
+    x = rand_c(60 + n1, (2, n1 * n2))
+    for sign in (FWD, BWD):
+        ref = oracle.fft(x, sign)
+        assert np.max(np.abs(oracle.fourstep_reference(x, n1, n2, sign) - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------- metric
+def test_metric_zero_and_scale():
+    x = rand_c(70, (3, 32))
+    e = metrics.rel_l2_per_transform(x, x)
+    assert np.all(e == 0)
+    y = x.copy()
+    y[1] *= 1 + 1e-3
+    e = metrics.rel_l2_per_transform(y, x)
+    assert e[0] == 0 and e[2] == 0 and abs(e[1] - 1e-3) < 1e-12
+    z = np.zeros((1, 8), complex)
+    assert metrics.rel_l2_per_transform(z, z)[0] == 0
+    assert metrics.tolerance(1024) == pytest.approx(1e-5)
+    with pytest.raises(AssertionError):
+        metrics.check(y, x, 32)
+
+
+def test_threaded_equals_single_thread():
+    x = rand_c(80, (9, 512))
+    a = oracle.fft_radix2(x, FWD, threads=1)
+    b = oracle.fft_radix2(x, FWD, threads=4)
+    assert np.array_equal(a, b)
