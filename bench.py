@@ -1,0 +1,308 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the batched complex64 FFT path on one MI355X.
+
+One step = one pass of the hot path over the plain workload:
+  * N = 4096, batch 4096, forward and inverse (single LDS-resident block);
+  * N = 2^20, batch 16, forward and inverse (four-step 1024 x 1024: column
+    block FFTs + twiddle, then row block FFTs + corner-turn store).
+Inputs are seeded uniform[-1,1] complex64, resident in HBM before timing;
+the step rotates over several (in, out) buffer sets so the footprint exceeds
+the 256 MB Infinity Cache (cold-cache timing).
+
+Metric: GFLOP/s counted as 5 N log2 N per transform.  Per-kernel durations
+are taken live with events between launches on the launch stream; the
+dominant kernel's algorithmic HBM bytes (16 N per transform and pass: the
+data read once and written once) over its average duration give the
+roofline fraction against 8 TB/s.  The FP64 oracle is timed on the host
+cores on the same step (CPU baseline).  Prints ONE JSON line on stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "batched c64 FFT GFLOP/s (5Nlog2N) + % HBM peak; serving p50/p99 latency"
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print("bench:", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--rotate", type=int, default=4, help="(in,out) buffer sets per shape")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle time for the CPU baseline")
+    p.add_argument("--no-extras", action="store_true", help="skip copy probe and SAR chain timing")
+    p.add_argument("--traffic", default=None,
+                   help="JSON file with measured HBM bytes per launch of the dominant kernel")
+    return p.parse_args()
+
+
+def flops(n, batch):
+    return 5.0 * n * math.log2(n) * batch if n > 1 else 0.0
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; the multi-GPU layout (batch sharding and an "
+              "all-to-all corner turn) is a design note, not implemented. Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1505_08067_amd import fftblock as fb
+    from paper_1505_08067_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    fb.load()
+    info = fb.device_query()
+    log("device", info["arch"], "CUs", info["compute_units"], "LDS/CU", info["lds_per_cu"])
+
+    # ------------------------------------------------------------ workload
+    items = [
+        ("block N=4096 fwd", 4096, 4096, fb.FORWARD),
+        ("block N=4096 inv", 4096, 4096, fb.BACKWARD),
+        ("fourstep N=2^20 fwd", 1 << 20, 16, fb.FORWARD),
+        ("fourstep N=2^20 inv", 1 << 20, 16, fb.BACKWARD),
+    ]
+    plans = {}
+    bufs = {}
+    for name, n, batch, sign in items:
+        plans[name] = fb.Plan(n, batch, sign)
+        if (n, batch) not in bufs:
+            x = torch.from_numpy(inputs.uniform(1, batch, n)).to("cuda")
+            sets = []
+            for _ in range(args.rotate):
+                sets.append((x.clone(), torch.empty_like(x)))
+            del x
+            bufs[(n, batch)] = sets
+    torch.cuda.synchronize()
+
+    # launches of one step: (kernel label, plan, pass, shape key)
+    launches = []
+    for name, n, batch, sign in items:
+        d = plans[name].describe()
+        if d["path"] == fb.PATH_BLOCK:
+            launches.append((d["kernel_name"], name, 1, (n, batch)))
+        else:
+            launches.append((d["kernel_name"], name, 1, (n, batch)))
+            launches.append((d["kernel_name2"], name, 2, (n, batch)))
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+
+    def run_step(s, evs=None):
+        k = s % args.rotate
+        for li, (_, name, pass_, key) in enumerate(launches):
+            xin, xout = bufs[key][k]
+            if evs is not None:
+                evs[li].record(stream)
+            plans[name].execute_pass_ptr(pass_, xin.data_ptr(), xout.data_ptr(), sh)
+        if evs is not None:
+            evs[len(launches)].record(stream)
+
+    for s in range(args.warmup):
+        run_step(s)
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} steps done")
+
+    K = args.steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(launches) + 1)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(K):
+        run_step(s, evs[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"timed {K} steps in {wall:.3f} s wall")
+
+    total_ms = evs[0][0].elapsed_time(evs[K - 1][len(launches)])
+    ms_per_step = total_ms / K
+    per = {}
+    for s in range(K):
+        for li, (kname, name, pass_, key) in enumerate(launches):
+            dt = evs[s][li].elapsed_time(evs[s][li + 1])
+            per.setdefault(li, []).append(dt)
+    fl_step = sum(flops(n, b) for _, n, b, _ in items)
+    value = fl_step / (ms_per_step * 1e-3) / 1e9
+
+    kernels = {}
+    for li, (kname, name, pass_, (n, batch)) in enumerate(launches):
+        avg_ms = sum(per[li]) / len(per[li])
+        byts = 16.0 * n * batch
+        e = kernels.setdefault(kname, {"launches_per_step": 0, "total_ms": 0.0, "bytes_per_launch": byts,
+                                       "durations_ms": []})
+        e["launches_per_step"] += 1
+        e["total_ms"] += avg_ms
+        e["durations_ms"].append(avg_ms)
+    breakdown = {}
+    for kname, e in kernels.items():
+        avg = e["total_ms"] / e["launches_per_step"]
+        gbps = e["bytes_per_launch"] / (avg * 1e-3) / 1e9
+        breakdown[kname] = {"avg_us": round(avg * 1e3, 2), "launches_per_step": e["launches_per_step"],
+                            "bytes_per_launch": int(e["bytes_per_launch"]), "GBps": round(gbps, 1),
+                            "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4)}
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    dom_avg_ms = kernels[dom]["total_ms"] / kernels[dom]["launches_per_step"]
+    achieved = kernels[dom]["bytes_per_launch"] / (dom_avg_ms * 1e-3) / 1e9
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as fh:
+            traffic = json.load(fh).get(dom)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic}
+    log("per-kernel:", json.dumps(breakdown))
+
+    extras = {}
+    if not args.no_extras:
+        extras = run_extras(torch, fb, inputs, stream)
+
+    # ------------------------------------------------------- CPU baseline
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(items, fl_step, args.cpu_seconds)
+
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched complex64 FFT, N=4096 x batch 4096 forward+inverse (single LDS block) "
+                        "+ N=2^20 x batch 16 forward+inverse (four-step 1024x1024)",
+            "inputs": "uniform[-1,1] re/im, seed 1",
+            "cold_cache_buffer_sets": args.rotate,
+            "flops_per_step": fl_step,
+            "hbm_bytes_per_step": int(sum(16.0 * n * b for _, _, _, (n, b) in launches)),
+            "device": info["arch"],
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": breakdown,
+        "extras": extras,
+    }
+    print(json.dumps(rec), flush=True)
+    for p in plans.values():
+        p.close()
+
+
+def run_extras(torch, fb, inputs, stream):
+    out = {}
+    # HBM copy probe: 1 GiB, read + write counted
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 8, dtype=torch.complex64, device="cuda")
+    b = torch.empty_like(a)
+    a.zero_()
+    for _ in range(3):
+        fb.copy_(b, a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record(stream)
+    for _ in range(reps):
+        fb.copy_(b, a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out["copy_probe"] = {"bytes": nbytes, "GBps_read_plus_write": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+    del a, b
+    log("copy probe", out["copy_probe"])
+
+    # SAR chain: range FFT (8192 x 4096) -> corner turn -> azimuth FFT (4096 x 8192), and back
+    P, R = 4096, 8192
+    x = torch.from_numpy(inputs.sar(2, pulses=P, ranges=R)).to("cuda")
+    rf, af = fb.Plan(R, P, fb.FORWARD), fb.Plan(P, R, fb.FORWARD)
+    ab, rb = fb.Plan(P, R, fb.BACKWARD), fb.Plan(R, P, fb.BACKWARD)
+    t1, t2, t3 = torch.empty_like(x), torch.empty_like(x), torch.empty_like(x)
+    sh = stream.cuda_stream
+    steps = [("range_fft", lambda: rf.execute_ptr(x.data_ptr(), t1.data_ptr(), sh)),
+             ("corner_turn", lambda: fb.transpose(t1.view(P, R), out=t2.view(R, P))),
+             ("azimuth_fft", lambda: af.execute_ptr(t2.data_ptr(), t3.data_ptr(), sh)),
+             ("azimuth_ifft", lambda: ab.execute_ptr(t3.data_ptr(), t2.data_ptr(), sh)),
+             ("corner_turn_back", lambda: fb.transpose(t2.view(R, P), out=t1.view(P, R))),
+             ("range_ifft", lambda: rb.execute_ptr(t1.data_ptr(), t3.data_ptr(), sh))]
+    for _ in range(2):
+        for _, f in steps:
+            f()
+    torch.cuda.synchronize()
+    reps = 10
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(steps) + 1)] for _ in range(reps)]
+    for r in range(reps):
+        for i, (_, f) in enumerate(steps):
+            evs[r][i].record(stream)
+            f()
+        evs[r][len(steps)].record(stream)
+    torch.cuda.synchronize()
+    pts = P * R
+    sar = {}
+    for i, (name, _) in enumerate(steps):
+        ms = sum(evs[r][i].elapsed_time(evs[r][i + 1]) for r in range(reps)) / reps
+        sar[name] = {"us": round(ms * 1e3, 1), "GBps": round(16.0 * pts / (ms * 1e-3) / 1e9, 1)}
+    fwd_ms = sum(sar[k]["us"] for k in ("range_fft", "corner_turn", "azimuth_fft")) / 1e3
+    inv_ms = sum(sar[k]["us"] for k in ("azimuth_ifft", "corner_turn_back", "range_ifft")) / 1e3
+    fl = 5.0 * pts * math.log2(pts)
+    sar["forward_GFLOPs"] = round(fl / (fwd_ms * 1e-3) / 1e9, 1)
+    sar["inverse_GFLOPs"] = round(fl / (inv_ms * 1e-3) / 1e9, 1)
+    sar["forward_frac_hbm_at_48B_per_point"] = round(48.0 * pts / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+    sar["shape"] = f"{P} pulses x {R} range samples"
+    out["sar_chain"] = sar
+    for p in (rf, af, ab, rb):
+        p.close()
+    log("SAR", json.dumps(sar))
+    return out
+
+
+def cpu_baseline(items, fl_step, target_s):
+    """The FP64 oracle (radix-2 recursion, all host threads) on the same step, repeated ~target_s."""
+    import numpy as np
+
+    import oracle
+    from paper_1505_08067_amd import inputs
+
+    data = {}
+    for _, n, batch, _ in items:
+        if (n, batch) not in data:
+            data[(n, batch)] = inputs.uniform(1, batch, n).astype(np.complex128)
+    reps, t_total = 0, 0.0
+    while t_total < target_s or reps == 0:
+        t0 = time.perf_counter()
+        for _, n, batch, sign in items:
+            oracle.fft_radix2(data[(n, batch)], sign)
+        t_total += time.perf_counter() - t0
+        reps += 1
+        if reps >= 50:
+            break
+    value = fl_step * reps / t_total / 1e9
+    log(f"cpu baseline: {reps} steps in {t_total:.2f} s")
+    return {"value": round(value, 3), "unit": "GFLOP/s", "cores": oracle.nthreads(), "kind": "oracle",
+            "sample": f"{reps} full step(s) of the same workload (4096x4096 fwd+inv, 2^20x16 fwd+inv) "
+                      f"through the FP64 radix-2 oracle, {t_total:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,200 @@
+/*
+ * fftblock.h -- C ABI of the MI355X (gfx950) batched complex FFT library.
+ *
+ * The library computes batched one-dimensional discrete Fourier transforms of
+ * single-precision complex data, following the definition in the paper's
+ * Background section ("FFT Basics"):
+ *
+ *     X(k) = sum_{n=0}^{N-1} x(n) * w_N^{n k},   w_N = exp(-2 i pi / N)
+ *
+ * and the backward transform obtained by flipping the sign of the exponent.
+ * Neither direction is normalised: backward(forward(x)) = N * x.
+ *
+ * Method (paper, Approach): one elementary FFT block sized to what one
+ * compute unit holds on chip (registers + the 160 KB LDS of a gfx950 CU) runs
+ * a whole transform per workgroup ("Top level analysis": read, compute,
+ * write).  Longer transforms are composed from two layers of such blocks by
+ * the four-step split N = N1 * N2 ("Other FFT sizes": larger FFTs from the
+ * fixed block): N2 column transforms of length N1 with a fused twiddle
+ * multiply, then N1 row transforms of length N2 with the corner turn fused
+ * into the store.  The data transpose used between the range and azimuth
+ * passes of the radar chain ("Radar application description") is
+ * fft_transpose.
+ *
+ * Data conventions (all entry points):
+ *   - complex values are interleaved (re, im) pairs of IEEE float32, 8 bytes
+ *     each (the layout of float2 and of torch.complex64);
+ *   - a batch is contiguous and batch-major: element k of transform b is at
+ *     index b * n + k;
+ *   - pointers named `in`/`out` are DEVICE pointers on the plan's device;
+ *     `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *   - output is always in natural order.
+ *
+ * Errors: every call returns an fft_status_t; nothing is thrown across the
+ * ABI.  Argument checks run before any HIP call.  Launches are asynchronous:
+ * a kernel fault surfaces at the caller's next synchronisation, not here.
+ * Thread safety: distinct plans may be used from distinct host threads; one
+ * plan must not be executed concurrently (it owns one workspace).
+ */
+#ifndef FFTBLOCK_H
+#define FFTBLOCK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fft_plan_s* fft_plan_t;   /* opaque; created and freed by this API */
+
+typedef enum {
+    FFT_SUCCESS = 0,
+    FFT_ERR_INVALID_ARG = 1,       /* zero size/batch, bad direction, null pointer, overlap */
+    FFT_ERR_UNSUPPORTED_SIZE = 2,  /* a length the library has no kernels for */
+    FFT_ERR_OUT_OF_MEMORY = 3,     /* hipMalloc failed */
+    FFT_ERR_DEVICE = 4,            /* any other HIP runtime error (launch, copy, device query) */
+    FFT_ERR_INVALID_PLAN = 5       /* null or destroyed plan handle */
+} fft_status_t;
+
+/* Direction = sign of the exponent in the definition above. */
+#define FFT_FORWARD (-1)
+#define FFT_BACKWARD (+1)
+
+/* Execution path chosen by the planner. */
+#define FFT_PATH_BLOCK 1      /* one LDS-resident block per transform (N <= block limit) */
+#define FFT_PATH_FOURSTEP 2   /* two block passes, N = N1 * N2 */
+
+/*
+ * fft_plan_create -- plan `batch` transforms of length `n` in `direction`
+ * on the calling thread's current HIP device.
+ *
+ *   n          transform length; powers of two from 1 to 2^22 (the single
+ *              block path covers n <= the LDS block limit, longer lengths
+ *              use the four-step path).  Other lengths: UNSUPPORTED_SIZE.
+ *   batch      number of transforms per execute (>= 1).
+ *   direction  FFT_FORWARD or FFT_BACKWARD.
+ *   plan_out   receives the plan handle.
+ *
+ * The plan allocates (hipMalloc) its twiddle tables, generated in FP64 on the
+ * host and rounded once to FP32, and for the four-step path a workspace of
+ * batch * n complex values.  Returns INVALID_ARG (n == 0, batch == 0, bad
+ * direction, null plan_out), UNSUPPORTED_SIZE, OUT_OF_MEMORY or DEVICE.
+ */
+fft_status_t fft_plan_create(size_t n, size_t batch, int direction, fft_plan_t* plan_out);
+
+/*
+ * fft_execute -- run the planned transforms on `stream`.
+ *
+ *   in   device pointer to batch * n complex64 values (read only).
+ *   out  device pointer to batch * n complex64 values; out == in is allowed
+ *        (in-place).  Partial overlap other than out == in is INVALID_ARG.
+ *
+ * Both pointers must be 8-byte aligned.  Asynchronous; returns DEVICE when a
+ * launch fails, INVALID_PLAN for a null plan.
+ */
+fft_status_t fft_execute(fft_plan_t plan, const void* in, void* out, void* stream);
+
+/*
+ * fft_execute_pass -- run one kernel of a plan, for per-kernel timing.
+ *   pass 1: block path: the whole transform (same as fft_execute);
+ *           four-step: the column transforms + twiddle, `in` -> plan workspace
+ *           (`out` is not touched).
+ *   pass 2: four-step only: the row transforms + corner turn, plan workspace
+ *           -> `out` (`in` is not touched); INVALID_ARG on the block path.
+ * fft_execute(plan, in, out) == pass 1 then pass 2 on the same stream.
+ * Same pointer rules and errors as fft_execute.
+ */
+fft_status_t fft_execute_pass(fft_plan_t plan, int pass, const void* in, void* out, void* stream);
+
+/*
+ * fft_transpose -- corner turn of `batch` row-major complex64 matrices:
+ *     out[b][c][r] = in[b][r][c],  0 <= r < rows, 0 <= c < cols.
+ * The values are copied bit for bit.  `in` and `out` must not overlap
+ * (INVALID_ARG).  Asynchronous on `stream`.
+ */
+fft_status_t fft_transpose(const void* in, void* out, size_t rows, size_t cols, size_t batch,
+                           void* stream);
+
+/*
+ * fft_plan_destroy -- synchronise the plan's device, free its tables and
+ * workspace, and invalidate the handle.  Null handle: INVALID_PLAN.
+ */
+fft_status_t fft_plan_destroy(fft_plan_t plan);
+
+/* Static English text for a status code (never NULL). */
+const char* fft_status_string(fft_status_t s);
+
+/* ---------------------------------------------------------------------------
+ * Introspection.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    size_t n, batch;
+    int direction;
+    int path;                 /* FFT_PATH_BLOCK or FFT_PATH_FOURSTEP */
+    size_t n1, n2;            /* four-step split (n1: pass-1 column length); 0 for block */
+    int n_radix;              /* radix schedule of the block kernel (pass 1 for four-step) */
+    int radix[8];
+    int n_radix2;             /* radix schedule of pass 2 (four-step only) */
+    int radix2[8];
+    int threads_per_block;    /* workgroup size of the (first) kernel */
+    int transforms_per_block; /* transforms (or columns) one workgroup handles */
+    size_t lds_bytes;         /* static LDS of the (first) kernel */
+    size_t workspace_bytes;   /* device workspace owned by the plan */
+    size_t twiddle_bytes;     /* device twiddle tables owned by the plan */
+    int kernels_per_execute;  /* 1 (block) or 2 (four-step) */
+    const char* kernel_name;  /* symbolic name of the (first) kernel */
+    const char* kernel_name2; /* symbolic name of the pass-2 kernel (four-step), else NULL */
+} fft_plan_desc_t;
+
+/* Fill `desc` for a plan.  INVALID_PLAN / INVALID_ARG on null arguments. */
+fft_status_t fft_plan_describe(fft_plan_t plan, fft_plan_desc_t* desc);
+
+/* Dry-run planning: fill `desc` with the path, split and kernels that
+ * fft_plan_create would choose for (n, batch, direction), without touching a
+ * device (no HIP call, no allocation).  Same argument errors as
+ * fft_plan_create. */
+fft_status_t fft_plan_query(size_t n, size_t batch, int direction, fft_plan_desc_t* desc);
+
+typedef struct {
+    int device;
+    char arch[64];            /* gcnArchName, e.g. "gfx950:sramecc+:xnack-" */
+    int compute_units;
+    int warp_size;
+    size_t lds_per_cu;        /* bytes of LDS per compute unit */
+    size_t lds_per_block;     /* max LDS bytes one workgroup may allocate */
+    size_t global_mem;
+    int clock_khz;
+    int mem_clock_khz;
+    int mem_bus_width;
+    /* Analytic block limit (paper, Approach: the largest FFT a compute unit's
+     * local memory holds): pow2floor(lds_per_cu / (8 * (1 + 1/16) * k)) for
+     * k = 1, 2, 4 workgroups resident per CU (8 bytes per complex value plus
+     * one pad value per 16). */
+    size_t block_max[3];
+} fft_device_info_t;
+
+/* Query the current device (device < 0) or device `device`. */
+fft_status_t fft_device_query(int device, fft_device_info_t* info);
+
+/* The analytic block limit for `lds_bytes` of local memory per compute unit
+ * and k resident workgroups: pow2floor(lds_bytes / (8 * (17/16) * k)); 0 if
+ * k < 1 or nothing fits.  Pure arithmetic, no device needed. */
+size_t fft_block_max(size_t lds_bytes, int k);
+
+/* Largest length the single-block path handles in this build (the block
+ * limit the planner uses: analytic, then confirmed by the runtime sweep). */
+size_t fft_block_limit(void);
+
+/* ---------------------------------------------------------------------------
+ * Bandwidth probe (the analogue of the paper's memory benchmark, Approach,
+ * bottom-level analysis): copy `bytes` (multiple of 16, 16-byte aligned
+ * pointers, no overlap) from `in` to `out` with 16-byte vector accesses.
+ * ------------------------------------------------------------------------- */
+fft_status_t fft_copy(const void* in, void* out, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFTBLOCK_H */

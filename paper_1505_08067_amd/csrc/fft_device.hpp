@@ -1,0 +1,239 @@
+// Device-side building blocks of the block FFT (gfx950, wave64).
+//
+// * In-register DFTs of radix 2, 4, 8, 16 and 32 (forward sign; the backward
+//   transform is run as conj(forward(conj(x))), which is exact in FP32 since
+//   negation does not round).  Larger radices are built from smaller ones by
+//   the same split N = N1*N2 used between kernels (paper, Approach, "Other FFT
+//   sizes": larger transforms from smaller blocks), with the inner twiddles
+//   as compile-time constants and the multiplications by 1, -1, +-i and
+//   (+-1 +-i)/sqrt(2) written out so they cost no general complex multiply.
+// * The schedule type Sched<R0, R1, ...>: a list of radices whose product is
+//   the transform length, with the per-stage strides and twiddle-table
+//   offsets (paper, Background: a mixed-radix FFT as a sequence of radix
+//   stages; Approach: a radix stage's inputs held in the private memory
+//   (registers) of one processing element).
+//
+// A Stockham stage (autosort, natural-order output) of radix R after
+// Ns = R0*...*R_{s-1} points have been combined maps butterfly j to inputs
+// x[j + r*N/R], r < R, multiplies input r by exp(-2 pi i r (j mod Ns)/(Ns R)),
+// takes the R-point DFT and writes output q to
+// ((j / Ns) * Ns * R + j mod Ns) + q * Ns.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+namespace fb {
+
+template <int I>
+using ic = std::integral_constant<int, I>;
+
+// Compile-time loop: calls f(ic<B>), f(ic<B+1>), ..., f(ic<E-1>).
+template <int B, int E, class F>
+__device__ __forceinline__ void sfor(F&& f)
+{
+    if constexpr (B < E) {
+        f(ic<B>{});
+        sfor<B + 1, E>(f);
+    }
+}
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// a * w
+__device__ __forceinline__ float2 cmul(float2 a, float2 w)
+{
+    return make_float2(fmaf(a.x, w.x, -(a.y * w.y)), fmaf(a.x, w.y, a.y * w.x));
+}
+// a * (c + i s) with compile-time c, s
+__device__ __forceinline__ float2 cmul_cs(float2 a, float c, float s)
+{
+    return make_float2(fmaf(a.x, c, -(a.y * s)), fmaf(a.x, s, a.y * c));
+}
+
+// cos(2 pi u / 32) for u = 0..8 (the first quadrant of the 32nd roots of unity)
+__host__ __device__ constexpr double cos32(int u)
+{
+    constexpr double t[9] = {1.0,
+                             0.98078528040323044913,
+                             0.92387953251128675613,
+                             0.83146961230254523708,
+                             0.70710678118654752440,
+                             0.55557023301960222474,
+                             0.38268343236508977173,
+                             0.19509032201612826785,
+                             0.0};
+    return t[u];
+}
+// cos and sin of 2 pi q / 32 by quadrant symmetry
+__host__ __device__ constexpr double cos_q32(int q)
+{
+    const int h = (q & 31) >> 3, u = q & 7;
+    const double c = cos32(u), s = cos32(8 - u);
+    return h == 0 ? c : h == 1 ? -s : h == 2 ? -c : s;
+}
+__host__ __device__ constexpr double sin_q32(int q)
+{
+    const int h = (q & 31) >> 3, u = q & 7;
+    const double c = cos32(u), s = cos32(8 - u);
+    return h == 0 ? s : h == 1 ? c : h == 2 ? -s : -c;
+}
+
+// v * exp(-2 pi i Q / R) with R dividing 32.
+template <int Q, int R>
+__device__ __forceinline__ float2 mul_root(float2 v)
+{
+    static_assert(32 % R == 0, "radix must divide 32");
+    constexpr int q = ((Q % R) * (32 / R)) & 31;
+    constexpr float h = 0.70710678118654752440f;
+    if constexpr (q == 0) {
+        return v;
+    } else if constexpr (q == 8) {
+        return make_float2(v.y, -v.x);
+    } else if constexpr (q == 16) {
+        return make_float2(-v.x, -v.y);
+    } else if constexpr (q == 24) {
+        return make_float2(-v.y, v.x);
+    } else if constexpr (q == 4) {
+        return make_float2(h * (v.x + v.y), h * (v.y - v.x));
+    } else if constexpr (q == 12) {
+        return make_float2(h * (v.y - v.x), -h * (v.x + v.y));
+    } else if constexpr (q == 20) {
+        return make_float2(-h * (v.x + v.y), h * (v.x - v.y));
+    } else if constexpr (q == 28) {
+        return make_float2(h * (v.x - v.y), h * (v.x + v.y));
+    } else {
+        constexpr float c = (float)cos_q32(q);
+        constexpr float s = (float)(-sin_q32(q));
+        return cmul_cs(v, c, s);
+    }
+}
+
+// ------------------------------------------------------------ small DFTs
+// Dft<R>::run(v) replaces v[0..R) by its forward R-point DFT, natural order.
+template <int R>
+struct Dft;
+
+template <>
+struct Dft<1> {
+    static __device__ __forceinline__ void run(float2*) {}
+};
+
+template <>
+struct Dft<2> {
+    static __device__ __forceinline__ void run(float2* v)
+    {
+        const float2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <>
+struct Dft<4> {
+    static __device__ __forceinline__ void run(float2* v)
+    {
+        const float2 t0 = cadd(v[0], v[2]);
+        const float2 t1 = csub(v[0], v[2]);
+        const float2 t2 = cadd(v[1], v[3]);
+        const float2 d = csub(v[1], v[3]);
+        const float2 t3 = make_float2(d.y, -d.x);  // (v1 - v3) * (-i)
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[3] = csub(t1, t3);
+    }
+};
+
+__host__ __device__ constexpr int dft_split(int R) { return R == 8 ? 4 : R == 16 ? 4 : R == 32 ? 8 : 1; }
+
+// R = R1 * R2: with n = R2*n1 + n2 and k = k1 + R1*k2,
+//   X[k] = sum_{n2} w_R2^{n2 k2} [ w_R^{n2 k1} sum_{n1} x[R2 n1 + n2] w_R1^{n1 k1} ].
+template <int R>
+struct Dft {
+    static constexpr int R1 = dft_split(R);
+    static constexpr int R2 = R / R1;
+    static_assert(R1 > 1 && R2 > 1, "unsupported radix");
+    static __device__ __forceinline__ void run(float2* v)
+    {
+        float2 a[R];
+        sfor<0, R2>([&](auto n2c) {
+            constexpr int n2 = decltype(n2c)::value;
+            float2 u[R1];
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) u[n1] = v[R2 * n1 + n2];
+            Dft<R1>::run(u);
+            sfor<0, R1>([&](auto k1c) {
+                constexpr int k1 = decltype(k1c)::value;
+                a[n2 * R1 + k1] = mul_root<n2 * k1, R>(u[k1]);
+            });
+        });
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            float2 w[R2];
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) w[n2] = a[n2 * R1 + k1];
+            Dft<R2>::run(w);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = w[k2];
+        }
+    }
+};
+
+// --------------------------------------------------------------- schedule
+template <int... Rs>
+struct Sched {
+    static constexpr int count = sizeof...(Rs);
+    static constexpr int r(int s)
+    {
+        constexpr int a[] = {Rs...};
+        return a[s];
+    }
+    // points already combined before stage s
+    static constexpr int ns(int s)
+    {
+        int p = 1;
+        for (int i = 0; i < s; ++i) p *= r(i);
+        return p;
+    }
+    static constexpr int n() { return ns(count); }
+    // offset of stage s's twiddle rows (stage 0 needs none): rows k < Ns of R entries
+    static constexpr int tw_off(int s)
+    {
+        int o = 0;
+        for (int i = 1; i < s; ++i) o += ns(i) * r(i);
+        return o;
+    }
+    static constexpr int tw_size() { return tw_off(count); }
+    static constexpr int max_r()
+    {
+        int m = 1;
+        for (int i = 0; i < count; ++i) m = r(i) > m ? r(i) : m;
+        return m;
+    }
+};
+
+// LDS index with one pad slot per 16 complex values (keeps stride-16 and
+// stride-R butterfly accesses on distinct banks).
+__host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
+
+// Multiplies the R inputs of one butterfly by its twiddle row
+// tw[k*R + r] = exp(-2 pi i r k / (Ns R)), loaded as 16-byte pairs.
+template <int R>
+__device__ __forceinline__ void apply_row(float2* v, const float2* __restrict__ row)
+{
+    if constexpr (R == 1) {
+        return;
+    } else {
+        const float4* row4 = reinterpret_cast<const float4*>(row);
+#pragma unroll
+        for (int r = 0; r < R; r += 2) {
+            const float4 w = row4[r / 2];
+            if (r > 0) v[r] = cmul(v[r], make_float2(w.x, w.y));
+            v[r + 1] = cmul(v[r + 1], make_float2(w.z, w.w));
+        }
+    }
+}
+
+}  // namespace fb

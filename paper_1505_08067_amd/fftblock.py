@@ -1,0 +1,260 @@
+"""Python binding of the C ABI in ``include/fftblock.h`` (ctypes).
+
+Argument marshalling only: every step of a transform runs in the HIP kernels
+of ``libfftblock.so``.  PyTorch provides device memory and the stream
+(``torch.cuda.current_stream()``).  There is no CPU fallback: if the library
+is missing or a call fails, an exception is raised.
+
+    plan = Plan(n, batch, FORWARD)        # fft_plan_create
+    y = plan.execute(x)                   # fft_execute on the current stream
+    t = transpose(m)                      # fft_transpose (corner turn)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfftblock.so")
+
+FORWARD = -1
+BACKWARD = +1
+PATH_BLOCK = 1
+PATH_FOURSTEP = 2
+
+STATUS = {
+    0: "FFT_SUCCESS",
+    1: "FFT_ERR_INVALID_ARG",
+    2: "FFT_ERR_UNSUPPORTED_SIZE",
+    3: "FFT_ERR_OUT_OF_MEMORY",
+    4: "FFT_ERR_DEVICE",
+    5: "FFT_ERR_INVALID_PLAN",
+}
+
+# Every symbol include/fftblock.h declares.
+EXPORTS = (
+    "fft_plan_create", "fft_execute", "fft_execute_pass", "fft_transpose", "fft_plan_destroy", "fft_status_string",
+    "fft_plan_describe", "fft_plan_query", "fft_device_query", "fft_block_max", "fft_block_limit",
+    "fft_copy",
+)
+
+
+class FFTError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_size_t), ("batch", ctypes.c_size_t),
+        ("direction", ctypes.c_int), ("path", ctypes.c_int),
+        ("n1", ctypes.c_size_t), ("n2", ctypes.c_size_t),
+        ("n_radix", ctypes.c_int), ("radix", ctypes.c_int * 8),
+        ("n_radix2", ctypes.c_int), ("radix2", ctypes.c_int * 8),
+        ("threads_per_block", ctypes.c_int), ("transforms_per_block", ctypes.c_int),
+        ("lds_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
+        ("twiddle_bytes", ctypes.c_size_t), ("kernels_per_execute", ctypes.c_int),
+        ("kernel_name", ctypes.c_char_p), ("kernel_name2", ctypes.c_char_p),
+    ]
+
+
+class DeviceInfo(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int), ("arch", ctypes.c_char * 64),
+        ("compute_units", ctypes.c_int), ("warp_size", ctypes.c_int),
+        ("lds_per_cu", ctypes.c_size_t), ("lds_per_block", ctypes.c_size_t),
+        ("global_mem", ctypes.c_size_t), ("clock_khz", ctypes.c_int),
+        ("mem_clock_khz", ctypes.c_int), ("mem_bus_width", ctypes.c_int),
+        ("block_max", ctypes.c_size_t * 3),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load ``libfftblock.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1505_08067_amd/build.py "
+                           "(or __graft_entry__.build()); there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    sz, vp, i = ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int
+    lib.fft_plan_create.argtypes = [sz, sz, i, ctypes.POINTER(vp)]
+    lib.fft_execute.argtypes = [vp, vp, vp, vp]
+    lib.fft_execute_pass.argtypes = [vp, i, vp, vp, vp]
+    lib.fft_transpose.argtypes = [vp, vp, sz, sz, sz, vp]
+    lib.fft_plan_destroy.argtypes = [vp]
+    lib.fft_status_string.argtypes = [i]
+    lib.fft_status_string.restype = ctypes.c_char_p
+    lib.fft_plan_describe.argtypes = [vp, ctypes.POINTER(PlanDesc)]
+    lib.fft_plan_query.argtypes = [sz, sz, i, ctypes.POINTER(PlanDesc)]
+    lib.fft_device_query.argtypes = [i, ctypes.POINTER(DeviceInfo)]
+    lib.fft_block_max.argtypes = [sz, i]
+    lib.fft_block_max.restype = sz
+    lib.fft_block_limit.argtypes = []
+    lib.fft_block_limit.restype = sz
+    lib.fft_copy.argtypes = [vp, vp, sz, vp]
+    for name in ("fft_plan_create", "fft_execute", "fft_execute_pass", "fft_transpose", "fft_plan_destroy",
+                 "fft_plan_describe", "fft_plan_query", "fft_device_query", "fft_copy"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        raise FFTError(status, where)
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_tensor(x, name: str):
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if x.dtype != torch.complex64:
+        raise TypeError(f"{name} must be complex64, got {x.dtype}")
+    if not x.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if x.data_ptr() % 8:
+        raise ValueError(f"{name} must be 8-byte aligned")
+
+
+def _desc_dict(d: "PlanDesc") -> dict:
+    return {
+        "n": d.n, "batch": d.batch, "direction": d.direction, "path": d.path,
+        "n1": d.n1, "n2": d.n2,
+        "radix": list(d.radix[: d.n_radix]), "radix2": list(d.radix2[: d.n_radix2]),
+        "threads_per_block": d.threads_per_block, "transforms_per_block": d.transforms_per_block,
+        "lds_bytes": d.lds_bytes, "workspace_bytes": d.workspace_bytes,
+        "twiddle_bytes": d.twiddle_bytes, "kernels_per_execute": d.kernels_per_execute,
+        "kernel_name": d.kernel_name.decode() if d.kernel_name else None,
+        "kernel_name2": d.kernel_name2.decode() if d.kernel_name2 else None,
+    }
+
+
+def plan_query(n: int, batch: int, direction: int = FORWARD) -> dict:
+    """What ``fft_plan_create`` would choose, without a device (``fft_plan_query``)."""
+    d = PlanDesc()
+    _check(load().fft_plan_query(n, batch, direction, ctypes.byref(d)), f"fft_plan_query(n={n})")
+    return _desc_dict(d)
+
+
+class Plan:
+    """Batched 1-D complex64 FFT plan (``fft_plan_create``)."""
+
+    def __init__(self, n: int, batch: int, direction: int = FORWARD):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.fft_plan_create(n, batch, direction, ctypes.byref(h)), f"fft_plan_create(n={n}, batch={batch})")
+        self._h = h
+        self.n, self.batch, self.direction = int(n), int(batch), int(direction)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def describe(self) -> dict:
+        d = PlanDesc()
+        _check(load().fft_plan_describe(self._h, ctypes.byref(d)), "fft_plan_describe")
+        return _desc_dict(d)
+
+    def execute(self, x, out=None, stream=None):
+        """Transform ``x`` (complex64, ``batch*n`` values) into ``out`` (new tensor if None)."""
+        import torch
+        _check_tensor(x, "x")
+        if x.numel() != self.n * self.batch:
+            raise ValueError(f"x has {x.numel()} values, plan expects {self.n * self.batch}")
+        if out is None:
+            out = torch.empty_like(x)
+        _check_tensor(out, "out")
+        if out.numel() != x.numel():
+            raise ValueError("out has the wrong size")
+        if out.device != x.device:
+            raise ValueError("x and out are on different devices")
+        st = _stream_handle(stream)
+        _check(load().fft_execute(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), st),
+               "fft_execute")
+        return out
+
+    def execute_ptr(self, in_ptr: int, out_ptr: int, stream_handle: int = 0) -> None:
+        """Raw-pointer variant (device addresses as ints) for benchmarks."""
+        _check(load().fft_execute(self._h, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
+                                  ctypes.c_void_p(stream_handle)), "fft_execute")
+
+    def execute_pass_ptr(self, pass_: int, in_ptr: int, out_ptr: int, stream_handle: int = 0) -> None:
+        """Run one kernel of the plan (``fft_execute_pass``): 1 = block / four-step pass 1, 2 = pass 2."""
+        _check(load().fft_execute_pass(self._h, pass_, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
+                                       ctypes.c_void_p(stream_handle)), f"fft_execute_pass({pass_})")
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load().fft_plan_destroy(self._h), "fft_plan_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def transpose(x, out=None, stream=None):
+    """Corner turn of the last two axes: ``out[..., c, r] = x[..., r, c]`` (``fft_transpose``)."""
+    import torch
+    _check_tensor(x, "x")
+    if x.dim() < 2:
+        raise ValueError("need at least two dimensions")
+    rows, cols = x.shape[-2], x.shape[-1]
+    batch = x.numel() // (rows * cols) if rows * cols else 0
+    if out is None:
+        out = torch.empty(x.shape[:-2] + (cols, rows), dtype=x.dtype, device=x.device)
+    _check_tensor(out, "out")
+    _check(load().fft_transpose(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                rows, cols, batch, _stream_handle(stream)), "fft_transpose")
+    return out
+
+
+def copy_(dst, src, stream=None):
+    """HBM copy probe (``fft_copy``): byte copy of ``src`` into ``dst``."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("size mismatch")
+    _check(load().fft_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                           _stream_handle(stream)), "fft_copy")
+    return dst
+
+
+def device_query(device: int = -1) -> dict:
+    info = DeviceInfo()
+    _check(load().fft_device_query(device, ctypes.byref(info)), "fft_device_query")
+    return {
+        "device": info.device, "arch": info.arch.decode(), "compute_units": info.compute_units,
+        "warp_size": info.warp_size, "lds_per_cu": info.lds_per_cu, "lds_per_block": info.lds_per_block,
+        "global_mem": info.global_mem, "clock_khz": info.clock_khz, "mem_clock_khz": info.mem_clock_khz,
+        "mem_bus_width": info.mem_bus_width, "block_max": list(info.block_max),
+    }
+
+
+def block_limit() -> int:
+    return int(load().fft_block_limit())
+
+
+def status_string(status: int) -> str:
+    return load().fft_status_string(status).decode()

@@ -1,0 +1,147 @@
+"""The C-ABI library on the CPU: it loads, exports what the header declares,
+checks arguments before any HIP call, and plans without a device."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1505_08067_amd import fftblock as fb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fftblock.h")
+
+
+def header_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fft_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fb.load()
+    declared = header_functions()
+    assert set(declared) == set(fb.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", fb.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (fft_\w+)", out))
+    assert set(declared) <= exported
+
+
+def test_header_is_plain_c():
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-x", "c", HEADER],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    monkeypatch.setattr(fb, "_lib", None)
+    monkeypatch.setattr(fb, "LIB_PATH", os.path.join(ROOT, "does_not_exist.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        fb.load()
+
+
+def test_product_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1505_08067_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", txt, re.M), f
+                assert "fft_oracle" not in txt and "liboracle" not in txt, f
+
+
+def test_status_strings():
+    for code in range(6):
+        assert fb.status_string(code)
+    assert fb.status_string(99) == "unknown status"
+
+
+@pytest.mark.parametrize("k,expect", [(1, 16384), (2, 8192), (4, 4096)])
+def test_block_max_for_160k_lds(k, expect):
+    # pow2floor(160 KiB / (8 B * 17/16 * k))
+    assert fb.load().fft_block_max(160 * 1024, k) == expect
+
+
+def test_block_max_other_sizes():
+    lib = fb.load()
+    assert lib.fft_block_max(64 * 1024, 1) == 4096
+    assert lib.fft_block_max(64 * 1024, 2) == 2048
+    assert lib.fft_block_max(100, 1) == 8
+    assert lib.fft_block_max(8, 1) == 0
+    assert lib.fft_block_max(160 * 1024, 0) == 0
+
+
+def test_plan_query_block_and_fourstep():
+    limit = fb.block_limit()
+    assert limit == 16384
+    for L in range(1, 23):
+        n = 1 << L
+        d = fb.plan_query(n, 3)
+        if n <= limit:
+            assert d["path"] == fb.PATH_BLOCK and d["kernels_per_execute"] == 1
+            assert math.prod(d["radix"]) == n
+            assert d["workspace_bytes"] == 0
+            assert d["lds_bytes"] <= 160 * 1024
+        else:
+            assert d["path"] == fb.PATH_FOURSTEP and d["kernels_per_execute"] == 2
+            assert d["n1"] * d["n2"] == n and d["n1"] >= d["n2"]
+            assert math.prod(d["radix"]) == d["n1"] and math.prod(d["radix2"]) == d["n2"]
+            assert d["workspace_bytes"] == 8 * n * 3
+            assert d["lds_bytes"] <= 160 * 1024
+    d = fb.plan_query(1 << 20, 16)
+    assert (d["n1"], d["n2"]) == (1024, 1024)
+    assert fb.plan_query(1, 5)["path"] == fb.PATH_BLOCK
+
+
+def test_block_limit_env_override():
+    code = ("from paper_1505_08067_amd import fftblock as f; "
+            "print(f.block_limit(), f.plan_query(8192, 1)['path'], f.plan_query(4096, 1)['path'])")
+    env = dict(os.environ, FFTBLOCK_BLOCK_MAX="4096")
+    out = subprocess.run(["python", "-c", code], env=env, cwd=ROOT, capture_output=True, text=True)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["4096", "2", "1"]
+
+
+@pytest.mark.parametrize("args,status", [
+    ((0, 1, -1), 1), ((8, 0, -1), 1), ((8, 1, 0), 1), ((8, 1, 2), 1),
+    ((6, 1, -1), 2), ((1000, 1, -1), 2), ((1 << 23, 1, -1), 2),
+])
+def test_plan_argument_errors_without_device(args, status):
+    with pytest.raises(fb.FFTError) as ei:
+        fb.plan_query(*args)
+    assert ei.value.status == status
+    # fft_plan_create rejects the same arguments before any HIP call
+    h = ctypes.c_void_p(123)
+    assert fb.load().fft_plan_create(*args, ctypes.byref(h)) == status
+    assert h.value is None
+
+
+def test_null_and_unknown_handles():
+    lib = fb.load()
+    assert lib.fft_plan_create(8, 1, -1, None) == 1
+    assert lib.fft_execute(None, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == 5
+    assert lib.fft_execute(ctypes.c_void_p(0xdead0), ctypes.c_void_p(16), ctypes.c_void_p(16), None) == 5
+    assert lib.fft_plan_destroy(None) == 5
+    assert lib.fft_plan_destroy(ctypes.c_void_p(0xdead0)) == 5
+    assert lib.fft_plan_describe(None, None) == 5
+    assert lib.fft_plan_query(8, 1, -1, None) == 1
+    assert lib.fft_device_query(0, None) == 1
+
+
+def test_transpose_and_copy_argument_errors_without_device():
+    lib = fb.load()
+    vp = ctypes.c_void_p
+    assert lib.fft_transpose(None, vp(0x10000), 4, 4, 1, None) == 1
+    assert lib.fft_transpose(vp(0x10000), vp(0x20000), 0, 4, 1, None) == 1
+    assert lib.fft_transpose(vp(0x10000), vp(0x20000), 4, 0, 1, None) == 1
+    assert lib.fft_transpose(vp(0x10000), vp(0x20000), 4, 4, 0, None) == 1
+    assert lib.fft_transpose(vp(0x10004), vp(0x20000), 4, 4, 1, None) == 1      # misaligned
+    assert lib.fft_transpose(vp(0x10000), vp(0x10008), 4, 4, 1, None) == 1      # overlap
+    assert lib.fft_copy(vp(0x10000), vp(0x20000), 24, None) == 1                 # not a multiple of 16
+    assert lib.fft_copy(vp(0x10008), vp(0x20000), 32, None) == 1                 # misaligned
+    assert lib.fft_copy(vp(0x10000), vp(0x10010), 32, None) == 1                 # overlap
+    assert lib.fft_copy(None, vp(0x20000), 32, None) == 1

@@ -1,0 +1,242 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Inputs are seeded and synthetic (uniform[-1,1] parts, or the SAR-shaped
+matrix).  Gate: per transform, relative L2 error <= 1e-6 * log2(N) (the 2-D
+SAR matrix counts as one transform of P*R points; a round trip gets twice the
+tolerance).  The transpose must be bit-exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import metrics
+from paper_1505_08067_amd import fftblock as fb
+from paper_1505_08067_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FWD, BWD = fb.FORWARD, fb.BACKWARD
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex64)).to("cuda")
+
+
+def gpu_fft(x, sign, inplace=False):
+    x = np.ascontiguousarray(x, dtype=np.complex64)
+    n = x.shape[-1]
+    batch = x.size // n
+    with fb.Plan(n, batch, sign) as plan:
+        d = to_dev(x)
+        y = plan.execute(d, out=d if inplace else None)
+        torch.cuda.synchronize()
+        return y.cpu().numpy().reshape(x.shape)
+
+
+def check(y, ref, n_points, n_axes=1, factor=1.0, label=""):
+    mx, md, tol = metrics.check(y, ref, n_points, n_axes=n_axes, factor=factor)
+    say(f"  {label}: max rel L2 {mx:.3e}  median {md:.3e}  tol {tol:.1e}")
+    return mx
+
+
+# ----------------------------------------------------------- the block path
+def test_cfg1_n1024_batch64_forward_against_definition():
+    say("case: N=1024 batch=64 forward seed=0 vs the O(N^2) definition")
+    x = inputs.uniform(0, 64, 1024)
+    y = gpu_fft(x, FWD)
+    ref = oracle.dft_naive(x.astype(np.complex128), FWD)
+    check(y, ref, 1024, label="N=1024 x 64")
+
+
+BLOCK_SIZES = [2 ** k for k in range(1, 15)]
+
+
+@pytest.mark.parametrize("n", BLOCK_SIZES)
+@pytest.mark.parametrize("sign", [FWD, BWD])
+def test_block_sizes_against_oracle(n, sign):
+    d = fb.plan_query(n, 1, sign)
+    fpb = max(1, d["transforms_per_block"])
+    batch = 2 * fpb + 1 if n < 16384 else 3   # a partly filled last workgroup
+    say(f"case: block N={n} batch={batch} sign={sign} kernel={d['kernel_name']}")
+    x = inputs.uniform(100 + n, batch, n)
+    y = gpu_fft(x, sign)
+    ref = oracle.fft(x.astype(np.complex128), sign)
+    check(y, ref, n, label=f"N={n}")
+
+
+def test_n1_is_copy():
+    x = inputs.uniform(5, 7, 1)
+    for sign in (FWD, BWD):
+        assert np.array_equal(gpu_fft(x, sign), x)
+        assert np.array_equal(gpu_fft(x, sign, inplace=True), x)
+
+
+@pytest.mark.parametrize("n", [4096, 1 << 20])
+def test_cfg2_full_size_forward_and_inverse(n):
+    batch = 4096 if n == 4096 else 16
+    say(f"case: N={n} batch={batch} forward+inverse, full comparison")
+    x = inputs.uniform(1, batch, n)
+    xd = x.astype(np.complex128)
+    for sign in (FWD, BWD):
+        y = gpu_fft(x, sign)
+        ref = oracle.fft(xd, sign)
+        check(y, ref, n, label=f"N={n} sign={sign}")
+
+
+@pytest.mark.parametrize("L", list(range(15, 23)))
+def test_fourstep_sizes_against_oracle(L):
+    n = 1 << L
+    batch = 2 if L <= 20 else 1
+    d = fb.plan_query(n, batch)
+    say(f"case: four-step N=2^{L} = {d['n1']}x{d['n2']} batch={batch}")
+    x = inputs.uniform(200 + L, batch, n)
+    for sign in (FWD, BWD):
+        y = gpu_fft(x, sign)
+        ref = oracle.fft(x.astype(np.complex128), sign)
+        check(y, ref, n, label=f"N=2^{L} sign={sign}")
+
+
+# ------------------------------------------------------------- closed forms
+@pytest.mark.parametrize("n", [64, 4096, 1 << 20])
+def test_closed_forms_on_gpu(n):
+    say(f"case: closed forms N={n}")
+    k = np.arange(n)
+    x = np.zeros((4, n), np.complex64)
+    x[0, 0] = 1                                   # impulse -> all ones
+    x[1, 3] = 1                                   # shifted impulse -> w^(3k)
+    x[2, :] = 1                                   # constant -> N delta
+    x[3] = np.exp(2j * np.pi * 5 * k / n)         # tone -> N delta at 5
+    y = gpu_fft(x, FWD)
+    exp = np.zeros((4, n), complex)
+    exp[0] = 1
+    exp[1] = np.exp(-2j * np.pi * ((3 * k) % n) / n)
+    exp[2, 0] = n
+    ref_tone = oracle.fft(x[3:4].astype(np.complex128), FWD)[0]
+    exp[3] = ref_tone
+    check(y[:3], exp[:3], n, label="impulse/shift/constant")
+    assert abs(y[3, 5] - n) / n < 1e-5
+    # Parseval on random input
+    r = inputs.uniform(7, 3, n)
+    Y = gpu_fft(r, FWD).astype(np.complex128)
+    lhs = np.sum(np.abs(Y) ** 2, -1)
+    rhs = n * np.sum(np.abs(r.astype(np.complex128)) ** 2, -1)
+    assert np.all(np.abs(lhs / rhs - 1) < 2e-6 * math.log2(n))
+
+
+@pytest.mark.parametrize("n", [1024, 8192, 1 << 18])
+def test_roundtrip(n):
+    batch = 8 if n < (1 << 18) else 2
+    x = inputs.uniform(9, batch, n)
+    y = gpu_fft(gpu_fft(x, FWD), BWD) / n
+    check(y, x.astype(np.complex128), n, factor=2.0, label=f"round trip N={n}")
+
+
+# ---------------------------------------------------------- isolation etc.
+@pytest.mark.parametrize("n", [256, 1024, 4096, 1 << 16])
+def test_batch_isolation_with_poisoned_neighbours(n):
+    d = fb.plan_query(n, 1)
+    batch = max(8, 2 * d["transforms_per_block"])
+    say(f"case: NaN-poisoned neighbours N={n} batch={batch}")
+    x = inputs.uniform(11, batch, n)
+    x[1::2] = np.nan + 1j * np.inf
+    y = gpu_fft(x, FWD)
+    good = x[0::2]
+    assert np.all(np.isfinite(y[0::2].view(np.float32)))
+    check(y[0::2], oracle.fft(good.astype(np.complex128), FWD), n, label="clean slots")
+
+
+@pytest.mark.parametrize("n", [512, 4096, 1 << 20])
+def test_in_place_equals_out_of_place(n):
+    batch = 3
+    x = inputs.uniform(12, batch, n)
+    a = gpu_fft(x, FWD)
+    b = gpu_fft(x, FWD, inplace=True)
+    assert np.array_equal(a, b)
+
+
+def test_deterministic_repeat():
+    x = inputs.uniform(13, 64, 4096)
+    assert np.array_equal(gpu_fft(x, FWD), gpu_fft(x, FWD))
+
+
+# ---------------------------------------------------------------- transpose
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 100, 37), (1, 64, 64), (2, 65, 129), (1, 4096, 8192)])
+def test_transpose_bit_exact(shape):
+    say(f"case: transpose {shape}")
+    rng = np.random.default_rng(14)
+    bits = rng.integers(0, 2 ** 32, size=shape + (2,), dtype=np.uint32)
+    x = bits.view(np.float32).view(np.complex64).reshape(shape)
+    d = torch.from_numpy(x.copy()).to("cuda")
+    t = fb.transpose(d)
+    tt = fb.transpose(t)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy()
+    ref = oracle.transpose(x.astype(np.complex128)) if x.size < 2e6 else None
+    exp = np.ascontiguousarray(np.swapaxes(x, -1, -2))
+    assert np.array_equal(got.view(np.uint32), exp.view(np.uint32))
+    if ref is not None:
+        assert np.array_equal(got[np.isfinite(got)], ref.astype(np.complex64)[np.isfinite(got)])
+    assert np.array_equal(tt.cpu().numpy().view(np.uint32), x.view(np.uint32))
+
+
+def test_copy_probe():
+    a = torch.from_numpy(inputs.uniform(15, 1, 1 << 20)).to("cuda")
+    b = torch.empty_like(a)
+    fb.copy_(b, a)
+    torch.cuda.synchronize()
+    assert torch.equal(a.view(torch.float32), b.view(torch.float32))
+
+
+def test_device_query_and_block_limit():
+    info = fb.device_query()
+    say(f"device: {info}")
+    assert info["arch"].startswith("gfx950")
+    assert info["warp_size"] == 64
+    assert info["lds_per_cu"] == 160 * 1024
+    assert info["block_max"] == [16384, 8192, 4096]
+    assert fb.block_limit() <= info["block_max"][0]
+
+
+def test_errors_on_device():
+    with fb.Plan(1024, 2) as p:
+        x = to_dev(inputs.uniform(1, 2, 1024))
+        with pytest.raises(ValueError):
+            p.execute(x[:1])
+        with pytest.raises(TypeError):
+            p.execute(x.to(torch.complex128))
+        # partial overlap is rejected by the library
+        big = to_dev(inputs.uniform(1, 3, 1024))
+        st = fb.load().fft_execute(p.handle, big.data_ptr(), big.data_ptr() + 8 * 1024, None)
+        assert st == 1
+    with pytest.raises(fb.FFTError) as ei:
+        fb.Plan(1000, 1)
+    assert ei.value.status == 2
+
+
+# ------------------------------------------------------------ SAR 2-D chain
+def test_sar_range_azimuth_chain_and_roundtrip():
+    P, R = 4096, 8192
+    say(f"case: SAR {P}x{R} range FFT -> corner turn -> azimuth FFT, and back")
+    x = inputs.sar(2, pulses=P, ranges=R)
+    xd = to_dev(x)
+    with fb.Plan(R, P, FWD) as rf, fb.Plan(P, R, FWD) as af, fb.Plan(P, R, BWD) as ab, fb.Plan(R, P, BWD) as rb:
+        a = rf.execute(xd)                 # range FFT per pulse
+        t = fb.transpose(a.view(P, R))     # [range][pulse]
+        b = af.execute(t)                  # azimuth FFT per range bin
+        torch.cuda.synchronize()
+        y = b.cpu().numpy().reshape(R, P).T
+        ref = oracle.fft2d(x.astype(np.complex128), FWD)
+        check(y[None], ref[None], P * R, n_axes=2, label="SAR forward 2-D")
+        c = ab.execute(b)
+        t2 = fb.transpose(c.view(R, P))
+        z = rb.execute(t2)
+        torch.cuda.synchronize()
+        back = z.cpu().numpy().reshape(P, R) / (P * R)
+        check(back[None], x.astype(np.complex128)[None], P * R, n_axes=2, factor=2.0, label="SAR round trip")
