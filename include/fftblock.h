@@ -145,7 +145,64 @@ typedef struct {
     int kernels_per_execute;  /* 1 (block) or 2 (four-step) */
     const char* kernel_name;  /* symbolic name of the (first) kernel */
     const char* kernel_name2; /* symbolic name of the pass-2 kernel (four-step), else NULL */
+    int flags;                /* variant flags (FFT_VARIANT_*) of the (first) kernel */
+    int flags2;               /* variant flags of the pass-2 kernel */
+    int c2;                   /* pass-2 rows per workgroup = workspace block width */
+    long long grid;           /* workgroups of the (first) launch; 0 from fft_plan_query */
 } fft_plan_desc_t;
+
+/* ---------------------------------------------------------------------------
+ * Kernel variants and planner options (the runtime sweep and the schedule
+ * search pick among compiled variants; the defaults need none of this).
+ * ------------------------------------------------------------------------- */
+#define FFT_VARIANT_NT_LOAD 1     /* non-temporal (streaming) loads of the data */
+#define FFT_VARIANT_NT_STORE 2    /* non-temporal stores of the data */
+#define FFT_VARIANT_PERSISTENT 4  /* persistent workgroups prefetching the next unit */
+#define FFT_VARIANT_SWIZZLE 8     /* XOR-swizzled unpadded LDS layout */
+
+typedef struct {
+    size_t block_limit;  /* longest single-block length; 0 = fft_block_limit() */
+    int n_radix;         /* single-block schedule: 0 = default, else radix[0..n_radix) */
+    int radix[8];
+    int flags;           /* variant of the block kernel / pass 1; -1 = default */
+    int c;               /* four-step pass-1 columns per workgroup; 0 = default */
+    int flags2;          /* variant of pass 2; -1 = default */
+    int c2;              /* pass-2 rows per workgroup (workspace block width); 0 = default */
+} fft_plan_opts_t;
+
+/* Fill `opts` with "use the defaults". */
+void fft_plan_opts_init(fft_plan_opts_t* opts);
+
+/* fft_plan_create with planner options (NULL = defaults).  A combination no
+ * compiled kernel provides returns UNSUPPORTED_SIZE. */
+fft_status_t fft_plan_create_ex(size_t n, size_t batch, int direction, const fft_plan_opts_t* opts,
+                                fft_plan_t* plan_out);
+
+/* fft_plan_query with planner options (no device needed). */
+fft_status_t fft_plan_query_ex(size_t n, size_t batch, int direction, const fft_plan_opts_t* opts,
+                               fft_plan_desc_t* desc);
+
+#define FFT_KERNEL_BLOCK 0
+#define FFT_KERNEL_PASS1 1
+#define FFT_KERNEL_PASS2 2
+
+typedef struct {
+    int kind;            /* FFT_KERNEL_* */
+    int n;               /* length of the transforms one thread group computes */
+    int e;               /* complex values per thread */
+    int c;               /* transforms (block) or columns/rows (passes) per workgroup */
+    int flags;           /* FFT_VARIANT_* */
+    int n_radix;
+    int radix[8];
+    int threads;         /* workgroup size */
+    size_t lds_bytes;
+    int is_default;      /* the planner's default for (kind, n) */
+    const char* name;
+} fft_kernel_info_t;
+
+/* Number of compiled transform kernels, and the description of one. */
+int fft_kernel_count(void);
+fft_status_t fft_kernel_info(int index, fft_kernel_info_t* info);
 
 /* Fill `desc` for a plan.  INVALID_PLAN / INVALID_ARG on null arguments. */
 fft_status_t fft_plan_describe(fft_plan_t plan, fft_plan_desc_t* desc);

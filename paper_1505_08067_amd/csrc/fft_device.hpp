@@ -236,4 +236,38 @@ __device__ __forceinline__ void apply_row(float2* v, const float2* __restrict__ 
     }
 }
 
+// ------------------------------------------------------ global accesses
+// Variant flags of the transform kernels.
+enum : int {
+    kNtLoad = 1,   // non-temporal (streaming) global loads of the transform data
+    kNtStore = 2,  // non-temporal global stores of the transform data
+    kPipe = 4,     // persistent workgroups that prefetch the next unit's inputs
+};
+
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+
+template <int FL>
+__device__ __forceinline__ float2 gload(const float2* p)
+{
+    if constexpr ((FL & kNtLoad) != 0) {
+        const v2f_t t = __builtin_nontemporal_load(reinterpret_cast<const v2f_t*>(p));
+        return make_float2(t.x, t.y);
+    } else {
+        return *p;
+    }
+}
+
+template <int FL>
+__device__ __forceinline__ void gstore(float2* p, float2 v)
+{
+    if constexpr ((FL & kNtStore) != 0) {
+        v2f_t t;
+        t.x = v.x;
+        t.y = v.y;
+        __builtin_nontemporal_store(t, reinterpret_cast<v2f_t*>(p));
+    } else {
+        *p = v;
+    }
+}
+
 }  // namespace fb

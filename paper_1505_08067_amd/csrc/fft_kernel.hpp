@@ -1,0 +1,308 @@
+// The transform kernel shared by the single-block path and the two four-step
+// passes (paper, Approach: one elementary FFT block per compute unit; each
+// task reads all its inputs, computes, and writes all its outputs).
+//
+// A workgroup runs C transforms of length N with T = N/E threads each; every
+// thread holds E complex values in VGPRs.  The radix stages of the schedule
+// S run in registers; between stages the values are exchanged through LDS
+// with a barrier pair.  The first stage reads global memory directly and the
+// last stage writes it directly, so the only difference between the block
+// kernel and the four-step passes is the address map (the policy P):
+//
+//   PolBlock : transform f of unit u is contiguous at (u*C + f) * N;
+//              threads of one transform are consecutive lanes.
+//   PolPass1 : column c0+f of a long transform viewed as N1 x N2 (row-major);
+//              sample n at n*N2 + c0 + f.  Lanes run over f first, so every
+//              wave reads runs of C consecutive complex values.  Outputs are
+//              multiplied by exp(-2 pi i (c0+f) k / N) and written to the
+//              workspace in blocks of CW consecutive k (layout
+//              W[k / CW][n2][k mod CW]), so a block of rows is contiguous.
+//   PolPass2 : row k1 = g*CW + f of the workspace; sample n2 at
+//              g*N2*CW + n2*CW + f (contiguous across the workgroup).  Output
+//              k2 goes to k1 + N1*k2: the corner turn is fused into the store.
+//
+// Variant flags (kNtLoad, kNtStore, kPipe, kSwz): non-temporal global loads
+// and stores, persistent workgroups that prefetch the next unit's stage-0
+// inputs while the current unit computes, and an XOR-swizzled unpadded LDS
+// layout (one transform per 16-aligned bank group).
+#pragma once
+
+#include "fft_device.hpp"
+#include "internal.hpp"
+
+namespace fb {
+
+enum : int { kSwz = 8 };
+
+// LDS index map: padded (default) or XOR-swizzled within 16-value groups.
+template <int FL>
+__device__ __forceinline__ int lds_at(int i)
+{
+    if constexpr ((FL & kSwz) != 0) {
+        return i ^ ((i >> 4) & 15);
+    } else {
+        return lds_pad(i);
+    }
+}
+
+template <int N, int FL>
+__host__ __device__ constexpr int lds_stride()
+{
+    return (FL & kSwz) != 0 ? N : lds_pad(N) + 1;
+}
+
+// ----------------------------------------------------------------- policies
+struct PolBlock {
+    static constexpr bool f_fast = false;
+    static constexpr bool conj_in = true;
+    static constexpr bool conj_out = true;
+    static constexpr int kind = kKindBlock;
+    struct Ctx {
+        const float2* src;
+        float2* dst;
+        bool act;
+    };
+    template <int N, int C>
+    __device__ static Ctx ctx(const KArgs& a, long long unit, int f)
+    {
+        const long long b = unit * C + f;
+        Ctx c;
+        c.act = b < a.batch;
+        const long long bb = c.act ? b : 0;
+        c.src = a.in + bb * N;
+        c.dst = a.out + bb * N;
+        return c;
+    }
+    template <int C>
+    __device__ static const float2* in_at(const KArgs&, const Ctx& c, int n)
+    {
+        return c.src + n;
+    }
+    template <int FL>
+    __device__ static void store(const KArgs&, const Ctx& c, int k, float2 x)
+    {
+        gstore<FL>(c.dst + k, x);
+    }
+    __host__ __device__ static long long units(const KArgs& a, int C) { return (a.batch + C - 1) / C; }
+};
+
+struct PolPass1 {
+    static constexpr bool f_fast = true;
+    static constexpr bool conj_in = true;
+    static constexpr bool conj_out = false;
+    static constexpr int kind = kKindPass1;
+    struct Ctx {
+        const float2* src;
+        float2* dst;
+        unsigned col;
+        bool act;
+    };
+    template <int N, int C>
+    __device__ static Ctx ctx(const KArgs& a, long long unit, int f)
+    {
+        const long long bt = unit / a.tiles;
+        const int tile = (int)(unit - bt * a.tiles);
+        Ctx c;
+        c.col = (unsigned)(tile * C + f);
+        c.act = true;
+        c.src = a.in + bt * a.nbig + c.col;
+        c.dst = a.out + bt * a.nbig + ((long long)c.col << a.cw_bits);
+        return c;
+    }
+    template <int C>
+    __device__ static const float2* in_at(const KArgs& a, const Ctx& c, int n)
+    {
+        return c.src + (long long)n * a.n_other;
+    }
+    template <int FL>
+    __device__ static void store(const KArgs& a, const Ctx& c, int k, float2 x)
+    {
+        const unsigned m = (c.col * (unsigned)k) & (unsigned)(a.nbig - 1);
+        const float2 w = cmul(a.tw_hi[m >> a.lo_bits], a.tw_lo[m & ((1u << a.lo_bits) - 1u)]);
+        const long long blk = (long long)(k >> a.cw_bits) * (a.n_other << a.cw_bits);
+        gstore<FL>(c.dst + blk + (k & ((1 << a.cw_bits) - 1)), cmul(x, w));
+    }
+    __host__ __device__ static long long units(const KArgs& a, int) { return a.batch * a.tiles; }
+};
+
+struct PolPass2 {
+    static constexpr bool f_fast = true;
+    static constexpr bool conj_in = false;
+    static constexpr bool conj_out = true;
+    static constexpr int kind = kKindPass2;
+    struct Ctx {
+        const float2* src;
+        float2* dst;
+        bool act;
+    };
+    template <int N, int C>
+    __device__ static Ctx ctx(const KArgs& a, long long unit, int f)
+    {
+        const long long bt = unit / a.tiles;
+        const int g = (int)(unit - bt * a.tiles);
+        Ctx c;
+        c.act = true;
+        c.src = a.in + bt * a.nbig + (long long)g * N * C + f;
+        c.dst = a.out + bt * a.nbig + (long long)g * C + f;
+        return c;
+    }
+    template <int C>
+    __device__ static const float2* in_at(const KArgs&, const Ctx& c, int n)
+    {
+        return c.src + (long long)n * C;
+    }
+    template <int FL>
+    __device__ static void store(const KArgs& a, const Ctx& c, int k, float2 x)
+    {
+        gstore<FL>(c.dst + (long long)k * a.n_other, x);
+    }
+    __host__ __device__ static long long units(const KArgs& a, int) { return a.batch * a.tiles; }
+};
+
+// --------------------------------------------------------------- the stages
+// v holds the stage-0 inputs x[t + i*T + r*N/R0] on entry and the outputs
+// X[t + i*T + q*Ns_last] on exit.
+template <int N, int E, class S, int FL>
+__device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const float2* __restrict__ tw, int t)
+{
+    constexpr int T = N / E;
+    constexpr int NST = S::count;
+    sfor<0, NST>([&](auto sc) {
+        constexpr int s = decltype(sc)::value;
+        constexpr int R = S::r(s);
+        constexpr int Ns = S::ns(s);
+        if constexpr (s > 0) {
+#pragma unroll
+            for (int i = 0; i < E / R; ++i)
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[i * R + r] = L[lds_at<FL>(t + i * T + r * (N / R))];
+#pragma unroll
+            for (int i = 0; i < E / R; ++i) {
+                const int k = (t + i * T) % Ns;
+                apply_row<R>(&v[i * R], tw + S::tw_off(s) + k * R);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < E / R; ++i) Dft<R>::run(&v[i * R]);
+        if constexpr (s < NST - 1) {
+            if constexpr (s > 0) __syncthreads();
+#pragma unroll
+            for (int i = 0; i < E / R; ++i) {
+                const int j = t + i * T;
+                const int base = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+                for (int q = 0; q < R; ++q) L[lds_at<FL>(base + q * Ns)] = v[i * R + q];
+            }
+            __syncthreads();
+        }
+    });
+}
+
+template <int N, int E, int C, class S, class P, int FL>
+__global__ void __launch_bounds__((N / E) * C) k_fft(KArgs a)
+{
+    constexpr int T = N / E;
+    constexpr int NST = S::count;
+    constexpr int LDSN = lds_stride<N, FL>();
+    constexpr int R0 = S::r(0);
+    constexpr int RL = S::r(NST - 1);
+    constexpr int NsL = S::ns(NST - 1);
+    static_assert(S::n() == N, "schedule does not multiply to N");
+    __shared__ float2 lds[NST > 1 ? C * LDSN : 1];
+
+    const int tid = threadIdx.x;
+    const int f = P::f_fast ? tid % C : tid / T;
+    const int t = P::f_fast ? tid / C : tid % T;
+    float2* L = lds + (NST > 1 ? f * LDSN : 0);
+
+    auto load = [&](float2(&v)[E], long long unit) {
+        const auto cx = P::template ctx<N, C>(a, unit, f);
+#pragma unroll
+        for (int i = 0; i < E / R0; ++i)
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                const int n = t + i * T + r * (N / R0);
+                float2 x = cx.act ? gload<FL>(P::template in_at<C>(a, cx, n)) : make_float2(0.f, 0.f);
+                if constexpr (P::conj_in) x.y *= a.sg;
+                v[i * R0 + r] = x;
+            }
+    };
+    auto finish = [&](float2(&v)[E], long long unit) {
+        run_stages<N, E, S, FL>(v, L, a.tw, t);
+        const auto cx = P::template ctx<N, C>(a, unit, f);
+        if (cx.act) {
+#pragma unroll
+            for (int i = 0; i < E / RL; ++i)
+#pragma unroll
+                for (int q = 0; q < RL; ++q) {
+                    float2 x = v[i * RL + q];
+                    if constexpr (P::conj_out) x.y *= a.sg;
+                    P::template store<FL>(a, cx, t + i * T + q * NsL, x);
+                }
+        }
+    };
+
+    if constexpr ((FL & kPipe) == 0) {
+        float2 v[E];
+        load(v, blockIdx.x);
+        finish(v, blockIdx.x);
+    } else {
+        const long long units = P::units(a, C);
+        long long u = blockIdx.x;
+        if (u >= units) return;
+        float2 nx[E];
+        load(nx, u);
+        for (;;) {
+            float2 v[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = nx[e];
+            const long long un = u + gridDim.x;
+            if (un < units) load(nx, un);
+            finish(v, u);
+            if (un >= units) break;
+            u = un;
+            __syncthreads();  // the next unit's first LDS writes follow every thread's last LDS reads
+        }
+    }
+}
+
+template <int N, int E, int C, class S, class P, int FL>
+hipError_t launch_fft(const KArgs& a, long long grid, hipStream_t st)
+{
+    if (grid <= 0 || grid > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_fft<N, E, C, S, P, FL>), dim3((unsigned)grid), dim3((N / E) * C), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int N, int E, int C, class S, class P, int FL>
+int occupancy_fft()
+{
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void*)&k_fft<N, E, C, S, P, FL>,
+                                                     (N / E) * C, 0) != hipSuccess)
+        return 0;
+    return blocks;
+}
+
+template <int N, int E, int C, class S, class P, int FL>
+constexpr KEntry make_entry(bool is_default, const char* name)
+{
+    KEntry k{};
+    k.kind = P::kind;
+    k.n = N;
+    k.e = E;
+    k.c = C;
+    k.flags = FL;
+    k.nr = S::count;
+    for (int i = 0; i < S::count && i < 8; ++i) k.radix[i] = S::r(i);
+    k.tw_size = S::tw_size();
+    k.threads = (N / E) * C;
+    k.lds = S::count > 1 ? (size_t)C * lds_stride<N, FL>() * sizeof(float2) : sizeof(float2);
+    k.is_default = is_default;
+    k.launch = &launch_fft<N, E, C, S, P, FL>;
+    k.occupancy = &occupancy_fft<N, E, C, S, P, FL>;
+    k.name = name;
+    return k;
+}
+
+}  // namespace fb

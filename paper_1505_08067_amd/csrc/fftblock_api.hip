@@ -1,5 +1,5 @@
 // Host side of the C ABI declared in include/fftblock.h: argument checks,
-// the planner (block limit, path, radix schedule, four-step split), FP64
+// the planner (block limit, path, kernel choice, four-step split), FP64
 // twiddle generation, plan lifetime and launches.
 //
 // Planner (paper, Approach): the largest transform one compute unit holds is
@@ -17,6 +17,7 @@
 #include <cstring>
 #include <mutex>
 #include <unordered_set>
+#include <vector>
 
 #include "../../include/fftblock.h"
 #include "internal.hpp"
@@ -28,17 +29,79 @@ struct fft_plan_s {
     int direction = FFT_FORWARD;
     int path = 0;
     int device = 0;
-    const BlockEntry* blk = nullptr;
-    const TileEntry* p1 = nullptr;
-    const TileEntry* p2 = nullptr;
+    const KEntry* k1 = nullptr;     // block kernel, or four-step pass 1
+    const KEntry* k2 = nullptr;     // four-step pass 2
     size_t n1 = 0, n2 = 0;
     int lo_bits = 0;
+    int cw_bits = 0;
+    long long grid1 = 0, grid2 = 0;
     float2* tw = nullptr;           // one allocation holding every table
     size_t tw_bytes = 0;
     size_t off_s1 = 0, off_s2 = 0, off_hi = 0, off_lo = 0;  // in complex entries
     float2* work = nullptr;
     size_t work_bytes = 0;
 };
+
+namespace fb {
+
+static std::vector<KEntry> build_table()
+{
+    std::vector<KEntry> v;
+    int nb = 0, np = 0;
+    const KEntry* b = block_entries(&nb);
+    const KEntry* p = pass_entries(&np);
+    v.insert(v.end(), b, b + nb);
+    v.insert(v.end(), p, p + np);
+    return v;
+}
+
+static const std::vector<KEntry>& table()
+{
+    static const std::vector<KEntry> t = build_table();
+    return t;
+}
+
+const KEntry* kernel_table(int* count)
+{
+    *count = (int)table().size();
+    return table().data();
+}
+
+const KEntry* kernel_default(int kind, int n, int c)
+{
+    const KEntry* any = nullptr;
+    for (const KEntry& k : table()) {
+        if (k.kind != kind || k.n != n || (c > 0 && k.c != c)) continue;
+        if (k.is_default) return &k;
+        if (!any && k.flags == 0) any = &k;
+    }
+    return any;
+}
+
+const KEntry* kernel_find(int kind, int n, const int* radix, int nr, int c, int flags)
+{
+    for (const KEntry& k : table()) {
+        if (k.kind != kind || k.n != n) continue;
+        if (c > 0 && k.c != c) continue;
+        if (flags >= 0 && k.flags != flags) continue;
+        if (nr > 0) {
+            if (k.nr != nr) continue;
+            bool same = true;
+            for (int i = 0; i < nr; ++i) same = same && k.radix[i] == radix[i];
+            if (!same) continue;
+        }
+        return &k;
+    }
+    return nullptr;
+}
+
+long long kernel_units(const KEntry& k, const KArgs& a)
+{
+    if (k.kind == kKindBlock) return (a.batch + k.c - 1) / k.c;
+    return a.batch * a.tiles;
+}
+
+}  // namespace fb
 
 namespace {
 
@@ -118,7 +181,6 @@ void fill_stage_table(const int* radix, int nr, float2* dst)
     }
 }
 
-
 size_t env_size(const char* name, size_t dflt)
 {
     const char* v = std::getenv(name);
@@ -132,6 +194,19 @@ constexpr size_t kMaxN = size_t(1) << 22;
 constexpr size_t kDefaultBlockLimit = 16384;
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+size_t sanitize_limit(size_t lim)
+{
+    if (!is_pow2(lim) || lim < 1024 || lim > kDefaultBlockLimit) return kDefaultBlockLimit;
+    return lim;
+}
+
+int log2i(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
 
 }  // namespace
 
@@ -150,73 +225,14 @@ const char* fft_status_string(fft_status_t s)
     return "unknown status";
 }
 
-size_t fft_block_limit(void)
-{
-    size_t lim = env_size("FFTBLOCK_BLOCK_MAX", kDefaultBlockLimit);
-    if (!is_pow2(lim) || lim < 1024) lim = kDefaultBlockLimit;
-    if (lim > kDefaultBlockLimit) lim = kDefaultBlockLimit;
-    return lim;
-}
+size_t fft_block_limit(void) { return sanitize_limit(env_size("FFTBLOCK_BLOCK_MAX", kDefaultBlockLimit)); }
 
-// Pure host planning: path, kernels, four-step split and table layout.
-// Makes no HIP call, so it is usable (and testable) without a device.
-static fft_status_t plan_choose(size_t n, size_t batch, int direction, fft_plan_s* p, size_t* table_entries)
+void fft_plan_opts_init(fft_plan_opts_t* o)
 {
-    if (n == 0 || batch == 0) return FFT_ERR_INVALID_ARG;
-    if (direction != FFT_FORWARD && direction != FFT_BACKWARD) return FFT_ERR_INVALID_ARG;
-    if (!is_pow2(n) || n > kMaxN) return FFT_ERR_UNSUPPORTED_SIZE;
-    if (batch > ((size_t)1 << 40) / n) return FFT_ERR_INVALID_ARG;
-    p->n = n;
-    p->batch = batch;
-    p->direction = direction;
-    const size_t limit = fft_block_limit();
-    size_t off = 0;
-    if (n == 1) {
-        p->path = FFT_PATH_BLOCK;
-    } else if (n <= limit) {
-        p->path = FFT_PATH_BLOCK;
-        p->blk = block_default((int)n);
-        if (!p->blk) return FFT_ERR_UNSUPPORTED_SIZE;
-        p->off_s1 = 0;
-        off = round_up((size_t)p->blk->tw_size, 32);
-    } else {
-        p->path = FFT_PATH_FOURSTEP;
-        const int L = ilog2(n);
-        p->n1 = size_t(1) << ((L + 1) / 2);
-        p->n2 = n / p->n1;
-        const int c = (int)env_size("FFTBLOCK_FOURSTEP_C", 0);
-        p->p1 = tile_find(1, (int)p->n1, c);
-        p->p2 = tile_find(2, (int)p->n2, c);
-        if (!p->p1) p->p1 = tile_find(1, (int)p->n1, 0);
-        if (!p->p2) p->p2 = tile_find(2, (int)p->n2, 0);
-        if (!p->p1 || !p->p2 || p->n2 % p->p1->c || p->n1 % p->p2->c) return FFT_ERR_UNSUPPORTED_SIZE;
-        p->lo_bits = (L + 1) / 2;
-        p->off_s1 = 0;
-        off = round_up((size_t)p->p1->tw_size, 32);
-        p->off_s2 = off;
-        off += round_up((size_t)p->p2->tw_size, 32);
-        p->off_hi = off;
-        off += round_up(n >> p->lo_bits, 32);
-        p->off_lo = off;
-        off += round_up(size_t(1) << p->lo_bits, 32);
-        p->work_bytes = n * batch * sizeof(float2);
-    }
-    p->tw_bytes = off * sizeof(float2);
-    *table_entries = off;
-    return FFT_SUCCESS;
-}
-
-static void describe(const fft_plan_s* plan, fft_plan_desc_t* d);
-
-fft_status_t fft_plan_query(size_t n, size_t batch, int direction, fft_plan_desc_t* desc)
-{
-    if (desc == nullptr) return FFT_ERR_INVALID_ARG;
-    fft_plan_s tmp;
-    size_t entries = 0;
-    const fft_status_t s = plan_choose(n, batch, direction, &tmp, &entries);
-    if (s != FFT_SUCCESS) return s;
-    describe(&tmp, desc);
-    return FFT_SUCCESS;
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->flags = -1;
+    o->flags2 = -1;
 }
 
 size_t fft_block_max(size_t lds_bytes, int k)
@@ -230,32 +246,218 @@ size_t fft_block_max(size_t lds_bytes, int k)
     return p2;
 }
 
-fft_status_t fft_plan_create(size_t n, size_t batch, int direction, fft_plan_t* plan_out)
+int fft_kernel_count(void)
+{
+    int c = 0;
+    kernel_table(&c);
+    return c;
+}
+
+fft_status_t fft_kernel_info(int index, fft_kernel_info_t* info)
+{
+    if (info == nullptr) return FFT_ERR_INVALID_ARG;
+    int c = 0;
+    const KEntry* t = kernel_table(&c);
+    if (index < 0 || index >= c) return FFT_ERR_INVALID_ARG;
+    const KEntry& k = t[index];
+    std::memset(info, 0, sizeof(*info));
+    info->kind = k.kind;
+    info->n = k.n;
+    info->e = k.e;
+    info->c = k.c;
+    info->flags = k.flags;
+    info->n_radix = k.nr;
+    for (int i = 0; i < k.nr; ++i) info->radix[i] = k.radix[i];
+    info->threads = k.threads;
+    info->lds_bytes = k.lds;
+    info->is_default = k.is_default ? 1 : 0;
+    info->name = k.name;
+    return FFT_SUCCESS;
+}
+
+// Pure host planning: path, kernels, four-step split and table layout.
+// Makes no HIP call, so it is usable (and testable) without a device.
+static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft_plan_opts_t* opts,
+                                fft_plan_s* p, size_t* table_entries)
+{
+    if (n == 0 || batch == 0) return FFT_ERR_INVALID_ARG;
+    if (direction != FFT_FORWARD && direction != FFT_BACKWARD) return FFT_ERR_INVALID_ARG;
+    if (!is_pow2(n) || n > kMaxN) return FFT_ERR_UNSUPPORTED_SIZE;
+    if (batch > ((size_t)1 << 40) / n) return FFT_ERR_INVALID_ARG;
+    fft_plan_opts_t o;
+    fft_plan_opts_init(&o);
+    if (opts) o = *opts;
+    if (o.n_radix < 0 || o.n_radix > 8) return FFT_ERR_INVALID_ARG;
+    p->n = n;
+    p->batch = batch;
+    p->direction = direction;
+    const size_t limit = o.block_limit ? sanitize_limit(o.block_limit) : fft_block_limit();
+    size_t off = 0;
+    if (n == 1) {
+        p->path = FFT_PATH_BLOCK;
+    } else if (n <= limit) {
+        p->path = FFT_PATH_BLOCK;
+        if (o.n_radix == 0 && o.flags < 0)
+            p->k1 = kernel_default(kKindBlock, (int)n, 0);
+        else
+            p->k1 = kernel_find(kKindBlock, (int)n, o.radix, o.n_radix, 0, o.flags < 0 ? 0 : o.flags);
+        if (!p->k1) return FFT_ERR_UNSUPPORTED_SIZE;
+        off = round_up((size_t)p->k1->tw_size, 32);
+    } else {
+        p->path = FFT_PATH_FOURSTEP;
+        const int L = ilog2(n);
+        p->n1 = size_t(1) << ((L + 1) / 2);
+        p->n2 = n / p->n1;
+        const int c1 = o.c > 0 ? o.c : (int)env_size("FFTBLOCK_FOURSTEP_C", 0);
+        const int c2 = o.c2 > 0 ? o.c2 : (int)env_size("FFTBLOCK_FOURSTEP_C2", 0);
+        p->k1 = o.flags < 0 ? kernel_default(kKindPass1, (int)p->n1, c1)
+                            : kernel_find(kKindPass1, (int)p->n1, nullptr, 0, c1, o.flags);
+        p->k2 = o.flags2 < 0 ? kernel_default(kKindPass2, (int)p->n2, c2)
+                             : kernel_find(kKindPass2, (int)p->n2, nullptr, 0, c2, o.flags2);
+        if (!p->k1 || !p->k2) return FFT_ERR_UNSUPPORTED_SIZE;
+        if (p->n2 % p->k1->c || p->n1 % p->k2->c) return FFT_ERR_UNSUPPORTED_SIZE;
+        p->lo_bits = (L + 1) / 2;
+        p->cw_bits = log2i(p->k2->c);
+        off = round_up((size_t)p->k1->tw_size, 32);
+        p->off_s2 = off;
+        off += round_up((size_t)p->k2->tw_size, 32);
+        p->off_hi = off;
+        off += round_up(n >> p->lo_bits, 32);
+        p->off_lo = off;
+        off += round_up(size_t(1) << p->lo_bits, 32);
+        p->work_bytes = n * batch * sizeof(float2);
+    }
+    p->tw_bytes = off * sizeof(float2);
+    *table_entries = off;
+    return FFT_SUCCESS;
+}
+
+static KArgs make_args(const fft_plan_s* p, int pass, const float2* in, float2* out)
+{
+    KArgs a{};
+    a.in = in;
+    a.out = out;
+    a.batch = (long long)p->batch;
+    a.sg = p->direction == FFT_FORWARD ? 1.0f : -1.0f;
+    if (p->path == FFT_PATH_BLOCK) {
+        a.tw = p->tw + p->off_s1;
+        return a;
+    }
+    a.nbig = (long long)p->n;
+    a.lo_bits = p->lo_bits;
+    a.cw_bits = p->cw_bits;
+    a.tw_hi = p->tw + p->off_hi;
+    a.tw_lo = p->tw + p->off_lo;
+    if (pass == 1) {
+        a.tw = p->tw + p->off_s1;
+        a.n_other = (long long)p->n2;
+        a.tiles = (int)(p->n2 / p->k1->c);
+    } else {
+        a.tw = p->tw + p->off_s2;
+        a.n_other = (long long)p->n1;
+        a.tiles = (int)(p->n1 / p->k2->c);
+    }
+    return a;
+}
+
+static void describe(const fft_plan_s* plan, fft_plan_desc_t* d)
+{
+    std::memset(d, 0, sizeof(*d));
+    d->n = plan->n;
+    d->batch = plan->batch;
+    d->direction = plan->direction;
+    d->path = plan->path;
+    d->n1 = plan->n1;
+    d->n2 = plan->n2;
+    d->workspace_bytes = plan->work_bytes;
+    d->twiddle_bytes = plan->tw_bytes;
+    d->kernels_per_execute = plan->path == FFT_PATH_FOURSTEP ? 2 : 1;
+    d->grid = plan->grid1;
+    if (!plan->k1) {
+        d->kernel_name = "copy";
+        return;
+    }
+    d->n_radix = plan->k1->nr;
+    for (int i = 0; i < plan->k1->nr; ++i) d->radix[i] = plan->k1->radix[i];
+    d->threads_per_block = plan->k1->threads;
+    d->transforms_per_block = plan->k1->c;
+    d->lds_bytes = plan->k1->lds;
+    d->kernel_name = plan->k1->name;
+    d->flags = plan->k1->flags;
+    if (plan->k2) {
+        d->n_radix2 = plan->k2->nr;
+        for (int i = 0; i < plan->k2->nr; ++i) d->radix2[i] = plan->k2->radix[i];
+        d->kernel_name2 = plan->k2->name;
+        d->flags2 = plan->k2->flags;
+        d->c2 = plan->k2->c;
+    }
+}
+
+fft_status_t fft_plan_query_ex(size_t n, size_t batch, int direction, const fft_plan_opts_t* opts,
+                               fft_plan_desc_t* desc)
+{
+    if (desc == nullptr) return FFT_ERR_INVALID_ARG;
+    fft_plan_s tmp;
+    size_t entries = 0;
+    const fft_status_t s = plan_choose(n, batch, direction, opts, &tmp, &entries);
+    if (s != FFT_SUCCESS) return s;
+    describe(&tmp, desc);
+    return FFT_SUCCESS;
+}
+
+fft_status_t fft_plan_query(size_t n, size_t batch, int direction, fft_plan_desc_t* desc)
+{
+    return fft_plan_query_ex(n, batch, direction, nullptr, desc);
+}
+
+// Workgroups of a launch: one per unit, or for persistent variants the
+// resident capacity of the device (units beyond it are looped over).
+static long long grid_for(const KEntry* k, const KArgs& a, int cus)
+{
+    const long long units = kernel_units(*k, a);
+    if ((k->flags & FFT_VARIANT_PERSISTENT) == 0) return units;
+    const int occ = k->occupancy ? k->occupancy() : 0;
+    const long long cap = (long long)(occ > 0 ? occ : 1) * (cus > 0 ? cus : 1);
+    return units < cap ? units : cap;
+}
+
+fft_status_t fft_plan_create_ex(size_t n, size_t batch, int direction, const fft_plan_opts_t* opts,
+                                fft_plan_t* plan_out)
 {
     if (plan_out == nullptr) return FFT_ERR_INVALID_ARG;
     *plan_out = nullptr;
     fft_plan_s* p = new (std::nothrow) fft_plan_s();
     if (!p) return FFT_ERR_OUT_OF_MEMORY;
     size_t off = 0;
-    const fft_status_t st = plan_choose(n, batch, direction, p, &off);
-    if (st != FFT_SUCCESS) { delete p; return st; }
+    const fft_status_t st = plan_choose(n, batch, direction, opts, p, &off);
+    if (st != FFT_SUCCESS) {
+        delete p;
+        return st;
+    }
 
     hipError_t e = hipGetDevice(&p->device);
-    if (e != hipSuccess) { delete p; return from_hip(e); }
+    int cus = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return from_hip(e);
+    }
+    if (p->k1) p->grid1 = grid_for(p->k1, make_args(p, 1, nullptr, nullptr), cus);
+    if (p->k2) p->grid2 = grid_for(p->k2, make_args(p, 2, nullptr, nullptr), cus);
 
     if (off > 0) {
         float2* host = (float2*)std::calloc(off, sizeof(float2));
-        if (!host) { delete p; return FFT_ERR_OUT_OF_MEMORY; }
-        if (p->path == FFT_PATH_BLOCK) {
-            fill_stage_table(p->blk->radix, p->blk->nr, host + p->off_s1);
-        } else {
-            fill_stage_table(p->p1->radix, p->p1->nr, host + p->off_s1);
-            fill_stage_table(p->p2->radix, p->p2->nr, host + p->off_s2);
+        if (!host) {
+            delete p;
+            return FFT_ERR_OUT_OF_MEMORY;
+        }
+        fill_stage_table(p->k1->radix, p->k1->nr, host + p->off_s1);
+        if (p->path == FFT_PATH_FOURSTEP) {
+            fill_stage_table(p->k2->radix, p->k2->nr, host + p->off_s2);
             const long long N = (long long)n;
             for (long long a = 0; a < (N >> p->lo_bits); ++a) host[p->off_hi + a] = root_f32(a << p->lo_bits, N);
             for (long long b = 0; b < (1LL << p->lo_bits); ++b) host[p->off_lo + b] = root_f32(b, N);
         }
-        p->tw_bytes = off * sizeof(float2);
         e = hipMalloc((void**)&p->tw, p->tw_bytes);
         if (e == hipSuccess) e = hipMemcpy(p->tw, host, p->tw_bytes, hipMemcpyHostToDevice);
         std::free(host);
@@ -281,6 +483,11 @@ fft_status_t fft_plan_create(size_t n, size_t batch, int direction, fft_plan_t* 
     return FFT_SUCCESS;
 }
 
+fft_status_t fft_plan_create(size_t n, size_t batch, int direction, fft_plan_t* plan_out)
+{
+    return fft_plan_create_ex(n, batch, direction, nullptr, plan_out);
+}
+
 fft_status_t fft_plan_destroy(fft_plan_t plan)
 {
     {
@@ -296,43 +503,6 @@ fft_status_t fft_plan_destroy(fft_plan_t plan)
     if (cur != plan->device) (void)hipSetDevice(cur);
     delete plan;
     return from_hip(e);
-}
-
-static void describe(const fft_plan_s* plan, fft_plan_desc_t* d)
-{
-    std::memset(d, 0, sizeof(*d));
-    d->n = plan->n;
-    d->batch = plan->batch;
-    d->direction = plan->direction;
-    d->path = plan->path;
-    d->n1 = plan->n1;
-    d->n2 = plan->n2;
-    d->workspace_bytes = plan->work_bytes;
-    d->twiddle_bytes = plan->tw_bytes;
-    if (plan->path == FFT_PATH_BLOCK) {
-        d->kernels_per_execute = 1;
-        if (plan->blk) {
-            d->n_radix = plan->blk->nr;
-            for (int i = 0; i < plan->blk->nr; ++i) d->radix[i] = plan->blk->radix[i];
-            d->threads_per_block = plan->blk->threads;
-            d->transforms_per_block = plan->blk->fpb;
-            d->lds_bytes = plan->blk->lds;
-            d->kernel_name = plan->blk->name;
-        } else {
-            d->kernel_name = "copy";
-        }
-    } else {
-        d->kernels_per_execute = 2;
-        d->n_radix = plan->p1->nr;
-        for (int i = 0; i < plan->p1->nr; ++i) d->radix[i] = plan->p1->radix[i];
-        d->n_radix2 = plan->p2->nr;
-        for (int i = 0; i < plan->p2->nr; ++i) d->radix2[i] = plan->p2->radix[i];
-        d->threads_per_block = plan->p1->threads;
-        d->transforms_per_block = plan->p1->c;
-        d->lds_bytes = plan->p1->lds;
-        d->kernel_name = plan->p1->name;
-        d->kernel_name2 = plan->p2->name;
-    }
 }
 
 fft_status_t fft_plan_describe(fft_plan_t plan, fft_plan_desc_t* d)
@@ -358,7 +528,6 @@ static fft_status_t execute_impl(fft_plan_t plan, int passes, const void* in, vo
     if (e != hipSuccess) return from_hip(e);
     if (cur != plan->device && (e = hipSetDevice(plan->device)) != hipSuccess) return from_hip(e);
     hipStream_t st = (hipStream_t)stream;
-    const float sg = plan->direction == FFT_FORWARD ? 1.0f : -1.0f;
     const float2* x = (const float2*)in;
     float2* y = (float2*)out;
     const bool run1 = passes == 0 || passes == 1;
@@ -368,25 +537,11 @@ static fft_status_t execute_impl(fft_plan_t plan, int passes, const void* in, vo
         if (plan->n == 1) {
             e = (in == out) ? hipSuccess : hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, st);
         } else {
-            e = plan->blk->launch(x, y, plan->tw + plan->off_s1, (long long)plan->batch, sg, st);
+            e = plan->k1->launch(make_args(plan, 1, x, y), plan->grid1, st);
         }
     } else {
-        FourStepArgs a1{};
-        a1.batch = (long long)plan->batch;
-        a1.nbig = (long long)plan->n;
-        a1.n_other = (long long)plan->n2;
-        a1.tiles = (int)(plan->n2 / plan->p1->c);
-        a1.lo_bits = plan->lo_bits;
-        a1.tw_hi = plan->tw + plan->off_hi;
-        a1.tw_lo = plan->tw + plan->off_lo;
-        a1.sg = sg;
-        if (run1) e = plan->p1->launch(x, plan->work, plan->tw + plan->off_s1, a1, st);
-        if (e == hipSuccess && run2) {
-            FourStepArgs a2 = a1;
-            a2.n_other = (long long)plan->n1;
-            a2.tiles = (int)(plan->n1 / plan->p2->c);
-            e = plan->p2->launch(plan->work, y, plan->tw + plan->off_s2, a2, st);
-        }
+        if (run1) e = plan->k1->launch(make_args(plan, 1, x, plan->work), plan->grid1, st);
+        if (e == hipSuccess && run2) e = plan->k2->launch(make_args(plan, 2, plan->work, y), plan->grid2, st);
     }
     if (cur != plan->device) (void)hipSetDevice(cur);
     return from_hip(e);

@@ -35,8 +35,15 @@ STATUS = {
 EXPORTS = (
     "fft_plan_create", "fft_execute", "fft_execute_pass", "fft_transpose", "fft_plan_destroy", "fft_status_string",
     "fft_plan_describe", "fft_plan_query", "fft_device_query", "fft_block_max", "fft_block_limit",
-    "fft_copy",
+    "fft_copy", "fft_plan_opts_init", "fft_plan_create_ex", "fft_plan_query_ex", "fft_kernel_count",
+    "fft_kernel_info",
 )
+
+VARIANT_NT_LOAD = 1
+VARIANT_NT_STORE = 2
+VARIANT_PERSISTENT = 4
+VARIANT_SWIZZLE = 8
+KERNEL_KINDS = {0: "block", 1: "pass1", 2: "pass2"}
 
 
 class FFTError(RuntimeError):
@@ -56,6 +63,24 @@ class PlanDesc(ctypes.Structure):
         ("lds_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
         ("twiddle_bytes", ctypes.c_size_t), ("kernels_per_execute", ctypes.c_int),
         ("kernel_name", ctypes.c_char_p), ("kernel_name2", ctypes.c_char_p),
+        ("flags", ctypes.c_int), ("flags2", ctypes.c_int), ("c2", ctypes.c_int),
+        ("grid", ctypes.c_longlong),
+    ]
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [
+        ("block_limit", ctypes.c_size_t), ("n_radix", ctypes.c_int), ("radix", ctypes.c_int * 8),
+        ("flags", ctypes.c_int), ("c", ctypes.c_int), ("flags2", ctypes.c_int), ("c2", ctypes.c_int),
+    ]
+
+
+class KernelInfo(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int), ("n", ctypes.c_int), ("e", ctypes.c_int), ("c", ctypes.c_int),
+        ("flags", ctypes.c_int), ("n_radix", ctypes.c_int), ("radix", ctypes.c_int * 8),
+        ("threads", ctypes.c_int), ("lds_bytes", ctypes.c_size_t), ("is_default", ctypes.c_int),
+        ("name", ctypes.c_char_p),
     ]
 
 
@@ -98,8 +123,16 @@ def load():
     lib.fft_block_limit.argtypes = []
     lib.fft_block_limit.restype = sz
     lib.fft_copy.argtypes = [vp, vp, sz, vp]
+    lib.fft_plan_opts_init.argtypes = [ctypes.POINTER(PlanOpts)]
+    lib.fft_plan_opts_init.restype = None
+    lib.fft_plan_create_ex.argtypes = [sz, sz, i, ctypes.POINTER(PlanOpts), ctypes.POINTER(vp)]
+    lib.fft_plan_query_ex.argtypes = [sz, sz, i, ctypes.POINTER(PlanOpts), ctypes.POINTER(PlanDesc)]
+    lib.fft_kernel_count.argtypes = []
+    lib.fft_kernel_count.restype = i
+    lib.fft_kernel_info.argtypes = [i, ctypes.POINTER(KernelInfo)]
     for name in ("fft_plan_create", "fft_execute", "fft_execute_pass", "fft_transpose", "fft_plan_destroy",
-                 "fft_plan_describe", "fft_plan_query", "fft_device_query", "fft_copy"):
+                 "fft_plan_describe", "fft_plan_query", "fft_device_query", "fft_copy",
+                 "fft_plan_create_ex", "fft_plan_query_ex", "fft_kernel_info"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -140,23 +173,58 @@ def _desc_dict(d: "PlanDesc") -> dict:
         "twiddle_bytes": d.twiddle_bytes, "kernels_per_execute": d.kernels_per_execute,
         "kernel_name": d.kernel_name.decode() if d.kernel_name else None,
         "kernel_name2": d.kernel_name2.decode() if d.kernel_name2 else None,
+        "flags": d.flags, "flags2": d.flags2, "c2": d.c2, "grid": d.grid,
     }
 
 
-def plan_query(n: int, batch: int, direction: int = FORWARD) -> dict:
-    """What ``fft_plan_create`` would choose, without a device (``fft_plan_query``)."""
+def make_opts(block_limit=0, radix=None, flags=-1, c=0, flags2=-1, c2=0):
+    """Planner options (``fft_plan_opts_t``); every default means "planner's choice"."""
+    o = PlanOpts()
+    load().fft_plan_opts_init(ctypes.byref(o))
+    o.block_limit = block_limit
+    if radix:
+        o.n_radix = len(radix)
+        for k, r in enumerate(radix):
+            o.radix[k] = r
+    o.flags, o.c, o.flags2, o.c2 = flags, c, flags2, c2
+    return o
+
+
+def kernels() -> list:
+    """The compiled transform kernels (``fft_kernel_count`` / ``fft_kernel_info``)."""
+    lib = load()
+    out = []
+    for idx in range(lib.fft_kernel_count()):
+        k = KernelInfo()
+        _check(lib.fft_kernel_info(idx, ctypes.byref(k)), "fft_kernel_info")
+        out.append({"kind": KERNEL_KINDS[k.kind], "n": k.n, "e": k.e, "c": k.c, "flags": k.flags,
+                    "radix": list(k.radix[: k.n_radix]), "threads": k.threads, "lds_bytes": k.lds_bytes,
+                    "is_default": bool(k.is_default), "name": k.name.decode()})
+    return out
+
+
+def plan_query(n: int, batch: int, direction: int = FORWARD, opts: "PlanOpts | None" = None) -> dict:
+    """What ``fft_plan_create`` would choose, without a device (``fft_plan_query[_ex]``)."""
     d = PlanDesc()
-    _check(load().fft_plan_query(n, batch, direction, ctypes.byref(d)), f"fft_plan_query(n={n})")
+    if opts is None:
+        st = load().fft_plan_query(n, batch, direction, ctypes.byref(d))
+    else:
+        st = load().fft_plan_query_ex(n, batch, direction, ctypes.byref(opts), ctypes.byref(d))
+    _check(st, f"fft_plan_query(n={n})")
     return _desc_dict(d)
 
 
 class Plan:
     """Batched 1-D complex64 FFT plan (``fft_plan_create``)."""
 
-    def __init__(self, n: int, batch: int, direction: int = FORWARD):
+    def __init__(self, n: int, batch: int, direction: int = FORWARD, opts: "PlanOpts | None" = None):
         lib = load()
         h = ctypes.c_void_p()
-        _check(lib.fft_plan_create(n, batch, direction, ctypes.byref(h)), f"fft_plan_create(n={n}, batch={batch})")
+        if opts is None:
+            st = lib.fft_plan_create(n, batch, direction, ctypes.byref(h))
+        else:
+            st = lib.fft_plan_create_ex(n, batch, direction, ctypes.byref(opts), ctypes.byref(h))
+        _check(st, f"fft_plan_create(n={n}, batch={batch})")
         self._h = h
         self.n, self.batch, self.direction = int(n), int(batch), int(direction)
 

@@ -1,0 +1,91 @@
+"""Every compiled kernel variant against the FP64 oracle.
+
+The planner's defaults are covered by test_gpu_parity.py; the runtime sweep
+and the schedule search can select any other compiled (schedule, workgroup
+shape, variant), so each of them is held to the same tolerance here,
+including the persistent variants with more work units than resident
+workgroups and the four-step path forced onto short lengths.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import metrics
+from paper_1505_08067_amd import fftblock as fb
+from paper_1505_08067_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def run(n, batch, sign, opts, x):
+    with fb.Plan(n, batch, sign, opts) as p:
+        d = p.describe()
+        xd = torch.from_numpy(x).to("cuda")
+        y = p.execute(xd)
+        torch.cuda.synchronize()
+        return y.cpu().numpy(), d
+
+
+def _block_variants():
+    out = []
+    for k in fb.kernels():
+        if k["kind"] == "block" and k["n"] >= 2:
+            out.append(pytest.param(k, id=k["name"]))
+    return out
+
+
+@pytest.mark.parametrize("k", _block_variants())
+def test_block_variant(k):
+    n = k["n"]
+    persistent = bool(k["flags"] & fb.VARIANT_PERSISTENT)
+    batch = 2 * k["c"] + 1
+    if persistent:
+        batch = max(batch, (1 << 24) // n + 3)   # more units than resident workgroups
+    opts = fb.make_opts(radix=k["radix"], flags=k["flags"])
+    x = inputs.uniform(300 + n, batch, n)
+    for sign in (fb.FORWARD, fb.BACKWARD):
+        y, d = run(n, batch, sign, opts, x)
+        assert d["kernel_name"] == k["name"]
+        say(f"{k['name']} batch={batch} grid={d['grid']} sign={sign}")
+        ref = oracle.fft(x.astype(np.complex128), sign)
+        metrics.check(y, ref, n)
+
+
+def _pass_combos():
+    ks = fb.kernels()
+    p1 = [k for k in ks if k["kind"] == "pass1" and k["n"] == 1024]
+    p2 = [k for k in ks if k["kind"] == "pass2" and k["n"] == 1024]
+    combos = []
+    for a in p1:
+        for b in p2:
+            combos.append(pytest.param(a, b, id=f"{a['name']}+{b['name']}"))
+    return combos
+
+
+@pytest.mark.parametrize("k1,k2", _pass_combos())
+def test_fourstep_variant_pairs(k1, k2):
+    n, batch = 1 << 20, 3
+    opts = fb.make_opts(flags=k1["flags"], c=k1["c"], flags2=k2["flags"], c2=k2["c"])
+    x = inputs.uniform(400, batch, n)
+    y, d = run(n, batch, fb.FORWARD, opts, x)
+    assert (d["kernel_name"], d["kernel_name2"]) == (k1["name"], k2["name"])
+    ref = oracle.fft(x.astype(np.complex128), fb.FORWARD)
+    metrics.check(y, ref, n)
+
+
+@pytest.mark.parametrize("n", [2048, 4096, 8192, 16384])
+@pytest.mark.parametrize("sign", [fb.FORWARD, fb.BACKWARD])
+def test_fourstep_forced_on_block_sizes(n, sign):
+    opts = fb.make_opts(block_limit=1024)
+    d = fb.plan_query(n, 5, sign, opts)
+    assert d["path"] == fb.PATH_FOURSTEP
+    x = inputs.uniform(500 + n, 5, n)
+    y, d = run(n, 5, sign, opts, x)
+    say(f"forced four-step N={n} = {d['n1']}x{d['n2']}")
+    ref = oracle.fft(x.astype(np.complex128), sign)
+    metrics.check(y, ref, n)
