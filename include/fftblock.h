@@ -159,6 +159,8 @@ typedef struct {
 #define FFT_VARIANT_NT_STORE 2    /* non-temporal stores of the data */
 #define FFT_VARIANT_PERSISTENT 4  /* persistent workgroups prefetching the next unit */
 #define FFT_VARIANT_SWIZZLE 8     /* XOR-swizzled unpadded LDS layout */
+#define FFT_VARIANT_STAGED 16     /* four-step pass 1: outputs staged through LDS, contiguous stores */
+#define FFT_VARIANT_TWIDDLE_POWERS 32 /* stage twiddles from per-row powers w^(2^i) and products */
 
 typedef struct {
     size_t block_limit;  /* longest single-block length; 0 = fft_block_limit() */

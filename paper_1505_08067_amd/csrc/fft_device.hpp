@@ -206,6 +206,39 @@ struct Sched {
         return o;
     }
     static constexpr int tw_size() { return tw_off(count); }
+    // Factorised layout (persistent kernels keep it in LDS): a stage with
+    // Ns <= 16 keeps its full rows; a larger one stores A[q][r] = w_{Q R}^{r q}
+    // for q < Q, then B[p][r] = w_{Ns R}^{r p} for p < M, with Ns = Q M and Q
+    // the largest power of two whose square is <= Ns, so that
+    // w_{Ns R}^{r (q M + p)} = A[q][r] * B[p][r].
+    static constexpr bool f_full(int s) { return ns(s) <= 16; }
+    static constexpr int fq(int s)
+    {
+        int q = 1;
+        while (4 * q * q <= ns(s)) q *= 2;
+        return f_full(s) ? ns(s) : q;
+    }
+    static constexpr int fm(int s) { return f_full(s) ? 1 : ns(s) / fq(s); }
+    static constexpr int f_size(int s) { return f_full(s) ? ns(s) * r(s) : (fq(s) + fm(s)) * r(s); }
+    static constexpr int ftw_off(int s)
+    {
+        int o = 0;
+        for (int i = 1; i < s; ++i) o += f_size(i);
+        return o;
+    }
+    static constexpr int ftw_size() { return ftw_off(count); }
+    // Power layout: row k of stage s holds w^(2^i), i < log2(R), for
+    // w = w_{Ns R}^k (padded to an even count for 16-byte loads); the other
+    // powers are formed by products (binary decomposition of the exponent).
+    static constexpr int lg(int v) { return v <= 1 ? 0 : 1 + lg(v / 2); }
+    static constexpr int p_row(int s) { return (lg(r(s)) + 1) & ~1; }
+    static constexpr int ptw_off(int s)
+    {
+        int o = 0;
+        for (int i = 1; i < s; ++i) o += ns(i) * p_row(i);
+        return o;
+    }
+    static constexpr int ptw_size() { return ptw_off(count); }
     static constexpr int max_r()
     {
         int m = 1;
@@ -267,6 +300,46 @@ __device__ __forceinline__ void gstore(float2* p, float2 v)
         __builtin_nontemporal_store(t, reinterpret_cast<v2f_t*>(p));
     } else {
         *p = v;
+    }
+}
+
+// Powers w^r, r < R, from the row w^(2^i), i < log2(R) (FP64-generated,
+// FP32-stored): w^r = w^h * w^(r-h) with h the highest power of two in r, so
+// each power carries at most popcount(r) - 1 complex products.
+template <int R>
+__device__ __forceinline__ void powers_from_row(float2 (&w)[R], const float2* __restrict__ row)
+{
+    constexpr int P = (R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : R == 16 ? 4 : 5);
+    constexpr int PP = (P + 1) & ~1;
+    float2 p[PP];
+    const float4* row4 = reinterpret_cast<const float4*>(row);
+#pragma unroll
+    for (int i = 0; i < PP; i += 2) {
+        const float4 q = row4[i / 2];
+        p[i] = make_float2(q.x, q.y);
+        p[i + 1] = make_float2(q.z, q.w);
+    }
+    w[0] = make_float2(1.f, 0.f);
+    sfor<1, R>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        constexpr int h = (r >= 16) ? 16 : (r >= 8) ? 8 : (r >= 4) ? 4 : (r >= 2) ? 2 : 1;
+        constexpr int hi = (h == 16) ? 4 : (h == 8) ? 3 : (h == 4) ? 2 : (h == 2) ? 1 : 0;
+        if constexpr (r == h)
+            w[r] = p[hi];
+        else
+            w[r] = cmul(w[h], w[r - h]);
+    });
+}
+
+// Multiplies input r of one radix-R butterfly by w^r (powers from the row).
+template <int R>
+__device__ __forceinline__ void apply_pow_row(float2* v, const float2* __restrict__ row)
+{
+    if constexpr (R > 1) {
+        float2 w[R];
+        powers_from_row<R>(w, row);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], w[r]);
     }
 }
 

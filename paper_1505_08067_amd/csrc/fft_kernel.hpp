@@ -32,7 +32,7 @@
 
 namespace fb {
 
-enum : int { kSwz = 8 };
+enum : int { kSwz = 8, kStaged = 16, kTwPow = 32 };
 
 // LDS index map: padded (default) or XOR-swizzled within 16-value groups.
 template <int FL>
@@ -78,6 +78,10 @@ struct PolBlock {
     {
         return c.src + n;
     }
+    template <int N, int E, int T, int RL, int NsL, int FL>
+    __device__ static void twiddle_outputs(const KArgs&, const Ctx&, int, float2 (&)[E])
+    {
+    }
     template <int FL>
     __device__ static void store(const KArgs&, const Ctx& c, int k, float2 x)
     {
@@ -114,13 +118,66 @@ struct PolPass1 {
     {
         return c.src + (long long)n * a.n_other;
     }
-    template <int FL>
-    __device__ static void store(const KArgs& a, const Ctx& c, int k, float2 x)
+    // x * exp(-2 pi i col k / N)
+    __device__ static float2 twiddled(const KArgs& a, const Ctx& c, int k, float2 x)
     {
         const unsigned m = (c.col * (unsigned)k) & (unsigned)(a.nbig - 1);
         const float2 w = cmul(a.tw_hi[m >> a.lo_bits], a.tw_lo[m & ((1u << a.lo_bits) - 1u)]);
+        return cmul(x, w);
+    }
+    // Multiplies every output of the thread by its long twiddle.  Output
+    // (i, q) of the last stage is k = t + T*m with m = i + q*(E/RL), so
+    // exp(-2 pi i col k / N) = exp(-2 pi i col t / N) * s^m with
+    // s = exp(-2 pi i col T / N); the power variant reads s^(2^i) from the
+    // per-column table and forms s^m by products, the plain one gathers every
+    // twiddle from the hi/lo tables.
+    template <int N, int E, int T, int RL, int NsL, int FL>
+    __device__ static void twiddle_outputs(const KArgs& a, const Ctx& c, int t, float2 (&v)[E])
+    {
+        if constexpr ((FL & kTwPow) != 0) {
+            constexpr int ROW = ((E == 2 ? 1 : E == 4 ? 2 : E == 8 ? 3 : E == 16 ? 4 : 5) + 1) & ~1;
+            const unsigned m0 = (c.col * (unsigned)t) & (unsigned)(a.nbig - 1);
+            const float2 b = cmul(a.tw_hi[m0 >> a.lo_bits], a.tw_lo[m0 & ((1u << a.lo_bits) - 1u)]);
+            float2 sp[E];
+            powers_from_row<E>(sp, a.tw_col + (long long)c.col * ROW);
+#pragma unroll
+            for (int i = 0; i < E / RL; ++i)
+#pragma unroll
+                for (int q = 0; q < RL; ++q) v[i * RL + q] = cmul(v[i * RL + q], cmul(b, sp[i + q * (E / RL)]));
+        } else {
+#pragma unroll
+            for (int i = 0; i < E / RL; ++i)
+#pragma unroll
+                for (int q = 0; q < RL; ++q) v[i * RL + q] = twiddled(a, c, t + i * T + q * NsL, v[i * RL + q]);
+        }
+    }
+    template <int FL>
+    __device__ static void store(const KArgs& a, const Ctx& c, int k, float2 x)
+    {
         const long long blk = (long long)(k >> a.cw_bits) * (a.n_other << a.cw_bits);
-        gstore<FL>(c.dst + blk + (k & ((1 << a.cw_bits) - 1)), cmul(x, w));
+        gstore<FL>(c.dst + blk + (k & ((1 << a.cw_bits) - 1)), x);
+    }
+    // Contiguous store of the workgroup's outputs from LDS (natural order per
+    // column): for each block g of CW rows the C columns x CW values are one
+    // contiguous run of the workspace.
+    template <int N, int C, int FL, int LDSN, int NT>
+    __device__ static void staged_store(const KArgs& a, long long unit, const float2* lds, int tid)
+    {
+        const long long bt = unit / a.tiles;
+        const int tile = (int)(unit - bt * a.tiles);
+        float2* base = a.out + bt * a.nbig + ((long long)(tile * C) << a.cw_bits);
+        const long long gstride = a.n_other << a.cw_bits;
+        const int cwm = (1 << a.cw_bits) - 1;
+        const int blk_bits = a.cw_bits + __builtin_ctz(C);
+#pragma unroll
+        for (int m = 0; m < N * C / NT; ++m) {
+            const int e = tid + m * NT;
+            const int g = e >> blk_bits;
+            const int w = e & ((1 << blk_bits) - 1);
+            const int ff = w >> a.cw_bits;
+            const int k = (g << a.cw_bits) + (w & cwm);
+            gstore<FL>(base + g * gstride + w, lds[ff * LDSN + lds_at<FL>(k)]);
+        }
     }
     __host__ __device__ static long long units(const KArgs& a, int) { return a.batch * a.tiles; }
 };
@@ -151,6 +208,10 @@ struct PolPass2 {
     {
         return c.src + (long long)n * C;
     }
+    template <int N, int E, int T, int RL, int NsL, int FL>
+    __device__ static void twiddle_outputs(const KArgs&, const Ctx&, int, float2 (&)[E])
+    {
+    }
     template <int FL>
     __device__ static void store(const KArgs& a, const Ctx& c, int k, float2 x)
     {
@@ -162,8 +223,37 @@ struct PolPass2 {
 // --------------------------------------------------------------- the stages
 // v holds the stage-0 inputs x[t + i*T + r*N/R0] on entry and the outputs
 // X[t + i*T + q*Ns_last] on exit.
+// Twiddle rows from the factorised table in LDS (persistent kernels).
+template <class S, int s, int R>
+__device__ __forceinline__ void apply_lds_tw(float2* v, const float2* Ltw, int k)
+{
+    const float4* A;
+    if constexpr (S::f_full(s)) {
+        A = reinterpret_cast<const float4*>(Ltw + S::ftw_off(s) + k * R);
+#pragma unroll
+        for (int r = 0; r < R; r += 2) {
+            const float4 w = A[r / 2];
+            if (r > 0) v[r] = cmul(v[r], make_float2(w.x, w.y));
+            v[r + 1] = cmul(v[r + 1], make_float2(w.z, w.w));
+        }
+    } else {
+        constexpr int M = S::fm(s);
+        constexpr int Q = S::fq(s);
+        const int q = k / M, p = k % M;
+        A = reinterpret_cast<const float4*>(Ltw + S::ftw_off(s) + q * R);
+        const float4* B = reinterpret_cast<const float4*>(Ltw + S::ftw_off(s) + Q * R + p * R);
+#pragma unroll
+        for (int r = 0; r < R; r += 2) {
+            const float4 wa = A[r / 2], wb = B[r / 2];
+            if (r > 0) v[r] = cmul(v[r], cmul(make_float2(wa.x, wa.y), make_float2(wb.x, wb.y)));
+            v[r + 1] = cmul(v[r + 1], cmul(make_float2(wa.z, wa.w), make_float2(wb.z, wb.w)));
+        }
+    }
+}
+
 template <int N, int E, class S, int FL>
-__device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const float2* __restrict__ tw, int t)
+__device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const float2* __restrict__ tw,
+                                           const float2* Ltw, int t)
 {
     constexpr int T = N / E;
     constexpr int NST = S::count;
@@ -179,7 +269,12 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const floa
 #pragma unroll
             for (int i = 0; i < E / R; ++i) {
                 const int k = (t + i * T) % Ns;
-                apply_row<R>(&v[i * R], tw + S::tw_off(s) + k * R);
+                if constexpr ((FL & kPipe) != 0)
+                    apply_lds_tw<S, s, R>(&v[i * R], Ltw, k);
+                else if constexpr ((FL & kTwPow) != 0)
+                    apply_pow_row<R>(&v[i * R], tw + S::ptw_off(s) + k * S::p_row(s));
+                else
+                    apply_row<R>(&v[i * R], tw + S::tw_off(s) + k * R);
             }
         }
 #pragma unroll
@@ -198,8 +293,36 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const floa
     });
 }
 
+// LDS layout of a kernel: C exchange buffers of lds_stride values, then (for
+// persistent variants) the factorised twiddle table, 16-byte aligned.
+template <int N, int C, class S, int FL>
+__host__ __device__ constexpr int k_tw_base()
+{
+    return (S::count > 1 ? ((C * lds_stride<N, FL>() + 1) & ~1) : 0);
+}
+template <int N, int C, class S, int FL>
+__host__ __device__ constexpr int k_lds_elems()
+{
+    const int tw = (FL & kPipe) != 0 ? S::ftw_size() : 0;
+    const int n = k_tw_base<N, C, S, FL>() + tw;
+    return n > 0 ? n : 1;
+}
+
+// Waves per SIMD the LDS footprint allows (160 KB per CU, 4 SIMDs); the
+// persistent variants ask the register allocator for that occupancy.
+template <int N, int E, int C, class S, int FL>
+__host__ __device__ constexpr int k_min_waves()
+{
+    if ((FL & kPipe) == 0) return 1;
+    const int lds = k_lds_elems<N, C, S, FL>() * 8;
+    const int wgs = 163840 / lds;
+    const int waves = wgs * (((N / E) * C + 63) / 64) / 4;
+    return waves < 1 ? 1 : waves > 8 ? 8 : waves;
+}
+
 template <int N, int E, int C, class S, class P, int FL>
-__global__ void __launch_bounds__((N / E) * C) k_fft(KArgs a)
+__global__ void __launch_bounds__((N / E) * C) __attribute__((amdgpu_waves_per_eu(k_min_waves<N, E, C, S, FL>())))
+k_fft(KArgs a)
 {
     constexpr int T = N / E;
     constexpr int NST = S::count;
@@ -208,37 +331,67 @@ __global__ void __launch_bounds__((N / E) * C) k_fft(KArgs a)
     constexpr int RL = S::r(NST - 1);
     constexpr int NsL = S::ns(NST - 1);
     static_assert(S::n() == N, "schedule does not multiply to N");
-    __shared__ float2 lds[NST > 1 ? C * LDSN : 1];
+    constexpr int TWB = k_tw_base<N, C, S, FL>();
+    __shared__ __attribute__((aligned(16))) float2 lds[k_lds_elems<N, C, S, FL>()];
 
     const int tid = threadIdx.x;
     const int f = P::f_fast ? tid % C : tid / T;
     const int t = P::f_fast ? tid / C : tid % T;
     float2* L = lds + (NST > 1 ? f * LDSN : 0);
+    float2* Ltw = lds + TWB;
 
+    // The backward transform is conj(forward(conj(x))): the conjugations are
+    // skipped by a uniform branch in the forward direction.
+    const bool bwd = a.sg < 0.f;
     auto load = [&](float2(&v)[E], long long unit) {
         const auto cx = P::template ctx<N, C>(a, unit, f);
+        if (cx.act) {
 #pragma unroll
-        for (int i = 0; i < E / R0; ++i)
+            for (int i = 0; i < E / R0; ++i)
 #pragma unroll
-            for (int r = 0; r < R0; ++r) {
-                const int n = t + i * T + r * (N / R0);
-                float2 x = cx.act ? gload<FL>(P::template in_at<C>(a, cx, n)) : make_float2(0.f, 0.f);
-                if constexpr (P::conj_in) x.y *= a.sg;
-                v[i * R0 + r] = x;
+                for (int r = 0; r < R0; ++r)
+                    v[i * R0 + r] = gload<FL>(P::template in_at<C>(a, cx, t + i * T + r * (N / R0)));
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = make_float2(0.f, 0.f);
+        }
+        if constexpr (P::conj_in) {
+            if (bwd) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
             }
+        }
     };
     auto finish = [&](float2(&v)[E], long long unit) {
-        run_stages<N, E, S, FL>(v, L, a.tw, t);
+        run_stages<N, E, S, FL>(v, L, a.tw, Ltw, t);
         const auto cx = P::template ctx<N, C>(a, unit, f);
-        if (cx.act) {
+        P::template twiddle_outputs<N, E, T, RL, NsL, FL>(a, cx, t, v);
+        if constexpr ((FL & kStaged) != 0) {
+            // outputs (twiddled) to LDS in natural order, then contiguous stores
+            static_assert(P::kind == kKindPass1, "staged store is a pass-1 variant");
+            __syncthreads();
 #pragma unroll
             for (int i = 0; i < E / RL; ++i)
 #pragma unroll
                 for (int q = 0; q < RL; ++q) {
-                    float2 x = v[i * RL + q];
-                    if constexpr (P::conj_out) x.y *= a.sg;
-                    P::template store<FL>(a, cx, t + i * T + q * NsL, x);
+                    const int k = t + i * T + q * NsL;
+                    L[lds_at<FL>(k)] = v[i * RL + q];
                 }
+            __syncthreads();
+            P::template staged_store<N, C, FL, LDSN, T * C>(a, unit, lds, tid);
+        } else {
+            if constexpr (P::conj_out) {
+                if (bwd) {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
+                }
+            }
+            if (cx.act) {
+#pragma unroll
+                for (int i = 0; i < E / RL; ++i)
+#pragma unroll
+                    for (int q = 0; q < RL; ++q) P::template store<FL>(a, cx, t + i * T + q * NsL, v[i * RL + q]);
+            }
         }
     };
 
@@ -250,8 +403,20 @@ __global__ void __launch_bounds__((N / E) * C) k_fft(KArgs a)
         const long long units = P::units(a, C);
         long long u = blockIdx.x;
         if (u >= units) return;
+        constexpr int TWN = S::ftw_size();
+        float2 twv[(TWN + T * C - 1) / (T * C) > 0 ? (TWN + T * C - 1) / (T * C) : 1];
+#pragma unroll
+        for (int m = 0; m * T * C < TWN; ++m) {
+            const int i = tid + m * T * C;
+            if (i < TWN) twv[m] = a.tw[i];
+        }
         float2 nx[E];
         load(nx, u);
+#pragma unroll
+        for (int m = 0; m * T * C < TWN; ++m) {
+            const int i = tid + m * T * C;
+            if (i < TWN) Ltw[i] = twv[m];
+        }
         for (;;) {
             float2 v[E];
 #pragma unroll
@@ -295,9 +460,9 @@ constexpr KEntry make_entry(bool is_default, const char* name)
     k.flags = FL;
     k.nr = S::count;
     for (int i = 0; i < S::count && i < 8; ++i) k.radix[i] = S::r(i);
-    k.tw_size = S::tw_size();
+    k.tw_size = (FL & kPipe) != 0 ? S::ftw_size() : (FL & kTwPow) != 0 ? S::ptw_size() : S::tw_size();
     k.threads = (N / E) * C;
-    k.lds = S::count > 1 ? (size_t)C * lds_stride<N, FL>() * sizeof(float2) : sizeof(float2);
+    k.lds = (size_t)k_lds_elems<N, C, S, FL>() * sizeof(float2);
     k.is_default = is_default;
     k.launch = &launch_fft<N, E, C, S, P, FL>;
     k.occupancy = &occupancy_fft<N, E, C, S, P, FL>;

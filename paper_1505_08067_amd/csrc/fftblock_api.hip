@@ -37,7 +37,7 @@ struct fft_plan_s {
     long long grid1 = 0, grid2 = 0;
     float2* tw = nullptr;           // one allocation holding every table
     size_t tw_bytes = 0;
-    size_t off_s1 = 0, off_s2 = 0, off_hi = 0, off_lo = 0;  // in complex entries
+    size_t off_s1 = 0, off_s2 = 0, off_hi = 0, off_lo = 0, off_col = 0;  // in complex entries
     float2* work = nullptr;
     size_t work_bytes = 0;
 };
@@ -181,6 +181,60 @@ void fill_stage_table(const int* radix, int nr, float2* dst)
     }
 }
 
+// The same twiddles in the factorised layout of persistent kernels: a stage
+// with Ns <= 16 keeps full rows; a larger stage stores A[q][r] =
+// exp(-2 pi i r q / (Q R)), q < Q, then B[p][r] = exp(-2 pi i r p / (Ns R)),
+// p < M, where Q is the largest power of two with Q*Q <= Ns and M = Ns / Q.
+void fill_stage_table_factored(const int* radix, int nr, float2* dst)
+{
+    size_t at = 0;
+    long long ns = radix[0];
+    for (int s = 1; s < nr; ++s) {
+        const int R = radix[s];
+        if (ns <= 16) {
+            for (long long k = 0; k < ns; ++k)
+                for (int r = 0; r < R; ++r) dst[at++] = root_f32((long long)r * k, ns * R);
+        } else {
+            long long Q = 1;
+            while (4 * Q * Q <= ns) Q *= 2;
+            const long long M = ns / Q;
+            for (long long q = 0; q < Q; ++q)
+                for (int r = 0; r < R; ++r) dst[at++] = root_f32((long long)r * q, Q * R);
+            for (long long p = 0; p < M; ++p)
+                for (int r = 0; r < R; ++r) dst[at++] = root_f32((long long)r * p, ns * R);
+        }
+        ns *= R;
+    }
+}
+
+// Power layout: row k of stage s holds w^(2^i), i < log2(R), for
+// w = exp(-2 pi i k / (Ns R)), padded to an even number of entries.
+void fill_stage_table_powers(const int* radix, int nr, float2* dst)
+{
+    size_t at = 0;
+    long long ns = radix[0];
+    for (int s = 1; s < nr; ++s) {
+        const int R = radix[s];
+        int lg = 0;
+        while ((1 << lg) < R) ++lg;
+        const int row = (lg + 1) & ~1;
+        for (long long k = 0; k < ns; ++k)
+            for (int i = 0; i < row; ++i)
+                dst[at++] = i < lg ? root_f32((long long)(1LL << i) * k, ns * R) : make_float2(0.f, 0.f);
+        ns *= R;
+    }
+}
+
+void fill_kernel_table(const KEntry* k, float2* dst)
+{
+    if (k->flags & FFT_VARIANT_PERSISTENT)
+        fill_stage_table_factored(k->radix, k->nr, dst);
+    else if (k->flags & FFT_VARIANT_TWIDDLE_POWERS)
+        fill_stage_table_powers(k->radix, k->nr, dst);
+    else
+        fill_stage_table(k->radix, k->nr, dst);
+}
+
 size_t env_size(const char* name, size_t dflt)
 {
     const char* v = std::getenv(name);
@@ -199,6 +253,14 @@ size_t sanitize_limit(size_t lim)
 {
     if (!is_pow2(lim) || lim < 1024 || lim > kDefaultBlockLimit) return kDefaultBlockLimit;
     return lim;
+}
+
+// Entries per row of a power table for exponents below e: log2(e), padded even.
+int col_row(int e)
+{
+    int lg = 0;
+    while ((1 << lg) < e) ++lg;
+    return (lg + 1) & ~1;
 }
 
 int log2i(int v)
@@ -325,6 +387,10 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
         off += round_up(n >> p->lo_bits, 32);
         p->off_lo = off;
         off += round_up(size_t(1) << p->lo_bits, 32);
+        if (p->k1->flags & FFT_VARIANT_TWIDDLE_POWERS) {
+            p->off_col = off;
+            off += round_up(p->n2 * (size_t)col_row(p->k1->e), 32);
+        }
         p->work_bytes = n * batch * sizeof(float2);
     }
     p->tw_bytes = off * sizeof(float2);
@@ -348,6 +414,7 @@ static KArgs make_args(const fft_plan_s* p, int pass, const float2* in, float2* 
     a.cw_bits = p->cw_bits;
     a.tw_hi = p->tw + p->off_hi;
     a.tw_lo = p->tw + p->off_lo;
+    a.tw_col = p->tw + p->off_col;
     if (pass == 1) {
         a.tw = p->tw + p->off_s1;
         a.n_other = (long long)p->n2;
@@ -451,12 +518,21 @@ fft_status_t fft_plan_create_ex(size_t n, size_t batch, int direction, const fft
             delete p;
             return FFT_ERR_OUT_OF_MEMORY;
         }
-        fill_stage_table(p->k1->radix, p->k1->nr, host + p->off_s1);
+        fill_kernel_table(p->k1, host + p->off_s1);
         if (p->path == FFT_PATH_FOURSTEP) {
-            fill_stage_table(p->k2->radix, p->k2->nr, host + p->off_s2);
+            fill_kernel_table(p->k2, host + p->off_s2);
             const long long N = (long long)n;
             for (long long a = 0; a < (N >> p->lo_bits); ++a) host[p->off_hi + a] = root_f32(a << p->lo_bits, N);
             for (long long b = 0; b < (1LL << p->lo_bits); ++b) host[p->off_lo + b] = root_f32(b, N);
+            if (p->off_col) {
+                // row col: exp(-2 pi i col T 2^i / N), i < log2(E), T = N1 / E threads per column
+                const int row = col_row(p->k1->e);
+                const long long T = (long long)p->n1 / p->k1->e;
+                for (long long c = 0; c < (long long)p->n2; ++c)
+                    for (int i = 0; i < row; ++i)
+                        host[p->off_col + c * row + i] =
+                            (1 << i) < p->k1->e ? root_f32((c * T * (1LL << i)) % N, N) : make_float2(0.f, 0.f);
+            }
         }
         e = hipMalloc((void**)&p->tw, p->tw_bytes);
         if (e == hipSuccess) e = hipMemcpy(p->tw, host, p->tw_bytes, hipMemcpyHostToDevice);

@@ -22,6 +22,7 @@ struct KArgs {
     int lo_bits;           // long twiddle split m = hi * 2^lo_bits + lo
     const float2* tw_hi;   // exp(-2 pi i hi 2^lo_bits / N)
     const float2* tw_lo;   // exp(-2 pi i lo / N)
+    const float2* tw_col;  // pass 1, power variant: row col holds exp(-2 pi i col T 2^i / N)
     float sg;              // +1 forward, -1 backward (conjugation on entry and exit)
 };
 

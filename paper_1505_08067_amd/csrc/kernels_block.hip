@@ -15,45 +15,69 @@ namespace fb {
                                                                 "],v" #FL ">")
 
 static const KEntry kBlock[] = {
-    // defaults
-    FB_BLK(true, 0, 2, 2, 256, 2),
-    FB_BLK(true, 0, 4, 4, 256, 4),
-    FB_BLK(true, 0, 8, 8, 256, 8),
-    FB_BLK(true, 0, 16, 16, 256, 16),
-    FB_BLK(true, 0, 32, 16, 128, 16, 2),
-    FB_BLK(true, 0, 64, 16, 64, 16, 4),
-    FB_BLK(true, 0, 128, 16, 32, 16, 8),
-    FB_BLK(true, 0, 256, 16, 16, 16, 16),
-    FB_BLK(true, 0, 512, 16, 8, 16, 16, 2),
-    FB_BLK(true, 0, 1024, 16, 4, 16, 16, 4),
-    FB_BLK(true, 0, 2048, 16, 2, 16, 16, 8),
-    FB_BLK(true, 0, 4096, 16, 1, 16, 16, 16),
-    FB_BLK(true, 0, 8192, 32, 1, 32, 16, 16),
-    FB_BLK(true, 0, 16384, 16, 1, 16, 16, 16, 4),
-    // variants of the main sizes: non-temporal access (1|2), persistent prefetch (4), swizzled LDS (8)
+    // planner defaults: non-temporal data access + power-row twiddles (35)
+    FB_BLK(true, 3, 2, 2, 256, 2),
+    FB_BLK(true, 3, 4, 4, 256, 4),
+    FB_BLK(true, 3, 8, 8, 256, 8),
+    FB_BLK(true, 3, 16, 16, 256, 16),
+    FB_BLK(true, 35, 32, 16, 128, 16, 2),
+    FB_BLK(true, 35, 64, 16, 64, 16, 4),
+    FB_BLK(true, 35, 128, 16, 32, 16, 8),
+    FB_BLK(true, 35, 256, 16, 16, 16, 16),
+    FB_BLK(true, 35, 512, 16, 8, 16, 16, 2),
+    FB_BLK(true, 35, 1024, 8, 2, 8, 8, 4, 4),
+    FB_BLK(true, 35, 2048, 16, 2, 16, 16, 8),
+    FB_BLK(true, 35, 4096, 16, 1, 16, 16, 16),
+    FB_BLK(true, 35, 8192, 16, 1, 8, 8, 8, 16),
+    FB_BLK(true, 35, 16384, 16, 1, 16, 16, 16, 4),
+    // plain variants (full twiddle rows, ordinary loads/stores)
+    FB_BLK(false, 0, 2, 2, 256, 2),
+    FB_BLK(false, 0, 16, 16, 256, 16),
+    FB_BLK(false, 0, 32, 16, 128, 16, 2),
+    FB_BLK(false, 0, 64, 16, 64, 16, 4),
+    FB_BLK(false, 0, 128, 16, 32, 16, 8),
+    FB_BLK(false, 0, 256, 16, 16, 16, 16),
+    FB_BLK(false, 0, 512, 16, 8, 16, 16, 2),
+    FB_BLK(false, 0, 1024, 16, 4, 16, 16, 4),
+    FB_BLK(false, 0, 2048, 16, 2, 16, 16, 8),
+    FB_BLK(false, 0, 4096, 16, 1, 16, 16, 16),
+    FB_BLK(false, 0, 8192, 32, 1, 32, 16, 16),
+    FB_BLK(false, 0, 16384, 16, 1, 16, 16, 16, 4),
+    // other variants of the main sizes: non-temporal (1|2), persistent with
+    // LDS twiddles (4), swizzled LDS (8), power-row twiddles (32)
     FB_BLK(false, 3, 1024, 16, 4, 16, 16, 4),
-    FB_BLK(false, 7, 1024, 16, 4, 16, 16, 4),
+    FB_BLK(false, 35, 1024, 16, 4, 16, 16, 4),
+    FB_BLK(false, 0, 1024, 8, 2, 8, 8, 4, 4),
+    FB_BLK(false, 3, 1024, 8, 2, 8, 8, 4, 4),
+    FB_BLK(false, 32, 1024, 8, 2, 8, 8, 4, 4),
+    FB_BLK(false, 7, 1024, 8, 2, 8, 8, 4, 4),
+    FB_BLK(false, 43, 1024, 8, 2, 8, 8, 4, 4),
     FB_BLK(false, 3, 4096, 16, 1, 16, 16, 16),
-    FB_BLK(false, 11, 4096, 16, 1, 16, 16, 16),
-    FB_BLK(false, 4, 4096, 16, 1, 16, 16, 16),
+    FB_BLK(false, 32, 4096, 16, 1, 16, 16, 16),
+    FB_BLK(false, 43, 4096, 16, 1, 16, 16, 16),
     FB_BLK(false, 7, 4096, 16, 1, 16, 16, 16),
-    FB_BLK(false, 15, 4096, 16, 1, 16, 16, 16),
+    FB_BLK(false, 0, 4096, 8, 1, 8, 8, 8, 8),
+    FB_BLK(false, 35, 4096, 8, 1, 8, 8, 8, 8),
+    FB_BLK(false, 7, 4096, 8, 1, 8, 8, 8, 8),
     FB_BLK(false, 3, 8192, 32, 1, 32, 16, 16),
-    FB_BLK(false, 7, 8192, 32, 1, 32, 16, 16),
+    FB_BLK(false, 35, 8192, 32, 1, 32, 16, 16),
+    FB_BLK(false, 0, 8192, 16, 1, 8, 8, 8, 16),
+    FB_BLK(false, 43, 8192, 16, 1, 8, 8, 8, 16),
     FB_BLK(false, 3, 16384, 16, 1, 16, 16, 16, 4),
+    FB_BLK(false, 7, 16384, 16, 1, 16, 16, 16, 4),
     // alternative schedules (radix search)
     FB_BLK(false, 0, 512, 8, 4, 8, 8, 8),
+    FB_BLK(false, 35, 512, 8, 4, 8, 8, 8),
     FB_BLK(false, 0, 1024, 16, 4, 4, 16, 16),
     FB_BLK(false, 0, 1024, 8, 2, 4, 8, 8, 4),
-    FB_BLK(false, 0, 1024, 8, 2, 8, 8, 4, 4),
+    FB_BLK(false, 35, 1024, 8, 2, 4, 8, 8, 4),
     FB_BLK(false, 0, 1024, 8, 2, 8, 8, 8, 2),
-    FB_BLK(false, 0, 4096, 8, 1, 8, 8, 8, 8),
-    FB_BLK(false, 3, 4096, 8, 1, 8, 8, 8, 8),
+    FB_BLK(false, 35, 1024, 8, 2, 8, 8, 8, 2),
     FB_BLK(false, 0, 4096, 16, 1, 4, 16, 16, 4),
     FB_BLK(false, 0, 8192, 16, 1, 16, 16, 16, 2),
-    FB_BLK(false, 3, 8192, 16, 1, 16, 16, 16, 2),
     FB_BLK(false, 0, 8192, 32, 1, 16, 16, 32),
     FB_BLK(false, 0, 16384, 32, 1, 32, 32, 16),
+    FB_BLK(false, 35, 16384, 32, 1, 32, 32, 16),
 };
 
 const KEntry* block_entries(int* count)

@@ -23,29 +23,37 @@ namespace fb {
     make_entry<N, E, C, Sched<__VA_ARGS__>, PolPass2, FL>(DEF, "fourstep_pass2<" #N ",C" #C ",[" #__VA_ARGS__ "],v" #FL ">")
 
 static const KEntry kPass[] = {
-    FB_P1(true, 0, 32, 16, 16, 16, 2),
-    FB_P1(true, 0, 64, 16, 16, 16, 4),
-    FB_P1(true, 0, 128, 16, 16, 16, 8),
-    FB_P1(true, 0, 256, 16, 16, 16, 16),
-    FB_P1(true, 0, 512, 16, 16, 16, 16, 2),
-    FB_P1(true, 0, 1024, 16, 16, 16, 16, 4),
-    FB_P1(true, 0, 2048, 16, 8, 16, 16, 8),
+    // planner defaults.  Pass 1: non-temporal loads, power-row twiddles
+    // (stage and long), outputs staged through LDS for contiguous stores
+    // (49).  Pass 2: non-temporal loads, power-row twiddles (33).
+    FB_P1(true, 49, 32, 16, 16, 16, 2),
+    FB_P1(true, 49, 64, 16, 16, 16, 4),
+    FB_P1(true, 49, 128, 16, 16, 16, 8),
+    FB_P1(true, 49, 256, 16, 16, 16, 16),
+    FB_P1(true, 49, 512, 16, 16, 16, 16, 2),
+    FB_P1(true, 49, 1024, 16, 16, 16, 16, 4),
+    FB_P1(true, 49, 2048, 16, 8, 16, 16, 8),
+    FB_P2(true, 33, 32, 16, 16, 16, 2),
+    FB_P2(true, 33, 64, 16, 16, 16, 4),
+    FB_P2(true, 33, 128, 16, 16, 16, 8),
+    FB_P2(true, 33, 256, 16, 16, 16, 16),
+    FB_P2(true, 33, 512, 16, 16, 16, 16, 2),
+    FB_P2(true, 33, 1024, 16, 8, 16, 16, 4),
+    FB_P2(true, 33, 2048, 16, 8, 16, 16, 8),
+    // plain and other variants (1: nt load, 16: staged store, 32: power twiddles)
+    FB_P1(false, 0, 1024, 16, 16, 16, 16, 4),
     FB_P1(false, 0, 1024, 16, 8, 16, 16, 4),
     FB_P1(false, 1, 1024, 16, 16, 16, 16, 4),
-    FB_P1(false, 1, 1024, 16, 8, 16, 16, 4),
-    FB_P1(false, 5, 1024, 16, 8, 16, 16, 4),
-    FB_P2(true, 0, 32, 16, 16, 16, 2),
-    FB_P2(true, 0, 64, 16, 16, 16, 4),
-    FB_P2(true, 0, 128, 16, 16, 16, 8),
-    FB_P2(true, 0, 256, 16, 16, 16, 16),
-    FB_P2(true, 0, 512, 16, 16, 16, 16, 2),
-    FB_P2(true, 0, 1024, 16, 16, 16, 16, 4),
-    FB_P2(true, 0, 2048, 16, 8, 16, 16, 8),
+    FB_P1(false, 17, 1024, 16, 16, 16, 16, 4),
+    FB_P1(false, 33, 1024, 16, 16, 16, 16, 4),
+    FB_P1(false, 48, 1024, 16, 16, 16, 16, 4),
+    FB_P1(false, 49, 1024, 16, 8, 16, 16, 4),
+    FB_P1(false, 0, 2048, 16, 8, 16, 16, 8),
+    FB_P2(false, 0, 1024, 16, 16, 16, 16, 4),
     FB_P2(false, 0, 1024, 16, 8, 16, 16, 4),
-    FB_P2(false, 1, 1024, 16, 16, 16, 16, 4),
-    FB_P2(false, 3, 1024, 16, 16, 16, 16, 4),
     FB_P2(false, 1, 1024, 16, 8, 16, 16, 4),
-    FB_P2(false, 5, 1024, 16, 8, 16, 16, 4),
+    FB_P2(false, 33, 1024, 16, 16, 16, 16, 4),
+    FB_P2(false, 0, 2048, 16, 8, 16, 16, 8),
 };
 
 const KEntry* pass_entries(int* count)

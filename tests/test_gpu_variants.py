@@ -57,12 +57,17 @@ def test_block_variant(k):
 
 
 def _pass_combos():
+    # every pass-1 kernel with a plain pass 2 of each workspace width, and
+    # every pass-2 kernel with the default pass 1
     ks = fb.kernels()
     p1 = [k for k in ks if k["kind"] == "pass1" and k["n"] == 1024]
     p2 = [k for k in ks if k["kind"] == "pass2" and k["n"] == 1024]
-    combos = []
-    for a in p1:
-        for b in p2:
+    plain2 = [k for k in p2 if k["flags"] == 0]
+    default1 = [k for k in p1 if k["is_default"]]
+    combos, seen = [], set()
+    for a, b in [(a, b) for a in p1 for b in plain2] + [(a, b) for a in default1 for b in p2]:
+        if (a["name"], b["name"]) not in seen:
+            seen.add((a["name"], b["name"]))
             combos.append(pytest.param(a, b, id=f"{a['name']}+{b['name']}"))
     return combos
 
