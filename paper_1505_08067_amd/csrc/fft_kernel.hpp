@@ -45,10 +45,23 @@ __device__ __forceinline__ int lds_at(int i)
     }
 }
 
-template <int N, int FL>
+// Distance between the LDS buffers of the C transforms of a workgroup.
+// Lanes that share a 16-lane group differ in their transform index f and in
+// their position t: with f-fast lanes (C values of f, 16/C of t) the stride
+// is made congruent to 16/C modulo 16, with t-fast lanes and T < 16 threads
+// per transform it is made congruent to T, so every such group hits 16
+// distinct 8-byte bank pairs.
+template <int N, int FL, bool FFAST, int C, int T>
 __host__ __device__ constexpr int lds_stride()
 {
-    return (FL & kSwz) != 0 ? N : lds_pad(N) + 1;
+    if constexpr ((FL & kSwz) != 0) {
+        return N;
+    } else {
+        const int want = FFAST ? (C < 16 ? 16 / C : 1) : (T < 16 ? T : 1);
+        int s = lds_pad(N);
+        while ((s & 15) != (want & 15)) ++s;
+        return s;
+    }
 }
 
 // ----------------------------------------------------------------- policies
@@ -295,44 +308,45 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const floa
 
 // LDS layout of a kernel: C exchange buffers of lds_stride values, then (for
 // persistent variants) the factorised twiddle table, 16-byte aligned.
-template <int N, int C, class S, int FL>
+template <int N, int C, class S, int FL, bool FFAST, int T>
 __host__ __device__ constexpr int k_tw_base()
 {
-    return (S::count > 1 ? ((C * lds_stride<N, FL>() + 1) & ~1) : 0);
+    return (S::count > 1 ? ((C * lds_stride<N, FL, FFAST, C, T>() + 1) & ~1) : 0);
 }
-template <int N, int C, class S, int FL>
+template <int N, int C, class S, int FL, bool FFAST, int T>
 __host__ __device__ constexpr int k_lds_elems()
 {
     const int tw = (FL & kPipe) != 0 ? S::ftw_size() : 0;
-    const int n = k_tw_base<N, C, S, FL>() + tw;
+    const int n = k_tw_base<N, C, S, FL, FFAST, T>() + tw;
     return n > 0 ? n : 1;
 }
 
 // Waves per SIMD the LDS footprint allows (160 KB per CU, 4 SIMDs); the
 // persistent variants ask the register allocator for that occupancy.
-template <int N, int E, int C, class S, int FL>
+template <int N, int E, int C, class S, int FL, bool FFAST>
 __host__ __device__ constexpr int k_min_waves()
 {
     if ((FL & kPipe) == 0) return 1;
-    const int lds = k_lds_elems<N, C, S, FL>() * 8;
+    const int lds = k_lds_elems<N, C, S, FL, FFAST, N / E>() * 8;
     const int wgs = 163840 / lds;
     const int waves = wgs * (((N / E) * C + 63) / 64) / 4;
     return waves < 1 ? 1 : waves > 8 ? 8 : waves;
 }
 
 template <int N, int E, int C, class S, class P, int FL>
-__global__ void __launch_bounds__((N / E) * C) __attribute__((amdgpu_waves_per_eu(k_min_waves<N, E, C, S, FL>())))
+__global__ void __launch_bounds__((N / E) * C)
+__attribute__((amdgpu_waves_per_eu(k_min_waves<N, E, C, S, FL, P::f_fast>())))
 k_fft(KArgs a)
 {
     constexpr int T = N / E;
     constexpr int NST = S::count;
-    constexpr int LDSN = lds_stride<N, FL>();
+    constexpr int LDSN = lds_stride<N, FL, P::f_fast, C, T>();
     constexpr int R0 = S::r(0);
     constexpr int RL = S::r(NST - 1);
     constexpr int NsL = S::ns(NST - 1);
     static_assert(S::n() == N, "schedule does not multiply to N");
-    constexpr int TWB = k_tw_base<N, C, S, FL>();
-    __shared__ __attribute__((aligned(16))) float2 lds[k_lds_elems<N, C, S, FL>()];
+    constexpr int TWB = k_tw_base<N, C, S, FL, P::f_fast, T>();
+    __shared__ __attribute__((aligned(16))) float2 lds[k_lds_elems<N, C, S, FL, P::f_fast, T>()];
 
     const int tid = threadIdx.x;
     const int f = P::f_fast ? tid % C : tid / T;
@@ -462,7 +476,7 @@ constexpr KEntry make_entry(bool is_default, const char* name)
     for (int i = 0; i < S::count && i < 8; ++i) k.radix[i] = S::r(i);
     k.tw_size = (FL & kPipe) != 0 ? S::ftw_size() : (FL & kTwPow) != 0 ? S::ptw_size() : S::tw_size();
     k.threads = (N / E) * C;
-    k.lds = (size_t)k_lds_elems<N, C, S, FL>() * sizeof(float2);
+    k.lds = (size_t)k_lds_elems<N, C, S, FL, P::f_fast, N / E>() * sizeof(float2);
     k.is_default = is_default;
     k.launch = &launch_fft<N, E, C, S, P, FL>;
     k.occupancy = &occupancy_fft<N, E, C, S, P, FL>;

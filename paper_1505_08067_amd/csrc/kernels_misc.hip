@@ -9,6 +9,8 @@
 // Copy probe (the analogue of the paper's CPU-to-iGPU memory benchmark):
 // 16-byte vector loads and stores, grid-stride, used to measure the practical
 // HBM bandwidth next to the 8 TB/s specification.
+#include <cstdint>
+
 #include "internal.hpp"
 
 namespace fb {
@@ -52,6 +54,44 @@ k_transpose(const float2* __restrict__ in, float2* __restrict__ out, long long r
     }
 }
 
+// Even row and column counts with 16-byte aligned buffers: each lane moves
+// two complex values (16 bytes) per access on both sides; tiles hanging over
+// the matrix edge are guarded per pair (pairs never straddle the edge since
+// both counts are even).
+__global__ void __launch_bounds__(kTransposeThreads)
+k_transpose16(const float2* __restrict__ in, float2* __restrict__ out, long long rows, long long cols,
+              long long tiles_r, long long tiles_c)
+{
+    __shared__ float2 tile[kTile][kTile + 1];
+    const long long blk = blockIdx.x;
+    const long long per_mat = tiles_r * tiles_c;
+    const long long b = blk / per_mat;
+    const long long rem = blk - b * per_mat;
+    const long long tr = rem / tiles_c;
+    const long long tc = rem - tr * tiles_c;
+    const long long r0 = tr * kTile, c0 = tc * kTile;
+    const int tx = threadIdx.x % (kTile / 2);
+    const int ty = threadIdx.x / (kTile / 2);
+    constexpr int step = kTransposeThreads / (kTile / 2);
+    const float2* __restrict__ src = in + b * rows * cols;
+    float2* __restrict__ dst = out + b * rows * cols;
+    const bool full = (r0 + kTile <= rows) && (c0 + kTile <= cols);
+    for (int i = ty; i < kTile; i += step) {
+        if (full || (r0 + i < rows && c0 + 2 * tx < cols)) {
+            const float4 v = *reinterpret_cast<const float4*>(src + (r0 + i) * cols + c0 + 2 * tx);
+            tile[i][2 * tx] = make_float2(v.x, v.y);
+            tile[i][2 * tx + 1] = make_float2(v.z, v.w);
+        }
+    }
+    __syncthreads();
+    for (int i = ty; i < kTile; i += step) {
+        if (full || (c0 + i < cols && r0 + 2 * tx < rows)) {
+            const float2 a = tile[2 * tx][i], c = tile[2 * tx + 1][i];
+            *reinterpret_cast<float4*>(dst + (c0 + i) * rows + r0 + 2 * tx) = make_float4(a.x, a.y, c.x, c.y);
+        }
+    }
+}
+
 hipError_t launch_transpose(const float2* in, float2* out, long long rows, long long cols, long long batch,
                             hipStream_t st)
 {
@@ -59,8 +99,13 @@ hipError_t launch_transpose(const float2* in, float2* out, long long rows, long 
     const long long tc = (cols + kTile - 1) / kTile;
     const long long grid = tr * tc * batch;
     if (grid <= 0 || grid > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_transpose, dim3((unsigned)grid), dim3(kTransposeThreads), 0, st, in, out, rows, cols, tr,
-                       tc);
+    const bool vec = (rows % 2 == 0) && (cols % 2 == 0) && ((uintptr_t)in % 16 == 0) && ((uintptr_t)out % 16 == 0);
+    if (vec)
+        hipLaunchKernelGGL(k_transpose16, dim3((unsigned)grid), dim3(kTransposeThreads), 0, st, in, out, rows, cols,
+                           tr, tc);
+    else
+        hipLaunchKernelGGL(k_transpose, dim3((unsigned)grid), dim3(kTransposeThreads), 0, st, in, out, rows, cols,
+                           tr, tc);
     return hipGetLastError();
 }
 

@@ -167,7 +167,7 @@ def test_deterministic_repeat():
 
 
 # ---------------------------------------------------------------- transpose
-@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 100, 37), (1, 64, 64), (2, 65, 129), (1, 4096, 8192)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 100, 37), (1, 64, 64), (2, 65, 129), (2, 66, 130), (3, 2, 200), (1, 4096, 8192)])
 def test_transpose_bit_exact(shape):
     say(f"case: transpose {shape}")
     rng = np.random.default_rng(14)
