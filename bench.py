@@ -46,9 +46,50 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle time for the CPU baseline")
     p.add_argument("--no-extras", action="store_true", help="skip copy probe and SAR chain timing")
-    p.add_argument("--traffic", default=None,
-                   help="JSON file with measured HBM bytes per launch of the dominant kernel")
+    p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.md"),
+                   help="rocprofv3 traffic summary (measured HBM bytes per launch per kernel)")
+    p.add_argument("--calibrate", action="store_true",
+                   help="also run the copy kernel on 256 MiB three times (counter calibration)")
     return p.parse_args()
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the kernel sources and the C header (what the traffic figures depend on)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1505_08067_amd", "csrc", "*.hip")) +
+                   glob.glob(os.path.join(ROOT, "paper_1505_08067_amd", "csrc", "*.hpp")) +
+                   [os.path.join(ROOT, "include", "fftblock.h")])
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(path: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the traffic summary, or None.
+
+    The summary lists `| kernel | ... | bytes_per_launch |` rows and a
+    `source_hash:` line; the figure is used only when the kernel sources still
+    hash to that value (a changed kernel makes the counters stale).
+    """
+    if not path or not os.path.exists(path):
+        return None
+    rows, src = {}, None
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("source_hash:"):
+                src = line.split(":", 1)[1].strip()
+            elif line.startswith("|") and not line.startswith("|-"):
+                cells = [c.strip() for c in line.strip("|").split("|")]
+                if len(cells) >= 2 and cells[-1].replace(".", "", 1).isdigit():
+                    rows[cells[0]] = float(cells[-1])
+    if src != kernel_source_hash():
+        return None
+    return rows.get(kernel)
 
 
 def flops(n, batch):
@@ -162,10 +203,7 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     dom_avg_ms = kernels[dom]["total_ms"] / kernels[dom]["launches_per_step"]
     achieved = kernels[dom]["bytes_per_launch"] / (dom_avg_ms * 1e-3) / 1e9
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        with open(args.traffic) as fh:
-            traffic = json.load(fh).get(dom)
+    traffic = measured_traffic(args.traffic, dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic}
     log("per-kernel:", json.dumps(breakdown))
@@ -173,6 +211,14 @@ def main():
     extras = {}
     if not args.no_extras:
         extras = run_extras(torch, fb, inputs, stream)
+    if args.calibrate:
+        src = torch.empty((1 << 28) // 8, dtype=torch.complex64, device="cuda")
+        dst = torch.empty_like(src)
+        src.zero_()
+        for _ in range(3):
+            fb.copy_(dst, src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ------------------------------------------------------- CPU baseline
     cpu = None
@@ -200,6 +246,7 @@ def main():
             "flops_per_step": fl_step,
             "hbm_bytes_per_step": int(sum(16.0 * n * b for _, _, _, (n, b) in launches)),
             "device": info["arch"],
+            "kernel_source_hash": kernel_source_hash(),
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
