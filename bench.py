@@ -320,8 +320,73 @@ def run_extras(torch, fb, inputs, stream):
     out["sar_chain"] = sar
     for p in (rf, af, ab, rb):
         p.close()
+    del x, t1, t2, t3
     log("SAR", json.dumps(sar))
+    out["ragged"] = run_ragged(torch, fb, inputs, stream)
     return out
+
+
+def run_ragged(torch, fb, inputs, stream):
+    """The ragged mix: 15 lengths with an equal share of about 2^28 points.
+
+    Each length is autotuned first (the paper's stage model plus whole-kernel
+    validation; the fastest kernel becomes the wisdom the plans use).  Then the
+    whole mix runs as one graph launch and is compared with the plain path:
+    every length as its own batched execute, timed separately and summed.
+    """
+    sizes = inputs.ragged_sizes(3)
+    classes = [(int(n), int((sizes == n).sum())) for n in inputs.RAGGED_POW2 + inputs.RAGGED_MIXED]
+    tuned = {}
+    for n, c in classes:
+        rep = fb.autotune(n, min(c, max(1, (1 << 22) // n)))
+        tuned[n] = {"kernel": rep["chosen"], "predicted_schedule": rep["predicted"]}
+    total = sum(n * c for n, c in classes)
+    x = torch.empty(total, dtype=torch.complex64, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    x.real.uniform_(-1.0, 1.0, generator=gen)
+    x.imag.uniform_(-1.0, 1.0, generator=gen)
+    y = torch.empty_like(x)
+    sh = stream.cuda_stream
+
+    def timed(fn, reps=10):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    t_plain, at = 0.0, 0
+    per_class = {}
+    for n, c in classes:
+        with fb.Plan(n, c, fb.FORWARD) as p:
+            xi, yi = x[at:at + n * c], y[at:at + n * c]
+            t = timed(lambda: p.execute_ptr(xi.data_ptr(), yi.data_ptr(), sh))
+        per_class[n] = round(t * 1e6, 2)
+        t_plain += t
+        at += n * c
+    with fb.Ragged(classes, fb.FORWARD) as r:
+        t_graph = timed(lambda: r.execute(x, out=y))
+        t_seq = timed(lambda: r.execute(x, out=y, graph=False))
+        nodes = r.describe()["graph_nodes"]
+    fl = sum(5.0 * n * math.log2(n) * c for n, c in classes)
+    res = {
+        "classes": [[n, c] for n, c in classes], "total_points": total, "graph_nodes": nodes,
+        "t_plain_sum_us": round(t_plain * 1e6, 1), "t_graph_us": round(t_graph * 1e6, 1),
+        "t_sequential_us": round(t_seq * 1e6, 1),
+        "ratio_plain_over_graph": round(t_plain / t_graph, 3),
+        "graph_GFLOPs": round(fl / t_graph / 1e9, 1),
+        "graph_GBps_one_pass": round(16.0 * total / t_graph / 1e9, 1),
+        "per_class_plain_us": per_class, "autotuned": tuned,
+    }
+    log("ragged", json.dumps({k: v for k, v in res.items() if k not in ("autotuned", "per_class_plain_us")}))
+    fb.wisdom_clear()
+    return res
 
 
 def cpu_baseline(items, fl_step, target_s):

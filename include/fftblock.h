@@ -252,6 +252,96 @@ size_t fft_block_limit(void);
  * ------------------------------------------------------------------------- */
 fft_status_t fft_copy(const void* in, void* out, size_t bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Schedule search (paper, Approach, bottom-level analysis, "FFT performance
+ * model"): radix stages as edges of a DAG over stage indices 0..log2 N, a
+ * radix-R stage starting at stage s weighted by its measured cost; under the
+ * hypothesis that a stage's cost depends only on (radix, start stage), the
+ * best mixed-radix schedule is the shortest source-to-sink path (Dijkstra).
+ * ------------------------------------------------------------------------- */
+
+/* Shortest path over the stage DAG.  costs[i * log2n + s] is the cost of
+ * radix radices[i] (a power of two) starting at stage s; a negative, NaN or
+ * infinite cost means "no such edge".  Ties go to fewer stages, then to the
+ * lexicographically larger radix list.  Writes the schedule (at most log2n
+ * radices) to sched_out, its length to n_sched_out and its cost to total_out
+ * (may be NULL).  Pure host code.  INVALID_ARG on bad arguments,
+ * UNSUPPORTED_SIZE when no path reaches the sink. */
+fft_status_t fft_schedule_search(int log2n, const int* radices, int n_radices, const double* costs,
+                                 int* sched_out, int* n_sched_out, double* total_out);
+
+/* GPU microbenchmark of one radix-R Stockham stage (R = 2, 4, 8, 16)
+ * starting at stage index start_stage on an LDS-resident power-of-two
+ * transform of length n (256..16384): nanoseconds per stage per transform,
+ * measured as the difference between repeating the stage `reps` times and
+ * not at all.  Allocates and frees its own device buffers; synchronous. */
+fft_status_t fft_stage_benchmark(size_t n, int radix, int start_stage, int reps, double* ns_per_stage);
+
+typedef struct {
+    size_t n;
+    int log2n;                    /* 0 for lengths that are not powers of two */
+    double stage_cost[4][16];     /* ns per stage per transform for radix 2,4,8,16 by start stage; <0 = none */
+    int predicted[16];            /* shortest-path schedule over stage_cost */
+    int n_predicted;
+    double predicted_cost;
+    int n_candidates;             /* compiled block kernels timed whole */
+    int candidate_kernel[32];     /* catalogue indices (fft_kernel_info) */
+    double candidate_us[32];      /* microseconds per execute of `batch` transforms */
+    int chosen_kernel;            /* fastest candidate; recorded as wisdom for n */
+    double chosen_us;
+} fft_tune_report_t;
+
+/* Autotune length n on the current device: stage microbenchmarks and the
+ * shortest-path schedule (the paper's model), then every compiled block kernel
+ * for n timed as a whole on `batch` transforms (runtime validation); the
+ * fastest becomes the wisdom entry fft_plan_create uses for n.  Synchronous;
+ * allocates temporary device buffers. */
+fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* report);
+
+/* Wisdom: the kernel chosen per length.  fft_plan_create uses it when no
+ * explicit options are given.  The file format is one "length kernel-name"
+ * line per entry; entries naming kernels this build does not have are skipped
+ * (INVALID_ARG is returned after loading the rest).  The environment variable
+ * FFTBLOCK_WISDOM names a file loaded before the first plan is created. */
+fft_status_t fft_wisdom_set(size_t n, int kernel_index);
+int fft_wisdom_get(size_t n);          /* catalogue index, or -1 */
+void fft_wisdom_clear(void);
+fft_status_t fft_wisdom_save(const char* path);
+fft_status_t fft_wisdom_load(const char* path);
+
+/* ---------------------------------------------------------------------------
+ * Ragged batches: transforms of several lengths in one submission.
+ * ------------------------------------------------------------------------- */
+typedef struct fft_ragged_s* fft_ragged_t;
+
+/*
+ * fft_ragged_create -- plan n_classes batches: counts[c] transforms of length
+ * sizes[c] each, all in `direction`, on the current device.  Every length must
+ * be one fft_plan_create accepts; each class gets an ordinary plan (which uses
+ * the autotuner's wisdom for its length).  Data layout for execute: the
+ * classes' batches concatenated in the given order, class c starting at
+ * complex element sum_{j<c} sizes[j] * counts[j].
+ */
+fft_status_t fft_ragged_create(const size_t* sizes, const size_t* counts, size_t n_classes, int direction,
+                               fft_ragged_t* out);
+
+/*
+ * fft_ragged_execute -- transform every class from `in` to `out` on `stream`
+ * (device pointers, 8-byte aligned, in == out allowed, other overlap
+ * INVALID_ARG).  mode 0: one hipGraphLaunch of a graph holding every class's
+ * kernels on parallel branches (captured on the first call with this (in, out)
+ * pair, re-captured when the pair changes); mode 1: the classes' kernels
+ * launched one after another on `stream` (the plain path).  Asynchronous.
+ */
+fft_status_t fft_ragged_execute(fft_ragged_t r, const void* in, void* out, void* stream, int mode);
+
+/* Total complex values of one execute, and nodes of the captured graph (0
+ * before the first graph execute).  Either pointer may be NULL. */
+fft_status_t fft_ragged_describe(fft_ragged_t r, size_t* total_points, size_t* graph_nodes);
+
+/* Synchronise the device and free the plans, graph, streams and events. */
+fft_status_t fft_ragged_destroy(fft_ragged_t r);
+
 #ifdef __cplusplus
 }
 #endif

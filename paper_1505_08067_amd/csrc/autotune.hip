@@ -1,0 +1,438 @@
+// Schedule search after the paper's performance model (Approach, bottom-level
+// analysis, "FFT performance model"), plus runtime validation and wisdom.
+//
+// * Stage microbenchmarks: the cost of one radix-R Stockham stage starting at
+//   stage index s (Ns = 2^s points already combined) on an LDS-resident
+//   N-point transform, measured on the GPU as the difference between a kernel
+//   that repeats the stage `reps` times and one that does not, per stage and
+//   transform.
+// * The stage DAG: states 0..log2 N, a radix-R edge from s to s + log2 R
+//   weighted by its measured cost; under the paper's hypothesis (a stage's cost
+//   depends only on its radix and start stage) the best schedule is the
+//   shortest source-to-sink path, found with Dijkstra's algorithm.
+// * Runtime validation: every compiled kernel for N is timed as a whole (the
+//   hypothesis does not hold exactly once stages are fused into one kernel);
+//   the fastest becomes the wisdom entry the planner uses for N.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "../../include/fftblock.h"
+#include "fft_device.hpp"
+#include "internal.hpp"
+
+namespace fb {
+
+// ------------------------------------------------------------ stage kernel
+// One workgroup per transform, T = N/16 threads, 16 values per thread.  The
+// transform is loaded into LDS once; then `reps` times: every thread reads the
+// inputs of its 16/R butterflies (Stockham positions j + r N/R), applies the
+// stage twiddles w^(r (j mod Ns)) from power rows, runs the R-point DFT and
+// writes the outputs back ((j/Ns) Ns R + j mod Ns + q Ns).  The result is
+// stored so the work cannot be removed.
+template <int R>
+__global__ void __launch_bounds__(1024) k_stage(float2* __restrict__ data, const float2* __restrict__ pw, int n, int ns,
+                                                int reps)
+{
+    extern __shared__ float2 sh[];
+    constexpr int E = 16;
+    constexpr int P = (R - 1) >= 16 ? 5 : (R - 1) >= 8 ? 4 : (R - 1) >= 4 ? 3 : (R - 1) >= 2 ? 2 : 1;
+    constexpr int ROW = (P + 1) & ~1;
+    const int T = n / E;
+    const int t = threadIdx.x;
+    float2* x = data + (long long)blockIdx.x * n;
+    for (int i = t; i < n; i += T) sh[i + (i >> 4)] = x[i];
+    __syncthreads();
+    float2 v[E];
+    for (int rep = 0; rep < reps; ++rep) {
+#pragma unroll
+        for (int b = 0; b < E / R; ++b) {
+            const int j = t + b * T;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = j + r * (n / R);
+                v[b * R + r] = sh[i + (i >> 4)];
+            }
+            apply_pow_row<R>(&v[b * R], pw + (long long)(j % ns) * ROW);
+            Dft<R>::run(&v[b * R]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < E / R; ++b) {
+            const int j = t + b * T;
+            const int base = (j / ns) * ns * R + (j % ns);
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int i = base + q * ns;
+                sh[i + (i >> 4)] = v[b * R + q];
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < n; i += T) x[i] = sh[i + (i >> 4)];
+}
+
+using StageFn = void (*)(float2*, const float2*, int, int, int);
+
+static StageFn stage_fn(int radix)
+{
+    switch (radix) {
+        case 2: return k_stage<2>;
+        case 4: return k_stage<4>;
+        case 8: return k_stage<8>;
+        case 16: return k_stage<16>;
+        default: return nullptr;
+    }
+}
+
+// exp(-2 pi i m / n) in FP64, rounded once (same reduction as the planner's)
+static float2 root32(long long m, long long n)
+{
+    m %= n;
+    if (m < 0) m += n;
+    const long long q = (4 * m) / n, rem = 4 * m - q * n;
+    const double hp = 1.57079632679489661923132169163975144;
+    double c, s;
+    if (2 * rem <= n) {
+        c = std::cos(hp * ((double)rem / (double)n));
+        s = std::sin(hp * ((double)rem / (double)n));
+    } else {
+        c = std::sin(hp * ((double)(n - rem) / (double)n));
+        s = std::cos(hp * ((double)(n - rem) / (double)n));
+    }
+    const double cr = q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+    const double sr = q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
+    return make_float2((float)cr, (float)-sr);
+}
+
+// ---------------------------------------------------------------- wisdom
+struct Wisdom {
+    std::mutex mu;
+    std::map<size_t, std::string> choice;  // length -> kernel name
+};
+static Wisdom& wisdom()
+{
+    static Wisdom w;
+    return w;
+}
+
+const KEntry* wisdom_kernel(size_t n)
+{
+    static std::once_flag env_once;
+    std::call_once(env_once, [] {
+        const char* path = std::getenv("FFTBLOCK_WISDOM");
+        if (path && *path) (void)fft_wisdom_load(path);
+    });
+    Wisdom& w = wisdom();
+    std::string name;
+    {
+        std::lock_guard<std::mutex> lk(w.mu);
+        auto it = w.choice.find(n);
+        if (it == w.choice.end()) return nullptr;
+        name = it->second;
+    }
+    int c = 0;
+    const KEntry* t = kernel_table(&c);
+    for (int i = 0; i < c; ++i)
+        if (t[i].kind == kKindBlock && (size_t)t[i].n == n && name == t[i].name) return &t[i];
+    return nullptr;
+}
+
+}  // namespace fb
+
+using namespace fb;
+
+extern "C" {
+
+fft_status_t fft_schedule_search(int log2n, const int* radices, int n_radices, const double* costs, int* sched_out,
+                                 int* n_sched_out, double* total_out)
+{
+    if (log2n < 1 || log2n > 30 || !radices || n_radices < 1 || n_radices > 8 || !costs || !sched_out ||
+        !n_sched_out)
+        return FFT_ERR_INVALID_ARG;
+    std::vector<int> step(n_radices);
+    for (int i = 0; i < n_radices; ++i) {
+        int l = 0;
+        while ((1 << l) < radices[i]) ++l;
+        if (radices[i] < 2 || (1 << l) != radices[i]) return FFT_ERR_INVALID_ARG;
+        step[i] = l;
+    }
+    // label: (cost, stages, radix list negated for "larger list wins ties")
+    struct Label {
+        double cost;
+        int stages;
+        std::vector<int> neg;
+        bool operator>(const Label& o) const
+        {
+            if (cost != o.cost) return cost > o.cost;
+            if (stages != o.stages) return stages > o.stages;
+            return neg > o.neg;
+        }
+    };
+    std::vector<bool> have(log2n + 1, false), done(log2n + 1, false);
+    std::vector<Label> best(log2n + 1);
+    using Item = std::pair<Label, int>;
+    auto cmp = [](const Item& a, const Item& b) { return a.first > b.first; };
+    std::priority_queue<Item, std::vector<Item>, decltype(cmp)> pq(cmp);
+    best[0] = Label{0.0, 0, {}};
+    have[0] = true;
+    pq.push({best[0], 0});
+    while (!pq.empty()) {
+        const Item it = pq.top();
+        pq.pop();
+        const int node = it.second;
+        if (done[node]) continue;
+        done[node] = true;
+        if (node == log2n) break;
+        for (int i = 0; i < n_radices; ++i) {
+            const int nxt = node + step[i];
+            if (nxt > log2n) continue;
+            const double c = costs[i * log2n + node];
+            if (!(c >= 0.0) || std::isinf(c)) continue;  // absent edge
+            Label cand = it.first;
+            cand.cost += c;
+            cand.stages += 1;
+            cand.neg.push_back(-radices[i]);
+            if (!have[nxt] || best[nxt] > cand) {
+                best[nxt] = cand;
+                have[nxt] = true;
+                pq.push({cand, nxt});
+            }
+        }
+    }
+    if (!have[log2n]) return FFT_ERR_UNSUPPORTED_SIZE;
+    const Label& b = best[log2n];
+    for (size_t i = 0; i < b.neg.size(); ++i) sched_out[i] = -b.neg[i];
+    *n_sched_out = (int)b.neg.size();
+    if (total_out) *total_out = b.cost;
+    return FFT_SUCCESS;
+}
+
+fft_status_t fft_stage_benchmark(size_t n, int radix, int start_stage, int reps, double* ns_per_stage)
+{
+    if (!ns_per_stage || reps < 1 || n < 256 || n > 16384 || (n & (n - 1)) || start_stage < 0) return FFT_ERR_INVALID_ARG;
+    StageFn fn = stage_fn(radix);
+    if (!fn) return FFT_ERR_INVALID_ARG;
+    int lg = 0, lr = 0;
+    while (((size_t)1 << lg) < n) ++lg;
+    while ((1 << lr) < radix) ++lr;
+    if (start_stage + lr > lg) return FFT_ERR_INVALID_ARG;
+    const int ns = 1 << start_stage;
+    const int P = (radix - 1) >= 16 ? 5 : (radix - 1) >= 8 ? 4 : (radix - 1) >= 4 ? 3 : (radix - 1) >= 2 ? 2 : 1;
+    const int row = (P + 1) & ~1;
+    std::vector<float2> pw((size_t)ns * row, make_float2(0.f, 0.f));
+    for (int k = 0; k < ns; ++k)
+        for (int i = 0; i < P; ++i) pw[(size_t)k * row + i] = root32((long long)k << i, (long long)ns * radix);
+    const size_t batch = std::max<size_t>((size_t)1 << 22, n) / n;
+    float2 *d = nullptr, *dpw = nullptr;
+    hipError_t e = hipMalloc(&d, batch * n * sizeof(float2));
+    if (e == hipSuccess) e = hipMalloc(&dpw, pw.size() * sizeof(float2));
+    if (e == hipSuccess) e = hipMemcpy(dpw, pw.data(), pw.size() * sizeof(float2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(d, 0, batch * n * sizeof(float2));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const size_t shmem = (n + n / 16) * sizeof(float2);
+    const int threads = (int)(n / 16);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    float ms_base = 0.f, ms_reps = 0.f;
+    for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {  // pass 0 warms up
+        for (int which = 0; which < 2 && e == hipSuccess; ++which) {
+            const int r = which == 0 ? 0 : reps;
+            e = hipEventRecord(e0, nullptr);
+            hipLaunchKernelGGL(fn, dim3((unsigned)batch), dim3(threads), shmem, nullptr, d, dpw, (int)n, ns, r);
+            if (e == hipSuccess) e = hipGetLastError();
+            if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (pass > 0) (which == 0 ? ms_base : ms_reps) += ms;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (d) (void)hipFree(d);
+    if (dpw) (void)hipFree(dpw);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? FFT_ERR_OUT_OF_MEMORY : FFT_ERR_DEVICE;
+    const double per = ((double)ms_reps - (double)ms_base) / 2.0 * 1e6 / ((double)reps * (double)batch);
+    *ns_per_stage = per > 0 ? per : 0.0;
+    return FFT_SUCCESS;
+}
+
+fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
+{
+    if (!rep || n < 2 || batch < 1) return FFT_ERR_INVALID_ARG;
+    std::memset(rep, 0, sizeof(*rep));
+    rep->n = n;
+    rep->chosen_kernel = -1;
+    int lg = 0;
+    while (((size_t)1 << lg) < n) ++lg;
+    const bool pow2 = ((size_t)1 << lg) == n;
+    rep->log2n = pow2 ? lg : 0;
+    for (int i = 0; i < 4; ++i)
+        for (int s = 0; s < 16; ++s) rep->stage_cost[i][s] = -1.0;
+    // 1) the paper's model: stage costs, DAG, Dijkstra (power-of-two lengths)
+    static const int kRad[4] = {2, 4, 8, 16};
+    if (pow2 && n >= 256 && n <= 16384) {
+        for (int i = 0; i < 4; ++i) {
+            int lr = 0;
+            while ((1 << lr) < kRad[i]) ++lr;
+            for (int s = 0; s + lr <= lg; ++s) {
+                double c = -1.0;
+                const fft_status_t st = fft_stage_benchmark(n, kRad[i], s, 8, &c);
+                if (st != FFT_SUCCESS) return st;
+                rep->stage_cost[i][s] = c;
+            }
+        }
+        std::vector<double> costs(4 * lg, -1.0);
+        for (int i = 0; i < 4; ++i)
+            for (int s = 0; s < lg; ++s) costs[i * lg + s] = rep->stage_cost[i][s];
+        int ns = 0;
+        if (fft_schedule_search(lg, kRad, 4, costs.data(), rep->predicted, &ns, &rep->predicted_cost) == FFT_SUCCESS)
+            rep->n_predicted = ns;
+    }
+    // 2) runtime validation: every compiled block kernel for n, timed whole
+    int count = 0;
+    const KEntry* t = kernel_table(&count);
+    float2 *x = nullptr, *y = nullptr;
+    hipError_t e = hipMalloc(&x, n * batch * sizeof(float2));
+    if (e == hipSuccess) e = hipMalloc(&y, n * batch * sizeof(float2));
+    if (e == hipSuccess) e = hipMemset(x, 0, n * batch * sizeof(float2));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    double best = 1e300;
+    for (int i = 0; i < count && e == hipSuccess && rep->n_candidates < 32; ++i) {
+        if (t[i].kind != kKindBlock || (size_t)t[i].n != n) continue;
+        fft_plan_opts_t o;
+        fft_plan_opts_init(&o);
+        o.n_radix = t[i].nr;
+        for (int r = 0; r < t[i].nr; ++r) o.radix[r] = t[i].radix[r];
+        o.flags = t[i].flags;
+        o.block_limit = 16384;
+        fft_plan_t p = nullptr;
+        fft_status_t st = fft_plan_create_ex(n, batch, FFT_FORWARD, &o, &p);
+        if (st != FFT_SUCCESS) continue;
+        fft_plan_desc_t d;
+        fft_plan_describe(p, &d);
+        if (std::strcmp(d.kernel_name, t[i].name) != 0) {
+            fft_plan_destroy(p);
+            continue;
+        }
+        for (int w = 0; w < 2; ++w) fft_execute(p, x, y, nullptr);
+        const int reps = 10;
+        e = hipEventRecord(e0, nullptr);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            if (fft_execute(p, (r & 1) ? y : x, (r & 1) ? x : y, nullptr) != FFT_SUCCESS) e = hipErrorUnknown;
+        if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        fft_plan_destroy(p);
+        const double us = (double)ms * 1e3 / reps;
+        rep->candidate_kernel[rep->n_candidates] = i;
+        rep->candidate_us[rep->n_candidates] = us;
+        rep->n_candidates++;
+        if (us < best) {
+            best = us;
+            rep->chosen_kernel = i;
+            rep->chosen_us = us;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (x) (void)hipFree(x);
+    if (y) (void)hipFree(y);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? FFT_ERR_OUT_OF_MEMORY : FFT_ERR_DEVICE;
+    if (rep->chosen_kernel < 0) return FFT_ERR_UNSUPPORTED_SIZE;
+    {
+        Wisdom& w = wisdom();
+        std::lock_guard<std::mutex> lk(w.mu);
+        w.choice[n] = t[rep->chosen_kernel].name;
+    }
+    return FFT_SUCCESS;
+}
+
+fft_status_t fft_wisdom_set(size_t n, int kernel_index)
+{
+    int c = 0;
+    const KEntry* t = kernel_table(&c);
+    if (kernel_index < 0 || kernel_index >= c || t[kernel_index].kind != kKindBlock || (size_t)t[kernel_index].n != n)
+        return FFT_ERR_INVALID_ARG;
+    Wisdom& w = wisdom();
+    std::lock_guard<std::mutex> lk(w.mu);
+    w.choice[n] = t[kernel_index].name;
+    return FFT_SUCCESS;
+}
+
+void fft_wisdom_clear(void)
+{
+    Wisdom& w = wisdom();
+    std::lock_guard<std::mutex> lk(w.mu);
+    w.choice.clear();
+}
+
+int fft_wisdom_get(size_t n)
+{
+    const KEntry* k = wisdom_kernel(n);
+    if (!k) return -1;
+    int c = 0;
+    const KEntry* t = kernel_table(&c);
+    return (int)(k - t);
+}
+
+fft_status_t fft_wisdom_save(const char* path)
+{
+    if (!path) return FFT_ERR_INVALID_ARG;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return FFT_ERR_INVALID_ARG;
+    Wisdom& w = wisdom();
+    std::lock_guard<std::mutex> lk(w.mu);
+    std::fprintf(f, "# fftblock wisdom: length kernel\n");
+    for (const auto& kv : w.choice) std::fprintf(f, "%zu %s\n", kv.first, kv.second.c_str());
+    std::fclose(f);
+    return FFT_SUCCESS;
+}
+
+fft_status_t fft_wisdom_load(const char* path)
+{
+    if (!path) return FFT_ERR_INVALID_ARG;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return FFT_ERR_INVALID_ARG;
+    char line[512];
+    int c = 0;
+    const KEntry* t = kernel_table(&c);
+    fft_status_t st = FFT_SUCCESS;
+    Wisdom& w = wisdom();
+    std::lock_guard<std::mutex> lk(w.mu);
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        size_t n = 0;
+        char name[400];
+        if (std::sscanf(line, "%zu %399[^\n]", &n, name) != 2) {
+            st = FFT_ERR_INVALID_ARG;
+            continue;
+        }
+        bool known = false;
+        for (int i = 0; i < c; ++i) known = known || (t[i].kind == kKindBlock && (size_t)t[i].n == n && std::strcmp(t[i].name, name) == 0);
+        if (!known) {
+            st = FFT_ERR_INVALID_ARG;  // stale entry (kernel no longer compiled): skipped
+            continue;
+        }
+        w.choice[n] = name;
+    }
+    std::fclose(f);
+    return st;
+}
+
+}  // extern "C"

@@ -80,14 +80,62 @@ __host__ __device__ constexpr double sin_q32(int q)
     return h == 0 ? s : h == 1 ? c : h == 2 ? -s : -c;
 }
 
-// v * exp(-2 pi i Q / R) with R dividing 32.
+// Compile-time cos/sin of 2 pi q / R for any integer q and R > 0: quadrant
+// reduction (exact at multiples of a quarter turn), then Taylor series on an
+// angle of at most pi/4 (error below 1e-16 after 12 terms).
+constexpr double kHalfPi = 1.57079632679489661923132169163975144;
+__host__ __device__ constexpr double ct_sin_small(double x)
+{
+    double x2 = x * x, term = x, sum = x;
+    for (int i = 1; i < 12; ++i) {
+        term *= -x2 / ((2.0 * i) * (2.0 * i + 1.0));
+        sum += term;
+    }
+    return sum;
+}
+__host__ __device__ constexpr double ct_cos_small(double x)
+{
+    double x2 = x * x, term = 1.0, sum = 1.0;
+    for (int i = 1; i < 12; ++i) {
+        term *= -x2 / ((2.0 * i - 1.0) * (2.0 * i));
+        sum += term;
+    }
+    return sum;
+}
+// {cos, sin}(2 pi q / R)
+__host__ __device__ constexpr double ct_cs(int q, int R, bool want_sin)
+{
+    int m = q % R;
+    if (m < 0) m += R;
+    const int quad = (4 * m) / R;
+    const int rem = 4 * m - quad * R;  // angle within the quadrant = (pi/2) rem / R
+    double c = 1.0, s = 0.0;
+    if (rem != 0) {
+        if (2 * rem <= R) {
+            const double phi = kHalfPi * ((double)rem / (double)R);
+            c = ct_cos_small(phi);
+            s = ct_sin_small(phi);
+        } else {
+            const double phi = kHalfPi * ((double)(R - rem) / (double)R);
+            c = ct_sin_small(phi);
+            s = ct_cos_small(phi);
+        }
+    }
+    const double cr = quad == 0 ? c : quad == 1 ? -s : quad == 2 ? -c : s;
+    const double sr = quad == 0 ? s : quad == 1 ? c : quad == 2 ? -s : -c;
+    return want_sin ? sr : cr;
+}
+
+// v * exp(-2 pi i Q / R).  Multiples of a quarter turn and odd multiples of
+// an eighth turn are written without a general complex multiply.
 template <int Q, int R>
 __device__ __forceinline__ float2 mul_root(float2 v)
 {
-    static_assert(32 % R == 0, "radix must divide 32");
-    constexpr int q = ((Q % R) * (32 / R)) & 31;
+    constexpr int q0 = ((Q % R) + R) % R;
+    constexpr bool eighth = (8 * q0) % R == 0;
+    constexpr int q = eighth ? (8 * q0) / R * 4 : -1;  // in 32nds when on the eighth grid
     constexpr float h = 0.70710678118654752440f;
-    if constexpr (q == 0) {
+    if constexpr (q0 == 0) {
         return v;
     } else if constexpr (q == 8) {
         return make_float2(v.y, -v.x);
@@ -104,9 +152,9 @@ __device__ __forceinline__ float2 mul_root(float2 v)
     } else if constexpr (q == 28) {
         return make_float2(h * (v.x - v.y), h * (v.x + v.y));
     } else {
-        constexpr float c = (float)cos_q32(q);
-        constexpr float s = (float)(-sin_q32(q));
-        return cmul_cs(v, c, s);
+        constexpr float c = (float)ct_cs(q0, R, false);
+        constexpr float sn = (float)(-ct_cs(q0, R, true));
+        return cmul_cs(v, c, sn);
     }
 }
 
@@ -146,7 +194,50 @@ struct Dft<4> {
     }
 };
 
-__host__ __device__ constexpr int dft_split(int R) { return R == 8 ? 4 : R == 16 ? 4 : R == 32 ? 8 : 1; }
+// 3-point DFT: X1,2 = x0 - (x1+x2)/2 -/+ i (sqrt(3)/2)(x1 - x2).
+template <>
+struct Dft<3> {
+    static __device__ __forceinline__ void run(float2* v)
+    {
+        constexpr float s3 = 0.86602540378443864676f;
+        const float2 a = cadd(v[1], v[2]);
+        const float2 b = csub(v[1], v[2]);
+        const float2 m = make_float2(fmaf(-0.5f, a.x, v[0].x), fmaf(-0.5f, a.y, v[0].y));
+        v[0] = cadd(v[0], a);
+        v[1] = make_float2(fmaf(s3, b.y, m.x), fmaf(-s3, b.x, m.y));
+        v[2] = make_float2(fmaf(-s3, b.y, m.x), fmaf(s3, b.x, m.y));
+    }
+};
+
+// 5-point DFT with the symmetric pairs (x1, x4) and (x2, x3):
+//   X1,4 = x0 + c1 a1 + c2 a2 -/+ i (s1 b1 + s2 b2)
+//   X2,3 = x0 + c2 a1 + c1 a2 -/+ i (s2 b1 - s1 b2)
+// with a = sums, b = differences, c_k = cos(2 pi k / 5), s_k = sin(2 pi k / 5).
+template <>
+struct Dft<5> {
+    static __device__ __forceinline__ void run(float2* v)
+    {
+        constexpr float c1 = (float)ct_cs(1, 5, false), c2 = (float)ct_cs(2, 5, false);
+        constexpr float s1 = (float)ct_cs(1, 5, true), s2 = (float)ct_cs(2, 5, true);
+        const float2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+        const float2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+        const float2 x0 = v[0];
+        const float2 m1 = make_float2(fmaf(c2, a2.x, fmaf(c1, a1.x, x0.x)), fmaf(c2, a2.y, fmaf(c1, a1.y, x0.y)));
+        const float2 m2 = make_float2(fmaf(c1, a2.x, fmaf(c2, a1.x, x0.x)), fmaf(c1, a2.y, fmaf(c2, a1.y, x0.y)));
+        const float2 n1 = make_float2(fmaf(s2, b2.x, s1 * b1.x), fmaf(s2, b2.y, s1 * b1.y));
+        const float2 n2 = make_float2(fmaf(-s1, b2.x, s2 * b1.x), fmaf(-s1, b2.y, s2 * b1.y));
+        v[0] = make_float2(x0.x + a1.x + a2.x, x0.y + a1.y + a2.y);
+        v[1] = make_float2(m1.x + n1.y, m1.y - n1.x);  // m1 - i n1
+        v[4] = make_float2(m1.x - n1.y, m1.y + n1.x);  // m1 + i n1
+        v[2] = make_float2(m2.x + n2.y, m2.y - n2.x);
+        v[3] = make_float2(m2.x - n2.y, m2.y + n2.x);
+    }
+};
+
+__host__ __device__ constexpr int dft_split(int R)
+{
+    return R == 8 ? 4 : R == 16 ? 4 : R == 32 ? 8 : R == 6 ? 2 : R == 10 ? 2 : R == 12 ? 4 : R == 15 ? 3 : R == 20 ? 4 : 1;
+}
 
 // R = R1 * R2: with n = R2*n1 + n2 and k = k1 + R1*k2,
 //   X[k] = sum_{n2} w_R2^{n2 k2} [ w_R^{n2 k1} sum_{n1} x[R2 n1 + n2] w_R1^{n1 k1} ].
@@ -199,10 +290,11 @@ struct Sched {
     }
     static constexpr int n() { return ns(count); }
     // offset of stage s's twiddle rows (stage 0 needs none): rows k < Ns of R entries
+    // (each stage's block is padded to an even number of entries)
     static constexpr int tw_off(int s)
     {
         int o = 0;
-        for (int i = 1; i < s; ++i) o += ns(i) * r(i);
+        for (int i = 1; i < s; ++i) o += (ns(i) * r(i) + 1) & ~1;
         return o;
     }
     static constexpr int tw_size() { return tw_off(count); }
@@ -230,8 +322,8 @@ struct Sched {
     // Power layout: row k of stage s holds w^(2^i), i < log2(R), for
     // w = w_{Ns R}^k (padded to an even count for 16-byte loads); the other
     // powers are formed by products (binary decomposition of the exponent).
-    static constexpr int lg(int v) { return v <= 1 ? 0 : 1 + lg(v / 2); }
-    static constexpr int p_row(int s) { return (lg(r(s)) + 1) & ~1; }
+    static constexpr int bits(int v) { return v <= 0 ? 0 : 1 + bits(v / 2); }
+    static constexpr int p_row(int s) { return (bits(r(s) - 1) + 1) & ~1; }
     static constexpr int ptw_off(int s)
     {
         int o = 0;
@@ -252,13 +344,14 @@ struct Sched {
 __host__ __device__ constexpr int lds_pad(int i) { return i + (i >> 4); }
 
 // Multiplies the R inputs of one butterfly by its twiddle row
-// tw[k*R + r] = exp(-2 pi i r k / (Ns R)), loaded as 16-byte pairs.
+// tw[k*R + r] = exp(-2 pi i r k / (Ns R)); even radices load 16-byte pairs
+// (rows start on even entries), odd radices single entries.
 template <int R>
 __device__ __forceinline__ void apply_row(float2* v, const float2* __restrict__ row)
 {
     if constexpr (R == 1) {
         return;
-    } else {
+    } else if constexpr (R % 2 == 0) {
         const float4* row4 = reinterpret_cast<const float4*>(row);
 #pragma unroll
         for (int r = 0; r < R; r += 2) {
@@ -266,6 +359,9 @@ __device__ __forceinline__ void apply_row(float2* v, const float2* __restrict__ 
             if (r > 0) v[r] = cmul(v[r], make_float2(w.x, w.y));
             v[r + 1] = cmul(v[r + 1], make_float2(w.z, w.w));
         }
+    } else {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], row[r]);
     }
 }
 
@@ -303,13 +399,13 @@ __device__ __forceinline__ void gstore(float2* p, float2 v)
     }
 }
 
-// Powers w^r, r < R, from the row w^(2^i), i < log2(R) (FP64-generated,
+// Powers w^r, r < R, from the row w^(2^i), 2^i < R (FP64-generated,
 // FP32-stored): w^r = w^h * w^(r-h) with h the highest power of two in r, so
 // each power carries at most popcount(r) - 1 complex products.
 template <int R>
 __device__ __forceinline__ void powers_from_row(float2 (&w)[R], const float2* __restrict__ row)
 {
-    constexpr int P = (R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : R == 16 ? 4 : 5);
+    constexpr int P = (R - 1) >= 16 ? 5 : (R - 1) >= 8 ? 4 : (R - 1) >= 4 ? 3 : (R - 1) >= 2 ? 2 : 1;
     constexpr int PP = (P + 1) & ~1;
     float2 p[PP];
     const float4* row4 = reinterpret_cast<const float4*>(row);

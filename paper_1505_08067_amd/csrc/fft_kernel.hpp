@@ -240,6 +240,7 @@ struct PolPass2 {
 template <class S, int s, int R>
 __device__ __forceinline__ void apply_lds_tw(float2* v, const float2* Ltw, int k)
 {
+    static_assert(R % 2 == 0, "persistent variants need even radices");
     const float4* A;
     if constexpr (S::f_full(s)) {
         A = reinterpret_cast<const float4*>(Ltw + S::ftw_off(s) + k * R);

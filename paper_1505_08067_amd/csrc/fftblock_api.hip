@@ -177,6 +177,7 @@ void fill_stage_table(const int* radix, int nr, float2* dst)
         const int R = radix[s];
         for (long long k = 0; k < ns; ++k)
             for (int r = 0; r < R; ++r) dst[at++] = root_f32((long long)r * k, ns * R);
+        at = (at + 1) & ~(size_t)1;  // stage blocks start on even entries
         ns *= R;
     }
 }
@@ -215,8 +216,8 @@ void fill_stage_table_powers(const int* radix, int nr, float2* dst)
     long long ns = radix[0];
     for (int s = 1; s < nr; ++s) {
         const int R = radix[s];
-        int lg = 0;
-        while ((1 << lg) < R) ++lg;
+        int lg = 0;  // number of bits of R - 1: powers 2^i < R
+        while ((1 << lg) <= R - 1) ++lg;
         const int row = (lg + 1) & ~1;
         for (long long k = 0; k < ns; ++k)
             for (int i = 0; i < row; ++i)
@@ -344,7 +345,9 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
 {
     if (n == 0 || batch == 0) return FFT_ERR_INVALID_ARG;
     if (direction != FFT_FORWARD && direction != FFT_BACKWARD) return FFT_ERR_INVALID_ARG;
-    if (!is_pow2(n) || n > kMaxN) return FFT_ERR_UNSUPPORTED_SIZE;
+    if (n > kMaxN) return FFT_ERR_UNSUPPORTED_SIZE;
+    if (!is_pow2(n) && (n > kDefaultBlockLimit || !kernel_default(kKindBlock, (int)n, 0)))
+        return FFT_ERR_UNSUPPORTED_SIZE;  // other lengths: the compiled mixed-radix blocks only
     if (batch > ((size_t)1 << 40) / n) return FFT_ERR_INVALID_ARG;
     fft_plan_opts_t o;
     fft_plan_opts_init(&o);
@@ -357,10 +360,12 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
     size_t off = 0;
     if (n == 1) {
         p->path = FFT_PATH_BLOCK;
-    } else if (n <= limit) {
+    } else if (n <= limit || !is_pow2(n)) {
         p->path = FFT_PATH_BLOCK;
-        if (o.n_radix == 0 && o.flags < 0)
-            p->k1 = kernel_default(kKindBlock, (int)n, 0);
+        if (o.n_radix == 0 && o.flags < 0) {
+            p->k1 = wisdom_kernel(n);
+            if (!p->k1) p->k1 = kernel_default(kKindBlock, (int)n, 0);
+        }
         else
             p->k1 = kernel_find(kKindBlock, (int)n, o.radix, o.n_radix, 0, o.flags < 0 ? 0 : o.flags);
         if (!p->k1) return FFT_ERR_UNSUPPORTED_SIZE;

@@ -62,6 +62,9 @@ const KEntry* kernel_find(int kind, int n, const int* radix, int nr, int c, int 
 const KEntry* block_entries(int* count);
 const KEntry* pass_entries(int* count);
 
+// Kernel the wisdom (autotuner or FFTBLOCK_WISDOM file) chose for length n, or nullptr.
+const KEntry* wisdom_kernel(size_t n);
+
 hipError_t launch_transpose(const float2* in, float2* out, long long rows, long long cols, long long batch,
                             hipStream_t st);
 hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t st);

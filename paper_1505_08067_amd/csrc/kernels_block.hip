@@ -30,6 +30,26 @@ static const KEntry kBlock[] = {
     FB_BLK(true, 35, 4096, 16, 1, 16, 16, 16),
     FB_BLK(true, 35, 8192, 16, 1, 8, 8, 8, 16),
     FB_BLK(true, 35, 16384, 16, 1, 16, 16, 16, 4),
+    // mixed-radix lengths (radix 3 and 5 butterflies and their products)
+    FB_BLK(true, 35, 3, 3, 64, 3),
+    FB_BLK(true, 35, 5, 5, 64, 5),
+    FB_BLK(true, 35, 6, 6, 64, 6),
+    FB_BLK(true, 35, 10, 10, 64, 10),
+    FB_BLK(true, 35, 12, 12, 64, 12),
+    FB_BLK(true, 35, 15, 15, 64, 15),
+    FB_BLK(true, 35, 20, 20, 64, 20),
+    FB_BLK(true, 35, 60, 30, 32, 6, 10),
+    FB_BLK(true, 35, 100, 10, 8, 10, 10),
+    FB_BLK(true, 35, 1000, 10, 2, 10, 10, 10),
+    FB_BLK(true, 35, 3072, 24, 2, 6, 8, 8, 8),
+    FB_BLK(true, 35, 6000, 30, 1, 10, 10, 10, 6),
+    FB_BLK(true, 35, 15360, 60, 1, 12, 20, 4, 4, 4),
+    FB_BLK(false, 0, 15, 15, 64, 15),
+    FB_BLK(false, 0, 60, 30, 32, 6, 10),
+    FB_BLK(false, 0, 1000, 10, 2, 10, 10, 10),
+    FB_BLK(false, 3, 3072, 24, 2, 6, 8, 8, 8),
+    FB_BLK(false, 0, 6000, 30, 1, 10, 10, 10, 6),
+    FB_BLK(false, 3, 15360, 60, 1, 12, 20, 4, 4, 4),
     // plain variants (full twiddle rows, ordinary loads/stores)
     FB_BLK(false, 0, 2, 2, 256, 2),
     FB_BLK(false, 0, 16, 16, 256, 16),

@@ -36,7 +36,9 @@ EXPORTS = (
     "fft_plan_create", "fft_execute", "fft_execute_pass", "fft_transpose", "fft_plan_destroy", "fft_status_string",
     "fft_plan_describe", "fft_plan_query", "fft_device_query", "fft_block_max", "fft_block_limit",
     "fft_copy", "fft_plan_opts_init", "fft_plan_create_ex", "fft_plan_query_ex", "fft_kernel_count",
-    "fft_kernel_info",
+    "fft_kernel_info", "fft_schedule_search", "fft_stage_benchmark", "fft_autotune", "fft_wisdom_set",
+    "fft_wisdom_get", "fft_wisdom_clear", "fft_wisdom_save", "fft_wisdom_load",
+    "fft_ragged_create", "fft_ragged_execute", "fft_ragged_describe", "fft_ragged_destroy",
 )
 
 VARIANT_NT_LOAD = 1
@@ -95,6 +97,16 @@ class DeviceInfo(ctypes.Structure):
     ]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_size_t), ("log2n", ctypes.c_int),
+        ("stage_cost", (ctypes.c_double * 16) * 4),
+        ("predicted", ctypes.c_int * 16), ("n_predicted", ctypes.c_int), ("predicted_cost", ctypes.c_double),
+        ("n_candidates", ctypes.c_int), ("candidate_kernel", ctypes.c_int * 32),
+        ("candidate_us", ctypes.c_double * 32), ("chosen_kernel", ctypes.c_int), ("chosen_us", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -130,6 +142,26 @@ def load():
     lib.fft_kernel_count.argtypes = []
     lib.fft_kernel_count.restype = i
     lib.fft_kernel_info.argtypes = [i, ctypes.POINTER(KernelInfo)]
+    dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+    lib.fft_schedule_search.argtypes = [i, ip, i, dp, ip, ip, dp]
+    lib.fft_stage_benchmark.argtypes = [sz, i, i, i, dp]
+    lib.fft_autotune.argtypes = [sz, sz, ctypes.POINTER(TuneReport)]
+    lib.fft_wisdom_set.argtypes = [sz, i]
+    lib.fft_wisdom_get.argtypes = [sz]
+    lib.fft_wisdom_get.restype = i
+    lib.fft_wisdom_clear.argtypes = []
+    lib.fft_wisdom_clear.restype = None
+    lib.fft_wisdom_save.argtypes = [ctypes.c_char_p]
+    lib.fft_wisdom_load.argtypes = [ctypes.c_char_p]
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    lib.fft_ragged_create.argtypes = [szp, szp, sz, i, ctypes.POINTER(vp)]
+    lib.fft_ragged_execute.argtypes = [vp, vp, vp, vp, i]
+    lib.fft_ragged_describe.argtypes = [vp, szp, szp]
+    lib.fft_ragged_destroy.argtypes = [vp]
+    for name in ("fft_schedule_search", "fft_stage_benchmark", "fft_autotune", "fft_wisdom_set",
+                 "fft_wisdom_save", "fft_wisdom_load", "fft_ragged_create", "fft_ragged_execute",
+                 "fft_ragged_describe", "fft_ragged_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
     for name in ("fft_plan_create", "fft_execute", "fft_execute_pass", "fft_transpose", "fft_plan_destroy",
                  "fft_plan_describe", "fft_plan_query", "fft_device_query", "fft_copy",
                  "fft_plan_create_ex", "fft_plan_query_ex", "fft_kernel_info"):
@@ -326,3 +358,138 @@ def block_limit() -> int:
 
 def status_string(status: int) -> str:
     return load().fft_status_string(status).decode()
+
+
+# ------------------------------------------------------------ schedule search
+RADICES = (2, 4, 8, 16)
+
+
+def schedule_search(log2n: int, costs: dict, radices=RADICES):
+    """Shortest path over the stage DAG (``fft_schedule_search``).
+
+    ``costs`` maps (radix, start_stage) to a cost; missing entries are absent
+    edges.  Returns (total cost, radix list).
+    """
+    lib = load()
+    nr = len(radices)
+    arr = (ctypes.c_double * (nr * log2n))(*([-1.0] * (nr * log2n)))
+    for i, r in enumerate(radices):
+        for s_ in range(log2n):
+            if (r, s_) in costs:
+                arr[i * log2n + s_] = float(costs[(r, s_)])
+    rad = (ctypes.c_int * nr)(*radices)
+    out = (ctypes.c_int * max(1, log2n))()
+    n_out = ctypes.c_int()
+    total = ctypes.c_double()
+    _check(lib.fft_schedule_search(log2n, rad, nr, arr, out, ctypes.byref(n_out), ctypes.byref(total)),
+           "fft_schedule_search")
+    return total.value, list(out[: n_out.value])
+
+
+def stage_benchmark(n: int, radix: int, start_stage: int, reps: int = 8) -> float:
+    """GPU cost of one radix stage in ns per transform (``fft_stage_benchmark``)."""
+    v = ctypes.c_double()
+    _check(load().fft_stage_benchmark(n, radix, start_stage, reps, ctypes.byref(v)), "fft_stage_benchmark")
+    return v.value
+
+
+def autotune(n: int, batch: int) -> dict:
+    """Stage model + whole-kernel validation for length n (``fft_autotune``); updates the wisdom."""
+    r = TuneReport()
+    _check(load().fft_autotune(n, batch, ctypes.byref(r)), f"fft_autotune({n})")
+    names = kernels()
+    stage = {}
+    for i, rad in enumerate(RADICES):
+        for s_ in range(16):
+            if r.stage_cost[i][s_] >= 0:
+                stage[(rad, s_)] = r.stage_cost[i][s_]
+    return {
+        "n": r.n, "log2n": r.log2n, "stage_cost": stage,
+        "predicted": list(r.predicted[: r.n_predicted]), "predicted_cost": r.predicted_cost,
+        "candidates": [(names[r.candidate_kernel[k]]["name"], r.candidate_us[k]) for k in range(r.n_candidates)],
+        "chosen": names[r.chosen_kernel]["name"] if r.chosen_kernel >= 0 else None, "chosen_us": r.chosen_us,
+    }
+
+
+def wisdom_set(n: int, kernel_name: str) -> None:
+    names = [k["name"] for k in kernels()]
+    _check(load().fft_wisdom_set(n, names.index(kernel_name)), "fft_wisdom_set")
+
+
+def wisdom_get(n: int):
+    idx = load().fft_wisdom_get(n)
+    return None if idx < 0 else kernels()[idx]["name"]
+
+
+def wisdom_clear() -> None:
+    load().fft_wisdom_clear()
+
+
+def wisdom_save(path: str) -> None:
+    _check(load().fft_wisdom_save(path.encode()), "fft_wisdom_save")
+
+
+def wisdom_load(path: str) -> None:
+    _check(load().fft_wisdom_load(path.encode()), "fft_wisdom_load")
+
+
+# ------------------------------------------------------------------- ragged
+class Ragged:
+    """Batches of several lengths in one submission (``fft_ragged_*``).
+
+    ``classes`` is a list of (length, count); the data of one execute is the
+    concatenation of the classes' batches in that order.
+    """
+
+    def __init__(self, classes, direction: int = FORWARD):
+        lib = load()
+        self.classes = [(int(n), int(c)) for n, c in classes]
+        k = len(self.classes)
+        sizes = (ctypes.c_size_t * k)(*[n for n, _ in self.classes])
+        counts = (ctypes.c_size_t * k)(*[c for _, c in self.classes])
+        h = ctypes.c_void_p()
+        _check(lib.fft_ragged_create(sizes, counts, k, direction, ctypes.byref(h)), "fft_ragged_create")
+        self._h = h
+        self.direction = direction
+        self.total_points = sum(n * c for n, c in self.classes)
+
+    def offsets(self):
+        out, at = [], 0
+        for n, c in self.classes:
+            out.append(at)
+            at += n * c
+        return out
+
+    def execute(self, x, out=None, stream=None, graph: bool = True):
+        import torch
+        _check_tensor(x, "x")
+        if x.numel() != self.total_points:
+            raise ValueError(f"x has {x.numel()} values, ragged plan expects {self.total_points}")
+        if out is None:
+            out = torch.empty_like(x)
+        _check_tensor(out, "out")
+        _check(load().fft_ragged_execute(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                         _stream_handle(stream), 0 if graph else 1), "fft_ragged_execute")
+        return out
+
+    def describe(self) -> dict:
+        tp, gn = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(load().fft_ragged_describe(self._h, ctypes.byref(tp), ctypes.byref(gn)), "fft_ragged_describe")
+        return {"total_points": tp.value, "graph_nodes": gn.value, "classes": list(self.classes)}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load().fft_ragged_destroy(self._h), "fft_ragged_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -108,7 +108,7 @@ def test_block_limit_env_override():
 
 @pytest.mark.parametrize("args,status", [
     ((0, 1, -1), 1), ((8, 0, -1), 1), ((8, 1, 0), 1), ((8, 1, 2), 1),
-    ((6, 1, -1), 2), ((1000, 1, -1), 2), ((1 << 23, 1, -1), 2),
+    ((7, 1, -1), 2), ((1001, 1, -1), 2), ((3000, 1, -1), 2), ((1 << 23, 1, -1), 2),
 ])
 def test_plan_argument_errors_without_device(args, status):
     with pytest.raises(fb.FFTError) as ei:

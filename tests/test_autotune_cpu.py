@@ -1,0 +1,64 @@
+"""The C++ schedule search against the reference model and the paper's tables,
+and the wisdom file, on the CPU (no device calls)."""
+import math
+import os
+import random
+
+import pytest
+
+from oracle import plan_dag
+from paper_1505_08067_amd import fftblock as fb
+
+
+def _table(golden_dir, name):
+    return plan_dag.load_stage_table(os.path.join(golden_dir, name))
+
+
+@pytest.mark.parametrize("name,cost", [("stage_costs_ivybridge.txt", 19785), ("stage_costs_haswell.txt", 18218)])
+def test_schedule_search_on_printed_tables(golden_dir, name, cost):
+    c = _table(golden_dir, name)
+    total, sched = fb.schedule_search(10, c, radices=(2, 4, 8))
+    assert sched == [8, 8, 4, 4] and total == cost
+    assert (total, sched) == plan_dag.dijkstra(10, c)
+
+
+def test_schedule_search_matches_reference_on_random_tables():
+    rnd = random.Random(11)
+    for L in range(1, 13):
+        for _ in range(5):
+            costs = {(r, s): rnd.randint(1, 30) for r in (2, 4, 8, 16) for s in range(L)
+                     if s + int(math.log2(r)) <= L}
+            got = fb.schedule_search(L, costs)
+            ref = plan_dag.dijkstra(L, costs, radices=(2, 4, 8, 16))
+            assert got[0] == ref[0] and got[1] == ref[1], (L, costs)
+
+
+def test_schedule_search_errors():
+    with pytest.raises(fb.FFTError):
+        fb.schedule_search(4, {}, radices=(2,))          # no edges: unreachable sink
+    with pytest.raises(fb.FFTError):
+        fb.schedule_search(4, {(3, 0): 1.0}, radices=(3,))  # not a power of two
+
+
+def test_wisdom_roundtrip(tmp_path):
+    fb.wisdom_clear()
+    assert fb.wisdom_get(4096) is None
+    alt = [k["name"] for k in fb.kernels() if k["kind"] == "block" and k["n"] == 4096 and not k["is_default"]][0]
+    fb.wisdom_set(4096, alt)
+    assert fb.wisdom_get(4096) == alt
+    assert fb.plan_query(4096, 8)["kernel_name"] == alt
+    p = tmp_path / "w.txt"
+    fb.wisdom_save(str(p))
+    fb.wisdom_clear()
+    assert fb.plan_query(4096, 8)["kernel_name"] != alt
+    fb.wisdom_load(str(p))
+    assert fb.wisdom_get(4096) == alt
+    # a stale entry is skipped and reported
+    p.write_text("4096 block_fft<4096,[no such],v0>\n1024 " + fb.plan_query(1024, 1)["kernel_name"] + "\n")
+    fb.wisdom_clear()
+    with pytest.raises(fb.FFTError):
+        fb.wisdom_load(str(p))
+    assert fb.wisdom_get(4096) is None and fb.wisdom_get(1024) is not None
+    fb.wisdom_clear()
+    with pytest.raises(fb.FFTError):
+        fb.wisdom_set(4096, [k["name"] for k in fb.kernels() if k["n"] == 1024][0])

@@ -1,0 +1,106 @@
+"""Ragged batches (one graph launch) and the autotuner, on the GPU, against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import metrics
+from paper_1505_08067_amd import fftblock as fb
+from paper_1505_08067_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CLASSES = [(64, 5), (1000, 3), (4096, 2), (3, 7), (1 << 16, 1), (15360, 2), (6000, 1), (3072, 3), (1, 4)]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _ragged_input(classes, seed):
+    parts = [inputs.uniform(seed + i, c, n).reshape(-1) for i, (n, c) in enumerate(classes)]
+    return np.concatenate(parts)
+
+
+def _check_classes(y, x, classes, sign):
+    at = 0
+    for n, c in classes:
+        xs = x[at:at + n * c].reshape(c, n).astype(np.complex128)
+        ys = y[at:at + n * c].reshape(c, n)
+        ref = oracle.fft(xs, sign)
+        mx, _, tol = metrics.check(ys, ref, max(n, 2))
+        say(f"  class N={n} x{c}: max rel L2 {mx:.2e} (tol {tol:.1e})")
+        at += n * c
+
+
+@pytest.mark.parametrize("sign", [fb.FORWARD, fb.BACKWARD])
+def test_ragged_graph_and_plain_match_oracle(sign):
+    say(f"case: ragged mix {CLASSES} sign={sign}")
+    x = _ragged_input(CLASSES, 700)
+    xd = torch.from_numpy(x).to("cuda")
+    with fb.Ragged(CLASSES, sign) as r:
+        yg = r.execute(xd)
+        torch.cuda.synchronize()
+        d = r.describe()
+        assert d["total_points"] == x.size and d["graph_nodes"] > 0
+        yp = r.execute(xd, graph=False)
+        torch.cuda.synchronize()
+        ygn, ypn = yg.cpu().numpy(), yp.cpu().numpy()
+        # the same kernels in both submissions: bitwise equal
+        assert np.array_equal(ygn.view(np.uint32), ypn.view(np.uint32))
+        _check_classes(ygn, x, CLASSES, sign)
+        # new buffers: the graph is captured again
+        x2 = _ragged_input(CLASSES, 800)
+        y2 = r.execute(torch.from_numpy(x2).to("cuda"))
+        torch.cuda.synchronize()
+        _check_classes(y2.cpu().numpy(), x2, CLASSES, sign)
+        # in place, launched several times with host work in between
+        buf = torch.from_numpy(x).to("cuda")
+        ref = ygn
+        for rep in range(3):
+            b = buf.clone()
+            r.execute(b, out=b)
+            torch.cuda.synchronize()
+            assert np.array_equal(b.cpu().numpy().view(np.uint32), ref.view(np.uint32)), rep
+
+
+def test_each_class_alone_equals_in_mix():
+    x = _ragged_input(CLASSES, 900)
+    xd = torch.from_numpy(x).to("cuda")
+    with fb.Ragged(CLASSES) as r:
+        mix = r.execute(xd).cpu().numpy()
+    at = 0
+    for n, c in CLASSES:
+        part = xd[at:at + n * c].clone()
+        with fb.Plan(n, c) as p:
+            alone = p.execute(part).cpu().numpy()
+        assert np.array_equal(alone.view(np.uint32), mix[at:at + n * c].view(np.uint32)), n
+        at += n * c
+
+
+def test_stage_benchmark_positive():
+    for radix, stage in ((2, 0), (4, 3), (8, 7), (16, 6)):
+        v = fb.stage_benchmark(1024, radix, stage)
+        say(f"  stage radix {radix} at {stage}: {v:.3f} ns per transform")
+        assert v >= 0.0
+
+
+def test_autotune_sets_wisdom_and_stays_correct(tmp_path):
+    fb.wisdom_clear()
+    rep = fb.autotune(1024, 4096)
+    say(f"  autotune 1024: predicted {rep['predicted']} cost {rep['predicted_cost']:.2f}; "
+        f"chosen {rep['chosen']} {rep['chosen_us']:.1f} us of {len(rep['candidates'])}")
+    assert rep["predicted"] and np.prod(rep["predicted"]) == 1024
+    assert len(rep["stage_cost"]) == 10 + 9 + 8 + 7
+    assert rep["chosen"] and fb.wisdom_get(1024) == rep["chosen"]
+    with fb.Plan(1024, 33) as p:
+        assert p.describe()["kernel_name"] == rep["chosen"]
+        x = inputs.uniform(1, 33, 1024)
+        y = p.execute(torch.from_numpy(x).to("cuda")).cpu().numpy()
+    metrics.check(y, oracle.fft(x.astype(np.complex128)), 1024)
+    rep2 = fb.autotune(6000, 256)           # mixed length: whole-kernel validation only
+    assert rep2["log2n"] == 0 and rep2["predicted"] == [] and rep2["chosen"]
+    path = tmp_path / "wisdom.txt"
+    fb.wisdom_save(str(path))
+    assert "1024 " in path.read_text() and "6000 " in path.read_text()
+    fb.wisdom_clear()
