@@ -284,23 +284,28 @@ typedef struct {
     int predicted[16];            /* shortest-path schedule over stage_cost */
     int n_predicted;
     double predicted_cost;
-    int n_candidates;             /* compiled block kernels timed whole */
-    int candidate_kernel[32];     /* catalogue indices (fft_kernel_info) */
+    int n_candidates;             /* compiled kernels (four-step: kernel pairs) timed whole */
+    int candidate_kernel[32];     /* catalogue indices (fft_kernel_info): block or pass-1 kernel */
+    int candidate_kernel2[32];    /* pass-2 kernel of a four-step candidate, else -1 */
     double candidate_us[32];      /* microseconds per execute of `batch` transforms */
     int chosen_kernel;            /* fastest candidate; recorded as wisdom for n */
+    int chosen_kernel2;
     double chosen_us;
 } fft_tune_report_t;
 
 /* Autotune length n on the current device: stage microbenchmarks and the
  * shortest-path schedule (the paper's model), then every compiled block kernel
- * for n timed as a whole on `batch` transforms (runtime validation); the
- * fastest becomes the wisdom entry fft_plan_create uses for n.  Synchronous;
- * allocates temporary device buffers. */
+ * for n -- or, for four-step lengths, every compiled pass-1 x pass-2 pair,
+ * which also chooses the column and row widths -- timed as a whole on `batch`
+ * transforms (runtime validation); the fastest becomes the wisdom entry
+ * fft_plan_create uses for n.  Synchronous; allocates temporary buffers. */
 fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* report);
 
-/* Wisdom: the kernel chosen per length.  fft_plan_create uses it when no
- * explicit options are given.  The file format is one "length kernel-name"
- * line per entry; entries naming kernels this build does not have are skipped
+/* Wisdom: the kernel (four-step: kernel pair) chosen per length.
+ * fft_plan_create uses it when no explicit options are given.  The file
+ * format is one "length<TAB>kernel[<TAB>pass-2 kernel]" line per entry
+ * (a space may separate length and kernel); entries naming kernels this build
+ * does not have are skipped
  * (INVALID_ARG is returned after loading the rest).  The environment variable
  * FFTBLOCK_WISDOM names a file loaded before the first plan is created. */
 fft_status_t fft_wisdom_set(size_t n, int kernel_index);

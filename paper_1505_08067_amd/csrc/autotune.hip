@@ -117,7 +117,7 @@ static float2 root32(long long m, long long n)
 // ---------------------------------------------------------------- wisdom
 struct Wisdom {
     std::mutex mu;
-    std::map<size_t, std::string> choice;  // length -> kernel name
+    std::map<size_t, std::pair<std::string, std::string>> choice;  // length -> (block or pass-1, pass-2)
 };
 static Wisdom& wisdom()
 {
@@ -125,26 +125,52 @@ static Wisdom& wisdom()
     return w;
 }
 
-const KEntry* wisdom_kernel(size_t n)
+static const KEntry* find_named(int kind, size_t n, const std::string& name)
+{
+    int c = 0;
+    const KEntry* t = kernel_table(&c);
+    for (int i = 0; i < c; ++i)
+        if (t[i].kind == kind && (size_t)t[i].n == n && name == t[i].name) return &t[i];
+    return nullptr;
+}
+
+static void load_env_wisdom()
 {
     static std::once_flag env_once;
     std::call_once(env_once, [] {
         const char* path = std::getenv("FFTBLOCK_WISDOM");
         if (path && *path) (void)fft_wisdom_load(path);
     });
+}
+
+const KEntry* wisdom_kernel(size_t n)
+{
+    load_env_wisdom();
     Wisdom& w = wisdom();
     std::string name;
     {
         std::lock_guard<std::mutex> lk(w.mu);
         auto it = w.choice.find(n);
-        if (it == w.choice.end()) return nullptr;
-        name = it->second;
+        if (it == w.choice.end() || !it->second.second.empty()) return nullptr;
+        name = it->second.first;
     }
-    int c = 0;
-    const KEntry* t = kernel_table(&c);
-    for (int i = 0; i < c; ++i)
-        if (t[i].kind == kKindBlock && (size_t)t[i].n == n && name == t[i].name) return &t[i];
-    return nullptr;
+    return find_named(kKindBlock, n, name);
+}
+
+bool wisdom_pair(size_t n, size_t n1, size_t n2, const KEntry** k1, const KEntry** k2)
+{
+    load_env_wisdom();
+    Wisdom& w = wisdom();
+    std::pair<std::string, std::string> names;
+    {
+        std::lock_guard<std::mutex> lk(w.mu);
+        auto it = w.choice.find(n);
+        if (it == w.choice.end() || it->second.second.empty()) return false;
+        names = it->second;
+    }
+    *k1 = find_named(kKindPass1, n1, names.first);
+    *k2 = find_named(kKindPass2, n2, names.second);
+    return *k1 && *k2;
 }
 
 }  // namespace fb
@@ -275,6 +301,7 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
     std::memset(rep, 0, sizeof(*rep));
     rep->n = n;
     rep->chosen_kernel = -1;
+    rep->chosen_kernel2 = -1;
     int lg = 0;
     while (((size_t)1 << lg) < n) ++lg;
     const bool pow2 = ((size_t)1 << lg) == n;
@@ -312,7 +339,54 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     double best = 1e300;
-    for (int i = 0; i < count && e == hipSuccess && rep->n_candidates < 32; ++i) {
+    auto time_plan = [&](fft_plan_t p) -> double {
+        for (int w = 0; w < 2; ++w) fft_execute(p, x, y, nullptr);
+        const int reps = 10;
+        e = hipEventRecord(e0, nullptr);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            if (fft_execute(p, (r & 1) ? y : x, (r & 1) ? x : y, nullptr) != FFT_SUCCESS) e = hipErrorUnknown;
+        if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        return (double)ms * 1e3 / reps;
+    };
+    fft_plan_desc_t dq;
+    const bool four = fft_plan_query(n, batch, FFT_FORWARD, &dq) == FFT_SUCCESS && dq.path == FFT_PATH_FOURSTEP;
+    if (four) {
+        // pass-1 x pass-2 pairs (schedules, column/row widths, variants)
+        for (int i = 0; i < count && e == hipSuccess; ++i) {
+            if (t[i].kind != kKindPass1 || (size_t)t[i].n != dq.n1 || dq.n2 % t[i].c) continue;
+            for (int j = 0; j < count && e == hipSuccess && rep->n_candidates < 32; ++j) {
+                if (t[j].kind != kKindPass2 || (size_t)t[j].n != dq.n2 || dq.n1 % t[j].c) continue;
+                fft_plan_opts_t o;
+                fft_plan_opts_init(&o);
+                o.flags = t[i].flags;
+                o.c = t[i].c;
+                o.flags2 = t[j].flags;
+                o.c2 = t[j].c;
+                fft_plan_t p = nullptr;
+                if (fft_plan_create_ex(n, batch, FFT_FORWARD, &o, &p) != FFT_SUCCESS) continue;
+                fft_plan_desc_t d;
+                fft_plan_describe(p, &d);
+                const bool same = std::strcmp(d.kernel_name, t[i].name) == 0 && std::strcmp(d.kernel_name2, t[j].name) == 0;
+                const double us = same ? time_plan(p) : -1.0;
+                fft_plan_destroy(p);
+                if (!same) continue;
+                rep->candidate_kernel[rep->n_candidates] = i;
+                rep->candidate_kernel2[rep->n_candidates] = j;
+                rep->candidate_us[rep->n_candidates] = us;
+                rep->n_candidates++;
+                if (us < best) {
+                    best = us;
+                    rep->chosen_kernel = i;
+                    rep->chosen_kernel2 = j;
+                    rep->chosen_us = us;
+                }
+            }
+        }
+    }
+    for (int i = 0; i < count && e == hipSuccess && rep->n_candidates < 32 && !four; ++i) {
         if (t[i].kind != kKindBlock || (size_t)t[i].n != n) continue;
         fft_plan_opts_t o;
         fft_plan_opts_init(&o);
@@ -329,18 +403,10 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
             fft_plan_destroy(p);
             continue;
         }
-        for (int w = 0; w < 2; ++w) fft_execute(p, x, y, nullptr);
-        const int reps = 10;
-        e = hipEventRecord(e0, nullptr);
-        for (int r = 0; r < reps && e == hipSuccess; ++r)
-            if (fft_execute(p, (r & 1) ? y : x, (r & 1) ? x : y, nullptr) != FFT_SUCCESS) e = hipErrorUnknown;
-        if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        const double us = time_plan(p);
         fft_plan_destroy(p);
-        const double us = (double)ms * 1e3 / reps;
         rep->candidate_kernel[rep->n_candidates] = i;
+        rep->candidate_kernel2[rep->n_candidates] = -1;
         rep->candidate_us[rep->n_candidates] = us;
         rep->n_candidates++;
         if (us < best) {
@@ -358,7 +424,7 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
     {
         Wisdom& w = wisdom();
         std::lock_guard<std::mutex> lk(w.mu);
-        w.choice[n] = t[rep->chosen_kernel].name;
+        w.choice[n] = {t[rep->chosen_kernel].name, rep->chosen_kernel2 >= 0 ? t[rep->chosen_kernel2].name : ""};
     }
     return FFT_SUCCESS;
 }
@@ -371,7 +437,7 @@ fft_status_t fft_wisdom_set(size_t n, int kernel_index)
         return FFT_ERR_INVALID_ARG;
     Wisdom& w = wisdom();
     std::lock_guard<std::mutex> lk(w.mu);
-    w.choice[n] = t[kernel_index].name;
+    w.choice[n] = {t[kernel_index].name, ""};
     return FFT_SUCCESS;
 }
 
@@ -398,8 +464,9 @@ fft_status_t fft_wisdom_save(const char* path)
     if (!f) return FFT_ERR_INVALID_ARG;
     Wisdom& w = wisdom();
     std::lock_guard<std::mutex> lk(w.mu);
-    std::fprintf(f, "# fftblock wisdom: length kernel\n");
-    for (const auto& kv : w.choice) std::fprintf(f, "%zu %s\n", kv.first, kv.second.c_str());
+    std::fprintf(f, "# fftblock wisdom: length kernel [pass-2 kernel, tab separated]\n");
+    for (const auto& kv : w.choice)
+        std::fprintf(f, "%zu\t%s\t%s\n", kv.first, kv.second.first.c_str(), kv.second.second.c_str());
     std::fclose(f);
     return FFT_SUCCESS;
 }
@@ -417,19 +484,38 @@ fft_status_t fft_wisdom_load(const char* path)
     std::lock_guard<std::mutex> lk(w.mu);
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
-        size_t n = 0;
-        char name[400];
-        if (std::sscanf(line, "%zu %399[^\n]", &n, name) != 2) {
+        // "length<TAB>name[<TAB>name2]" (a space also separates length and name)
+        char* end = nullptr;
+        const size_t n = std::strtoull(line, &end, 10);
+        if (end == line) {
             st = FFT_ERR_INVALID_ARG;
             continue;
         }
+        while (*end == ' ' || *end == '\t') ++end;
+        std::string rest(end);
+        while (!rest.empty() && (rest.back() == '\n' || rest.back() == '\r')) rest.pop_back();
+        std::string a = rest, b;
+        const size_t tab = rest.find('\t');
+        if (tab != std::string::npos) {
+            a = rest.substr(0, tab);
+            b = rest.substr(tab + 1);
+        }
         bool known = false;
-        for (int i = 0; i < c; ++i) known = known || (t[i].kind == kKindBlock && (size_t)t[i].n == n && std::strcmp(t[i].name, name) == 0);
+        if (b.empty()) {
+            for (int i = 0; i < c; ++i) known = known || (t[i].kind == kKindBlock && (size_t)t[i].n == n && a == t[i].name);
+        } else {
+            bool k1 = false, k2 = false;
+            for (int i = 0; i < c; ++i) {
+                k1 = k1 || (t[i].kind == kKindPass1 && a == t[i].name);
+                k2 = k2 || (t[i].kind == kKindPass2 && b == t[i].name);
+            }
+            known = k1 && k2;
+        }
         if (!known) {
             st = FFT_ERR_INVALID_ARG;  // stale entry (kernel no longer compiled): skipped
             continue;
         }
-        w.choice[n] = name;
+        w.choice[n] = {a, b};
     }
     std::fclose(f);
     return st;

@@ -377,10 +377,13 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
         p->n2 = n / p->n1;
         const int c1 = o.c > 0 ? o.c : (int)env_size("FFTBLOCK_FOURSTEP_C", 0);
         const int c2 = o.c2 > 0 ? o.c2 : (int)env_size("FFTBLOCK_FOURSTEP_C2", 0);
-        p->k1 = o.flags < 0 ? kernel_default(kKindPass1, (int)p->n1, c1)
-                            : kernel_find(kKindPass1, (int)p->n1, nullptr, 0, c1, o.flags);
-        p->k2 = o.flags2 < 0 ? kernel_default(kKindPass2, (int)p->n2, c2)
-                             : kernel_find(kKindPass2, (int)p->n2, nullptr, 0, c2, o.flags2);
+        const bool explicit_opts = o.flags >= 0 || o.flags2 >= 0 || o.c > 0 || o.c2 > 0;
+        if (explicit_opts || !wisdom_pair(n, p->n1, p->n2, &p->k1, &p->k2)) {
+            p->k1 = o.flags < 0 ? kernel_default(kKindPass1, (int)p->n1, c1)
+                                : kernel_find(kKindPass1, (int)p->n1, nullptr, 0, c1, o.flags);
+            p->k2 = o.flags2 < 0 ? kernel_default(kKindPass2, (int)p->n2, c2)
+                                 : kernel_find(kKindPass2, (int)p->n2, nullptr, 0, c2, o.flags2);
+        }
         if (!p->k1 || !p->k2) return FFT_ERR_UNSUPPORTED_SIZE;
         if (p->n2 % p->k1->c || p->n1 % p->k2->c) return FFT_ERR_UNSUPPORTED_SIZE;
         p->lo_bits = (L + 1) / 2;

@@ -64,6 +64,8 @@ const KEntry* pass_entries(int* count);
 
 // Kernel the wisdom (autotuner or FFTBLOCK_WISDOM file) chose for length n, or nullptr.
 const KEntry* wisdom_kernel(size_t n);
+// Four-step kernels the wisdom chose for length n = n1 * n2 (false if none).
+bool wisdom_pair(size_t n, size_t n1, size_t n2, const KEntry** k1, const KEntry** k2);
 
 hipError_t launch_transpose(const float2* in, float2* out, long long rows, long long cols, long long batch,
                             hipStream_t st);

@@ -103,7 +103,9 @@ class TuneReport(ctypes.Structure):
         ("stage_cost", (ctypes.c_double * 16) * 4),
         ("predicted", ctypes.c_int * 16), ("n_predicted", ctypes.c_int), ("predicted_cost", ctypes.c_double),
         ("n_candidates", ctypes.c_int), ("candidate_kernel", ctypes.c_int * 32),
-        ("candidate_us", ctypes.c_double * 32), ("chosen_kernel", ctypes.c_int), ("chosen_us", ctypes.c_double),
+        ("candidate_kernel2", ctypes.c_int * 32),
+        ("candidate_us", ctypes.c_double * 32), ("chosen_kernel", ctypes.c_int), ("chosen_kernel2", ctypes.c_int),
+        ("chosen_us", ctypes.c_double),
     ]
 
 
@@ -406,8 +408,13 @@ def autotune(n: int, batch: int) -> dict:
     return {
         "n": r.n, "log2n": r.log2n, "stage_cost": stage,
         "predicted": list(r.predicted[: r.n_predicted]), "predicted_cost": r.predicted_cost,
-        "candidates": [(names[r.candidate_kernel[k]]["name"], r.candidate_us[k]) for k in range(r.n_candidates)],
-        "chosen": names[r.chosen_kernel]["name"] if r.chosen_kernel >= 0 else None, "chosen_us": r.chosen_us,
+        "candidates": [(names[r.candidate_kernel[k]]["name"] +
+                        ("+" + names[r.candidate_kernel2[k]]["name"] if r.candidate_kernel2[k] >= 0 else ""),
+                        r.candidate_us[k]) for k in range(r.n_candidates)],
+        "chosen": (names[r.chosen_kernel]["name"] +
+                   ("+" + names[r.chosen_kernel2]["name"] if r.chosen_kernel2 >= 0 else ""))
+        if r.chosen_kernel >= 0 else None,
+        "chosen_us": r.chosen_us,
     }
 
 

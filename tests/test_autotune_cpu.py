@@ -62,3 +62,21 @@ def test_wisdom_roundtrip(tmp_path):
     fb.wisdom_clear()
     with pytest.raises(fb.FFTError):
         fb.wisdom_set(4096, [k["name"] for k in fb.kernels() if k["n"] == 1024][0])
+
+
+def test_wisdom_pair_for_fourstep(tmp_path):
+    fb.wisdom_clear()
+    ks = fb.kernels()
+    p1 = [k["name"] for k in ks if k["kind"] == "pass1" and k["n"] == 1024 and not k["is_default"] and k["c"] == 8][0]
+    p2 = [k["name"] for k in ks if k["kind"] == "pass2" and k["n"] == 1024 and not k["is_default"] and k["c"] == 16][0]
+    path = tmp_path / "w.txt"
+    path.write_text(f"1048576\t{p1}\t{p2}\n")
+    fb.wisdom_load(str(path))
+    d = fb.plan_query(1 << 20, 4)
+    assert (d["kernel_name"], d["kernel_name2"]) == (p1, p2)
+    assert d["transforms_per_block"] == 8 and d["c2"] == 16
+    fb.wisdom_save(str(path))
+    assert p1 in path.read_text() and p2 in path.read_text()
+    fb.wisdom_clear()
+    d = fb.plan_query(1 << 20, 4)
+    assert (d["kernel_name"], d["kernel_name2"]) != (p1, p2)

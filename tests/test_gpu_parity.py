@@ -216,7 +216,7 @@ def test_errors_on_device():
         st = fb.load().fft_execute(p.handle, big.data_ptr(), big.data_ptr() + 8 * 1024, None)
         assert st == 1
     with pytest.raises(fb.FFTError) as ei:
-        fb.Plan(1000, 1)
+        fb.Plan(1001, 1)
     assert ei.value.status == 2
 
 

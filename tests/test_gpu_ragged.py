@@ -100,7 +100,17 @@ def test_autotune_sets_wisdom_and_stays_correct(tmp_path):
     metrics.check(y, oracle.fft(x.astype(np.complex128)), 1024)
     rep2 = fb.autotune(6000, 256)           # mixed length: whole-kernel validation only
     assert rep2["log2n"] == 0 and rep2["predicted"] == [] and rep2["chosen"]
+    rep3 = fb.autotune(1 << 20, 4)          # four-step: pass-1 x pass-2 pairs
+    say(f"  autotune 2^20: chosen {rep3['chosen']} {rep3['chosen_us']:.1f} us of {len(rep3['candidates'])}")
+    assert "+" in rep3["chosen"] and len(rep3["candidates"]) > 1
+    with fb.Plan(1 << 20, 2) as p:
+        d = p.describe()
+        assert d["kernel_name"] + "+" + d["kernel_name2"] == rep3["chosen"]
+        x = inputs.uniform(2, 2, 1 << 20)
+        y = p.execute(torch.from_numpy(x).to("cuda")).cpu().numpy()
+    metrics.check(y, oracle.fft(x.astype(np.complex128)), 1 << 20)
     path = tmp_path / "wisdom.txt"
     fb.wisdom_save(str(path))
-    assert "1024 " in path.read_text() and "6000 " in path.read_text()
+    txt = path.read_text()
+    assert "\n1024\t" in txt and "\n6000\t" in txt and "\n1048576\t" in txt
     fb.wisdom_clear()
