@@ -17,6 +17,10 @@ Functions (all return complex128 numpy arrays of the input's shape):
 * ``fft``         -- ``fft_radix2`` for powers of two, else ``fft_mixed``.
 * ``fft2d``       -- separable 2-D transform (rows, then columns).
 * ``transpose``   -- ``out[b][c][r] = in[b][r][c]``.
+* ``range_compress`` -- SAR range compression (the matched filter): the
+  circular cross-correlation of every row with the pulse replica, scaled by n
+  (what B(F(x) * conj(F(ref))) gives with the unnormalised backward
+  transform), evaluated from its definition.
 * ``fourstep_reference`` -- the four-step identity written out with numpy
   (column DFTs, twiddle, row DFTs, transposed read-out), used only to locate
   index mistakes; its sub-DFTs call ``fft``.
@@ -68,6 +72,8 @@ def _load():
     lib.oracle_transpose.restype = ctypes.c_int
     lib.oracle_unit_root.argtypes = [i64, i64, ctypes.c_int, dp]
     lib.oracle_unit_root.restype = None
+    lib.oracle_range_compress.argtypes = [dp, dp, i64, i64, dp, i64, ctypes.c_int]
+    lib.oracle_range_compress.restype = ctypes.c_int
     lib.oracle_nthreads.argtypes = []
     lib.oracle_nthreads.restype = ctypes.c_int
     _lib = lib
@@ -155,6 +161,27 @@ def transpose(x) -> np.ndarray:
     rc = _load().oracle_transpose(_ptr(a), _ptr(out), rows, cols, batch)
     if rc != 0:
         raise RuntimeError("oracle_transpose failed")
+    return out
+
+
+def range_compress(x, ref, threads: int = 0) -> np.ndarray:
+    """SAR range compression of every row of ``x`` (shape [..., n]) with the
+    pulse replica ``ref`` (length L <= n), from the definition
+    ``y[m] = n * sum_{l<L} x[(m + l) mod n] * conj(ref[l])`` (paper: the SAR
+    application section and Fig. 3, range compression after the range FFT)."""
+    a = _as_c128(x)
+    r = _as_c128(ref).reshape(-1)
+    if a.ndim == 0:
+        raise ValueError("need at least one dimension")
+    n = a.shape[-1]
+    if not 1 <= r.size <= n:
+        raise ValueError("replica length must be in [1, n]")
+    rows = a.size // n if n else 0
+    out = np.empty_like(a)
+    if a.size == 0:
+        return out
+    if _load().oracle_range_compress(_ptr(a), _ptr(out), n, rows, _ptr(r), r.size, threads) != 0:
+        raise RuntimeError("oracle_range_compress failed")
     return out
 
 

@@ -19,6 +19,9 @@
  *                        any N >= 1 (prime lengths fall back to the definition).
  *   oracle_fft2d       - separable 2-D transform: every row, then every column.
  *   oracle_transpose   - out[b][c][r] = in[b][r][c].
+ *   oracle_range_compress - the matched filter of SAR range compression: the
+ *                        circular cross-correlation of every row with the
+ *                        transmitted pulse replica (definition, O(n L)).
  *
  * Data: interleaved (re, im) doubles, batch-major [batch][n].  The `sign`
  * argument is the sign of the exponent: -1 forward, +1 backward.
@@ -304,6 +307,73 @@ int oracle_transpose(const double* in, double* out, int64_t rows, int64_t cols, 
         for (int64_t r = 0; r < rows; ++r)
             for (int64_t c = 0; c < cols; ++c)
                 co[b * rows * cols + c * rows + r] = ci[b * rows * cols + r * cols + c];
+    return 0;
+}
+
+/*
+ * Range compression, the first step of the range-Doppler chain after the
+ * range FFT (SAR application section, Fig. 3): each received row is
+ * correlated with the transmitted pulse replica ref[0..L).  Done with
+ * transforms it is B(F(x) .* conj(F(ref zero-padded to n))); with the
+ * unnormalised backward transform that product reaches exactly
+ *     y[m] = n * sum_{l<L} x[(m + l) mod n] * conj(ref[l]),   0 <= m < n,
+ * (the n is the 1/n the backward transform leaves out), which is what this
+ * evaluates, directly and in FP64, for `rows` rows of length n; rows are
+ * split over threads.  `out` must not overlap `in`.
+ */
+typedef struct {
+    const cplx* in;
+    cplx* out;
+    const cplx* ref;
+    int64_t n, L, first, last;
+} xc_job_t;
+
+static void* xc_run(void* arg)
+{
+    xc_job_t* j = (xc_job_t*)arg;
+    for (int64_t b = j->first; b < j->last; ++b) {
+        const cplx* x = j->in + b * j->n;
+        cplx* y = j->out + b * j->n;
+        for (int64_t m = 0; m < j->n; ++m) {
+            double re = 0.0, im = 0.0;
+            for (int64_t l = 0; l < j->L; ++l) {
+                const cplx a = x[(m + l) % j->n];
+                const cplx r = j->ref[l];
+                /* a * conj(r) */
+                re += a.re * r.re + a.im * r.im;
+                im += a.im * r.re - a.re * r.im;
+            }
+            y[m].re = (double)j->n * re;
+            y[m].im = (double)j->n * im;
+        }
+    }
+    return NULL;
+}
+
+int oracle_range_compress(const double* in, double* out, int64_t n, int64_t rows, const double* ref,
+                          int64_t L, int threads)
+{
+    if (n < 1 || rows < 0 || L < 1 || L > n) return 1;
+    if (rows == 0) return 0;
+    int T = resolve_threads(threads, rows);
+    xc_job_t* jobs = (xc_job_t*)calloc((size_t)T, sizeof(xc_job_t));
+    pthread_t* tid = (pthread_t*)calloc((size_t)T, sizeof(pthread_t));
+    int* started = (int*)calloc((size_t)T, sizeof(int));
+    if (!jobs || !tid || !started) { free(jobs); free(tid); free(started); return 1; }
+    int64_t per = rows / T, extra = rows % T, at = 0;
+    for (int t = 0; t < T; ++t) {
+        int64_t c = per + (t < extra ? 1 : 0);
+        xc_job_t jb = { (const cplx*)in, (cplx*)out, (const cplx*)ref, n, L, at, at + c };
+        jobs[t] = jb;
+        at += c;
+    }
+    for (int t = 1; t < T; ++t) {
+        started[t] = pthread_create(&tid[t], NULL, xc_run, &jobs[t]) == 0;
+        if (!started[t]) xc_run(&jobs[t]);
+    }
+    xc_run(&jobs[0]);
+    for (int t = 1; t < T; ++t) if (started[t]) pthread_join(tid[t], NULL);
+    free(jobs); free(tid); free(started);
     return 0;
 }
 

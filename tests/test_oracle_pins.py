@@ -255,3 +255,76 @@ def test_threaded_equals_single_thread():
     a = oracle.fft_radix2(x, FWD, threads=1)
     b = oracle.fft_radix2(x, FWD, threads=4)
     assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- range compression
+def _chirp(L, tb):
+    k = np.arange(L, dtype=np.float64)
+    return np.exp(1j * np.pi * tb * (k / L - 0.5) ** 2)
+
+
+def test_range_compress_tiny_brute_force():
+    # y[m] = n * sum_j x[j] conj(ref_padded[(j - m) mod n]): the same sum indexed
+    # over the data instead of the replica
+    rng = np.random.default_rng(11)
+    for n, L in ((1, 1), (2, 1), (5, 3), (8, 8), (12, 5)):
+        x = rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))
+        ref = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+        pad = np.zeros(n, complex)
+        pad[:L] = ref
+        want = np.zeros((3, n), complex)
+        for b in range(3):
+            for m in range(n):
+                for j in range(n):
+                    want[b, m] += x[b, j] * np.conj(pad[(j - m) % n])
+        want *= n
+        got = oracle.range_compress(x, ref)
+        assert np.allclose(got, want, rtol=1e-13, atol=1e-12)
+
+
+def test_range_compress_matches_transform_product():
+    # the library FFT route B(F(x) conj(F(ref))) = n * ifft(fft(x) conj(fft(ref)))
+    rng = np.random.default_rng(12)
+    n, L = 1024, 200
+    x = rng.standard_normal((4, n)) + 1j * rng.standard_normal((4, n))
+    ref = _chirp(L, 160.0)
+    pad = np.zeros(n, complex)
+    pad[:L] = ref
+    lib = n * np.fft.ifft(np.fft.fft(x, axis=1) * np.conj(np.fft.fft(pad)), axis=1)
+    got = oracle.range_compress(x, ref)
+    assert np.max(np.abs(got - lib)) <= 1e-12 * np.max(np.abs(lib))
+    # and through the oracle's own transforms
+    via = oracle.fft(oracle.fft(x) * np.conj(oracle.fft(pad)), +1)
+    assert np.max(np.abs(got - via)) <= 1e-12 * np.max(np.abs(via))
+
+
+def test_range_compress_single_target_peak_at_delay():
+    # closed form: a unit chirp of length L at delay d with phase phi compresses
+    # to n * L * exp(i phi) at m = d, and |y[m]| <= |y[d]| elsewhere (Cauchy-Schwarz)
+    n, tb = 8192, 500.0
+    L = int(round(1.25 * tb))
+    ref = _chirp(L, tb)
+    for d, phi in ((0, 0.3), (1234, 2.0), (n - L, -1.1)):
+        x = np.zeros(n, complex)
+        x[d:d + L] = np.exp(1j * phi) * ref
+        y = oracle.range_compress(x[None, :], ref)[0]
+        assert int(np.argmax(np.abs(y))) == d
+        assert abs(y[d] - n * L * np.exp(1j * phi)) <= 1e-9 * n * L
+        assert np.all(np.abs(y) <= np.abs(y[d]) * (1 + 1e-12))
+        # the chirp's compressed main lobe is narrow: 3 samples away it is down > 10 dB
+        assert np.abs(y[(d + 3) % n]) < 0.32 * np.abs(y[d])
+
+
+def test_range_compress_shift_and_linearity():
+    rng = np.random.default_rng(13)
+    n, L = 256, 40
+    x = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    z = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    ref = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+    y = oracle.range_compress(x, ref)
+    assert np.allclose(oracle.range_compress(np.roll(x, 17, axis=1), ref), np.roll(y, 17, axis=1), atol=1e-10)
+    a, b = 0.7 - 0.2j, -1.3
+    assert np.allclose(oracle.range_compress(a * x + b * z, ref), a * y + b * oracle.range_compress(z, ref),
+                       atol=1e-10)
+    with pytest.raises(ValueError):
+        oracle.range_compress(x, np.ones(n + 1))
