@@ -64,6 +64,7 @@ typedef enum {
 /* Execution path chosen by the planner. */
 #define FFT_PATH_BLOCK 1      /* one LDS-resident block per transform (N <= block limit) */
 #define FFT_PATH_FOURSTEP 2   /* two block passes, N = N1 * N2 */
+#define FFT_PATH_FILTER 3     /* range compression: forward, filter, backward in one block */
 
 /*
  * fft_plan_create -- plan `batch` transforms of length `n` in `direction`
@@ -86,11 +87,13 @@ fft_status_t fft_plan_create(size_t n, size_t batch, int direction, fft_plan_t* 
 /*
  * fft_execute -- run the planned transforms on `stream`.
  *
- *   in   device pointer to batch * n complex64 values (read only).
- *   out  device pointer to batch * n complex64 values; out == in is allowed
- *        (in-place).  Partial overlap other than out == in is INVALID_ARG.
+ *   in   device pointer to batch * n complex values (read only), complex64
+ *        or, for FFT_STORAGE_F16 plans, FP16 pairs.
+ *   out  device pointer to batch * n complex values of the same storage;
+ *        out == in is allowed (in-place).  Partial overlap other than
+ *        out == in is INVALID_ARG.
  *
- * Both pointers must be 8-byte aligned.  Asynchronous; returns DEVICE when a
+ * Both pointers must be aligned to the element size (8 or 4 bytes).  Asynchronous; returns DEVICE when a
  * launch fails, INVALID_PLAN for a null plan.
  */
 fft_status_t fft_execute(fft_plan_t plan, const void* in, void* out, void* stream);
@@ -131,7 +134,7 @@ const char* fft_status_string(fft_status_t s);
 typedef struct {
     size_t n, batch;
     int direction;
-    int path;                 /* FFT_PATH_BLOCK or FFT_PATH_FOURSTEP */
+    int path;                 /* FFT_PATH_BLOCK, FFT_PATH_FOURSTEP or FFT_PATH_FILTER */
     size_t n1, n2;            /* four-step split (n1: pass-1 column length); 0 for block */
     int n_radix;              /* radix schedule of the block kernel (pass 1 for four-step) */
     int radix[8];
@@ -149,6 +152,8 @@ typedef struct {
     int flags2;               /* variant flags of the pass-2 kernel */
     int c2;                   /* pass-2 rows per workgroup = workspace block width */
     long long grid;           /* workgroups of the (first) launch; 0 from fft_plan_query */
+    int storage;              /* FFT_STORAGE_C64 or FFT_STORAGE_F16 */
+    int device_twiddles;      /* tables evaluated on the GPU */
 } fft_plan_desc_t;
 
 /* ---------------------------------------------------------------------------
@@ -161,6 +166,13 @@ typedef struct {
 #define FFT_VARIANT_SWIZZLE 8     /* XOR-swizzled unpadded LDS layout */
 #define FFT_VARIANT_STAGED 16     /* four-step pass 1: outputs staged through LDS, contiguous stores */
 #define FFT_VARIANT_TWIDDLE_POWERS 32 /* stage twiddles from per-row powers w^(2^i) and products */
+#define FFT_VARIANT_FP16_STORAGE 64   /* data stored as FP16 pairs, FP32 arithmetic */
+
+/* Storage of the transform data (fft_plan_opts_t.storage). */
+#define FFT_STORAGE_C64 0   /* interleaved FP32 (re, im), 8 bytes per value */
+#define FFT_STORAGE_F16 1   /* interleaved IEEE FP16 (re, im), 4 bytes per value; arithmetic stays FP32
+                               (values are widened on load and rounded to nearest even on store);
+                               the four-step workspace stays FP32 */
 
 typedef struct {
     size_t block_limit;  /* longest single-block length; 0 = fft_block_limit() */
@@ -170,6 +182,9 @@ typedef struct {
     int c;               /* four-step pass-1 columns per workgroup; 0 = default */
     int flags2;          /* variant of pass 2; -1 = default */
     int c2;              /* pass-2 rows per workgroup (workspace block width); 0 = default */
+    int storage;         /* FFT_STORAGE_C64 (default) or FFT_STORAGE_F16 */
+    int device_twiddles; /* nonzero: evaluate the twiddle tables in FP64 on the GPU
+                            (default: FP64 on the host); both round once to FP32 */
 } fft_plan_opts_t;
 
 /* Fill `opts` with "use the defaults". */
@@ -187,6 +202,7 @@ fft_status_t fft_plan_query_ex(size_t n, size_t batch, int direction, const fft_
 #define FFT_KERNEL_BLOCK 0
 #define FFT_KERNEL_PASS1 1
 #define FFT_KERNEL_PASS2 2
+#define FFT_KERNEL_FILTER 3
 
 typedef struct {
     int kind;            /* FFT_KERNEL_* */
@@ -208,6 +224,26 @@ fft_status_t fft_kernel_info(int index, fft_kernel_info_t* info);
 
 /* Fill `desc` for a plan.  INVALID_PLAN / INVALID_ARG on null arguments. */
 fft_status_t fft_plan_describe(fft_plan_t plan, fft_plan_desc_t* desc);
+
+/*
+ * fft_execute_ex -- fft_execute with the batch and the workspace given per call.
+ *   batch      transforms of this call, any number >= 1 (0 = the plan's batch);
+ *              the plan's tables do not depend on it.
+ *   workspace  four-step plans: DEVICE pointer to n * batch complex64 values
+ *              (8-byte aligned, overlapping neither in nor out) used instead
+ *              of the plan's own workspace, or NULL for the plan's own (then
+ *              batch must not exceed the plan's).  Ignored on other paths.
+ * With an external workspace one plan may run on several streams at once.
+ * Errors as fft_execute, plus INVALID_ARG for a batch the plan's workspace
+ * cannot hold or a bad workspace pointer.
+ */
+fft_status_t fft_execute_ex(fft_plan_t plan, size_t batch, const void* in, void* out, void* workspace,
+                            void* stream);
+
+/* Copy the plan's twiddle table (complex64 entries) to host memory: the
+ * number of entries goes to *n_entries; with host_dst NULL only the count is
+ * returned; max_entries below the count is INVALID_ARG.  Synchronous. */
+fft_status_t fft_plan_twiddles(fft_plan_t plan, void* host_dst, size_t max_entries, size_t* n_entries);
 
 /* Dry-run planning: fill `desc` with the path, split and kernels that
  * fft_plan_create would choose for (n, batch, direction), without touching a
@@ -315,6 +351,41 @@ fft_status_t fft_wisdom_save(const char* path);
 fft_status_t fft_wisdom_load(const char* path);
 
 /* ---------------------------------------------------------------------------
+ * Range compression (radar chain, "Radar application description", Fig. 3:
+ * the range lines are compressed after the range FFT by the matched filter).
+ * ------------------------------------------------------------------------- */
+
+/*
+ * fft_filter_create -- plan the range compression of `batch` rows of length n
+ * against a transmitted pulse replica of replica_len <= n samples:
+ *
+ *     y = B(F(x) .* conj(F(r)))   per row,  r = replica zero-padded to n,
+ *
+ * F the forward and B the unnormalised backward transform, which equals the
+ * circular cross-correlation y[m] = n * sum_{l<L} x[(m + l) mod n] conj(r[l]);
+ * a target echo delayed by d samples compresses to a peak at m = d.  One
+ * workgroup runs the forward transform, the product and the backward
+ * transform of a row in LDS, so a row is read and written once.
+ *
+ *   replica  DEVICE pointer to replica_len complex64 values (8-byte aligned);
+ *            read during this call only (the plan keeps F(r) in its table,
+ *            computed on the device with this library's forward transform).
+ *   opts     may be NULL; flags / radix select a catalogue variant,
+ *            device_twiddles as for fft_plan_create_ex; storage must be 0.
+ *
+ * n: a power of two from 64 to 16384.  Execute with fft_execute(plan, in,
+ * out, stream) (direction is ignored; in == out allowed).  Synchronous.
+ * Errors: INVALID_ARG (null or misaligned pointers, zero sizes, replica_len
+ * > n, storage != 0), UNSUPPORTED_SIZE (other n), OUT_OF_MEMORY, DEVICE.
+ */
+fft_status_t fft_filter_create(size_t n, size_t batch, const void* replica, size_t replica_len,
+                               const fft_plan_opts_t* opts, fft_plan_t* plan_out);
+
+/* Dry run of fft_filter_create's planning (no device needed). */
+fft_status_t fft_filter_query(size_t n, size_t batch, size_t replica_len, const fft_plan_opts_t* opts,
+                              fft_plan_desc_t* desc);
+
+/* ---------------------------------------------------------------------------
  * Ragged batches: transforms of several lengths in one submission.
  * ------------------------------------------------------------------------- */
 typedef struct fft_ragged_s* fft_ragged_t;
@@ -330,9 +401,15 @@ typedef struct fft_ragged_s* fft_ragged_t;
 fft_status_t fft_ragged_create(const size_t* sizes, const size_t* counts, size_t n_classes, int direction,
                                fft_ragged_t* out);
 
+/* As fft_ragged_create; of `opts` (may be NULL) only `storage` and
+ * `device_twiddles` are used, for every class.  With FFT_STORAGE_F16 the data
+ * of execute are FP16 pairs (4 bytes per value, 4-byte alignment). */
+fft_status_t fft_ragged_create_ex(const size_t* sizes, const size_t* counts, size_t n_classes, int direction,
+                                  const fft_plan_opts_t* opts, fft_ragged_t* out);
+
 /*
  * fft_ragged_execute -- transform every class from `in` to `out` on `stream`
- * (device pointers, 8-byte aligned, in == out allowed, other overlap
+ * (device pointers aligned to the element size, in == out allowed, other overlap
  * INVALID_ARG).  mode 0: one hipGraphLaunch of a graph holding every class's
  * kernels on parallel branches (captured on the first call with this (in, out)
  * pair, re-captured when the pair changes); mode 1: the classes' kernels

@@ -125,12 +125,15 @@ static Wisdom& wisdom()
     return w;
 }
 
+// Wisdom applies to complex64 plans: FP16-storage kernels are never chosen.
+static bool wisdom_eligible(const KEntry& k) { return (k.flags & FFT_VARIANT_FP16_STORAGE) == 0; }
+
 static const KEntry* find_named(int kind, size_t n, const std::string& name)
 {
     int c = 0;
     const KEntry* t = kernel_table(&c);
     for (int i = 0; i < c; ++i)
-        if (t[i].kind == kind && (size_t)t[i].n == n && name == t[i].name) return &t[i];
+        if (t[i].kind == kind && (size_t)t[i].n == n && name == t[i].name && wisdom_eligible(t[i])) return &t[i];
     return nullptr;
 }
 
@@ -356,9 +359,9 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
     if (four) {
         // pass-1 x pass-2 pairs (schedules, column/row widths, variants)
         for (int i = 0; i < count && e == hipSuccess; ++i) {
-            if (t[i].kind != kKindPass1 || (size_t)t[i].n != dq.n1 || dq.n2 % t[i].c) continue;
+            if (t[i].kind != kKindPass1 || (size_t)t[i].n != dq.n1 || dq.n2 % t[i].c || !wisdom_eligible(t[i])) continue;
             for (int j = 0; j < count && e == hipSuccess && rep->n_candidates < 32; ++j) {
-                if (t[j].kind != kKindPass2 || (size_t)t[j].n != dq.n2 || dq.n1 % t[j].c) continue;
+                if (t[j].kind != kKindPass2 || (size_t)t[j].n != dq.n2 || dq.n1 % t[j].c || !wisdom_eligible(t[j])) continue;
                 fft_plan_opts_t o;
                 fft_plan_opts_init(&o);
                 o.flags = t[i].flags;
@@ -387,7 +390,7 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
         }
     }
     for (int i = 0; i < count && e == hipSuccess && rep->n_candidates < 32 && !four; ++i) {
-        if (t[i].kind != kKindBlock || (size_t)t[i].n != n) continue;
+        if (t[i].kind != kKindBlock || (size_t)t[i].n != n || !wisdom_eligible(t[i])) continue;
         fft_plan_opts_t o;
         fft_plan_opts_init(&o);
         o.n_radix = t[i].nr;
@@ -433,7 +436,8 @@ fft_status_t fft_wisdom_set(size_t n, int kernel_index)
 {
     int c = 0;
     const KEntry* t = kernel_table(&c);
-    if (kernel_index < 0 || kernel_index >= c || t[kernel_index].kind != kKindBlock || (size_t)t[kernel_index].n != n)
+    if (kernel_index < 0 || kernel_index >= c || t[kernel_index].kind != kKindBlock || (size_t)t[kernel_index].n != n ||
+        !wisdom_eligible(t[kernel_index]))
         return FFT_ERR_INVALID_ARG;
     Wisdom& w = wisdom();
     std::lock_guard<std::mutex> lk(w.mu);
@@ -502,12 +506,13 @@ fft_status_t fft_wisdom_load(const char* path)
         }
         bool known = false;
         if (b.empty()) {
-            for (int i = 0; i < c; ++i) known = known || (t[i].kind == kKindBlock && (size_t)t[i].n == n && a == t[i].name);
+            for (int i = 0; i < c; ++i)
+                known = known || (t[i].kind == kKindBlock && (size_t)t[i].n == n && a == t[i].name && wisdom_eligible(t[i]));
         } else {
             bool k1 = false, k2 = false;
             for (int i = 0; i < c; ++i) {
-                k1 = k1 || (t[i].kind == kKindPass1 && a == t[i].name);
-                k2 = k2 || (t[i].kind == kKindPass2 && b == t[i].name);
+                k1 = k1 || (t[i].kind == kKindPass1 && a == t[i].name && wisdom_eligible(t[i]));
+                k2 = k2 || (t[i].kind == kKindPass2 && b == t[i].name && wisdom_eligible(t[i]));
             }
             known = k1 && k2;
         }

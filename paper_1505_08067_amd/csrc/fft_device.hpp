@@ -374,6 +374,8 @@ enum : int {
 };
 
 typedef float v2f_t __attribute__((ext_vector_type(2)));
+// Two IEEE half values: the storage element of the FP16-storage form.
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
 
 template <int FL>
 __device__ __forceinline__ float2 gload(const float2* p)
@@ -384,6 +386,30 @@ __device__ __forceinline__ float2 gload(const float2* p)
     } else {
         return *p;
     }
+}
+
+// FP16 storage: widened to FP32 on load, rounded to nearest even on store.
+template <int FL>
+__device__ __forceinline__ float2 gload(const h2_t* p)
+{
+    h2_t h;
+    if constexpr ((FL & kNtLoad) != 0)
+        h = __builtin_nontemporal_load(p);
+    else
+        h = *p;
+    return make_float2((float)h.x, (float)h.y);
+}
+
+template <int FL>
+__device__ __forceinline__ void gstore(h2_t* p, float2 v)
+{
+    h2_t h;
+    h.x = (_Float16)v.x;
+    h.y = (_Float16)v.y;
+    if constexpr ((FL & kNtStore) != 0)
+        __builtin_nontemporal_store(h, p);
+    else
+        *p = h;
 }
 
 template <int FL>

@@ -65,14 +65,18 @@ __host__ __device__ constexpr int lds_stride()
 }
 
 // ----------------------------------------------------------------- policies
-struct PolBlock {
+// TI / TO: element type of the data in HBM -- float2 (complex64) or h2_t
+// (two FP16 values, the storage-only half precision form); arithmetic is
+// always FP32.  The four-step workspace is always complex64.
+template <typename TI, typename TO>
+struct PolBlockT {
     static constexpr bool f_fast = false;
     static constexpr bool conj_in = true;
     static constexpr bool conj_out = true;
     static constexpr int kind = kKindBlock;
     struct Ctx {
-        const float2* src;
-        float2* dst;
+        const TI* src;
+        TO* dst;
         bool act;
     };
     template <int N, int C>
@@ -82,12 +86,12 @@ struct PolBlock {
         Ctx c;
         c.act = b < a.batch;
         const long long bb = c.act ? b : 0;
-        c.src = a.in + bb * N;
-        c.dst = a.out + bb * N;
+        c.src = reinterpret_cast<const TI*>(a.in) + bb * N;
+        c.dst = reinterpret_cast<TO*>(a.out) + bb * N;
         return c;
     }
     template <int C>
-    __device__ static const float2* in_at(const KArgs&, const Ctx& c, int n)
+    __device__ static const TI* in_at(const KArgs&, const Ctx& c, int n)
     {
         return c.src + n;
     }
@@ -102,14 +106,43 @@ struct PolBlock {
     }
     __host__ __device__ static long long units(const KArgs& a, int C) { return (a.batch + C - 1) / C; }
 };
+using PolBlock = PolBlockT<float2, float2>;
+using PolBlockH = PolBlockT<h2_t, h2_t>;
 
-struct PolPass1 {
+// List launches: transform b of the launch reads and writes where its
+// descriptor points (the block layout otherwise).
+struct PolList : PolBlock {
+    static constexpr int kind = kKindList;
+    template <int N, int C>
+    __device__ static Ctx ctx(const KArgs& a, long long unit, int f)
+    {
+        const long long b = unit * C + f;
+        Ctx c;
+        c.act = b < a.batch;
+        const ListEnt e = reinterpret_cast<const ListEnt*>(a.list)[c.act ? b : 0];
+        c.src = e.in;
+        c.dst = e.out;
+        return c;
+    }
+};
+
+// Range compression: the block layout, a forward transform, the product with
+// the conjugate replica spectrum and the backward transform, all in one
+// workgroup (the conjugations are explicit, not direction dependent).
+struct PolFilt : PolBlock {
+    static constexpr bool conj_in = false;
+    static constexpr bool conj_out = false;
+    static constexpr int kind = kKindFilter;
+};
+
+template <typename TI>
+struct PolPass1T {
     static constexpr bool f_fast = true;
     static constexpr bool conj_in = true;
     static constexpr bool conj_out = false;
     static constexpr int kind = kKindPass1;
     struct Ctx {
-        const float2* src;
+        const TI* src;
         float2* dst;
         unsigned col;
         bool act;
@@ -122,12 +155,12 @@ struct PolPass1 {
         Ctx c;
         c.col = (unsigned)(tile * C + f);
         c.act = true;
-        c.src = a.in + bt * a.nbig + c.col;
+        c.src = reinterpret_cast<const TI*>(a.in) + bt * a.nbig + c.col;
         c.dst = a.out + bt * a.nbig + ((long long)c.col << a.cw_bits);
         return c;
     }
     template <int C>
-    __device__ static const float2* in_at(const KArgs& a, const Ctx& c, int n)
+    __device__ static const TI* in_at(const KArgs& a, const Ctx& c, int n)
     {
         return c.src + (long long)n * a.n_other;
     }
@@ -194,15 +227,18 @@ struct PolPass1 {
     }
     __host__ __device__ static long long units(const KArgs& a, int) { return a.batch * a.tiles; }
 };
+using PolPass1 = PolPass1T<float2>;
+using PolPass1H = PolPass1T<h2_t>;
 
-struct PolPass2 {
+template <typename TO>
+struct PolPass2T {
     static constexpr bool f_fast = true;
     static constexpr bool conj_in = false;
     static constexpr bool conj_out = true;
     static constexpr int kind = kKindPass2;
     struct Ctx {
         const float2* src;
-        float2* dst;
+        TO* dst;
         bool act;
     };
     template <int N, int C>
@@ -213,7 +249,7 @@ struct PolPass2 {
         Ctx c;
         c.act = true;
         c.src = a.in + bt * a.nbig + (long long)g * N * C + f;
-        c.dst = a.out + bt * a.nbig + (long long)g * C + f;
+        c.dst = reinterpret_cast<TO*>(a.out) + bt * a.nbig + (long long)g * C + f;
         return c;
     }
     template <int C>
@@ -232,6 +268,8 @@ struct PolPass2 {
     }
     __host__ __device__ static long long units(const KArgs& a, int) { return a.batch * a.tiles; }
 };
+using PolPass2 = PolPass2T<float2>;
+using PolPass2H = PolPass2T<h2_t>;
 
 // --------------------------------------------------------------- the stages
 // v holds the stage-0 inputs x[t + i*T + r*N/R0] on entry and the outputs
@@ -379,6 +417,38 @@ k_fft(KArgs a)
     };
     auto finish = [&](float2(&v)[E], long long unit) {
         run_stages<N, E, S, FL>(v, L, a.tw, Ltw, t);
+        if constexpr (P::kind == kKindFilter) {
+            // Z = X conj(H) is transformed back as conj(F(conj Z)), and
+            // conj Z = conj(X) H: X[k] sits at v[i RL + q], k = t + i T + q NsL.
+#pragma unroll
+            for (int i = 0; i < E / RL; ++i)
+#pragma unroll
+                for (int q = 0; q < RL; ++q) {
+                    const float2 h = a.flt[t + i * T + q * NsL];
+                    const float2 x = v[i * RL + q];
+                    v[i * RL + q] = cmul(make_float2(x.x, -x.y), h);
+                }
+            if constexpr (NST > 1) {
+                __syncthreads();  // every read of the last stage precedes the next writes
+                if constexpr (R0 != RL) {
+                    // natural order through LDS, then the stage-0 gather
+#pragma unroll
+                    for (int i = 0; i < E / RL; ++i)
+#pragma unroll
+                        for (int q = 0; q < RL; ++q) L[lds_at<FL>(t + i * T + q * NsL)] = v[i * RL + q];
+                    __syncthreads();
+#pragma unroll
+                    for (int i = 0; i < E / R0; ++i)
+#pragma unroll
+                        for (int r = 0; r < R0; ++r) v[i * R0 + r] = L[lds_at<FL>(t + i * T + r * (N / R0))];
+                    __syncthreads();
+                }
+                // with R0 == RL the outputs already sit where stage 0 wants its inputs
+            }
+            run_stages<N, E, S, FL>(v, L, a.tw, Ltw, t);
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
+        }
         const auto cx = P::template ctx<N, C>(a, unit, f);
         P::template twiddle_outputs<N, E, T, RL, NsL, FL>(a, cx, t, v);
         if constexpr ((FL & kStaged) != 0) {

@@ -38,8 +38,14 @@ struct fft_plan_s {
     float2* tw = nullptr;           // one allocation holding every table
     size_t tw_bytes = 0;
     size_t off_s1 = 0, off_s2 = 0, off_hi = 0, off_lo = 0, off_col = 0;  // in complex entries
+    size_t off_flt = 0;             // range compression: spectrum of the pulse replica
     float2* work = nullptr;
     size_t work_bytes = 0;
+    std::vector<TwSeg> segs;        // layout of the twiddle table
+    int storage = 0;                // 0: complex64 data, 1: FP16 pairs
+    int device_twiddles = 0;        // tables generated on the device
+    int cus = 0;                    // compute units of the plan's device
+    const KEntry* klist = nullptr;  // list form of k1 (same schedule and shape), if compiled
 };
 
 namespace fb {
@@ -47,11 +53,15 @@ namespace fb {
 static std::vector<KEntry> build_table()
 {
     std::vector<KEntry> v;
-    int nb = 0, np = 0;
+    int nb = 0, np = 0, nf = 0, nl = 0;
     const KEntry* b = block_entries(&nb);
     const KEntry* p = pass_entries(&np);
+    const KEntry* f = filter_entries(&nf);
+    const KEntry* l = list_entries(&nl);
     v.insert(v.end(), b, b + nb);
     v.insert(v.end(), p, p + np);
+    v.insert(v.end(), f, f + nf);
+    v.insert(v.end(), l, l + nl);
     return v;
 }
 
@@ -67,13 +77,14 @@ const KEntry* kernel_table(int* count)
     return table().data();
 }
 
-const KEntry* kernel_default(int kind, int n, int c)
+const KEntry* kernel_default(int kind, int n, int c, int storage)
 {
     const KEntry* any = nullptr;
     for (const KEntry& k : table()) {
         if (k.kind != kind || k.n != n || (c > 0 && k.c != c)) continue;
+        if (((k.flags & FFT_VARIANT_FP16_STORAGE) != 0) != (storage != 0)) continue;
         if (k.is_default) return &k;
-        if (!any && k.flags == 0) any = &k;
+        if (!any && (k.flags & ~FFT_VARIANT_FP16_STORAGE) == 0) any = &k;
     }
     return any;
 }
@@ -97,7 +108,7 @@ const KEntry* kernel_find(int kind, int n, const int* radix, int nr, int c, int 
 
 long long kernel_units(const KEntry& k, const KArgs& a)
 {
-    if (k.kind == kKindBlock) return (a.batch + k.c - 1) / k.c;
+    if (k.kind == kKindBlock || k.kind == kKindFilter || k.kind == kKindList) return (a.batch + k.c - 1) / k.c;
     return a.batch * a.tiles;
 }
 
@@ -167,73 +178,85 @@ float2 root_f32(long long m, long long n)
     return make_float2((float)re, (float)im);  // one round-to-nearest-even from FP64
 }
 
-// Stage twiddle rows of a radix schedule: for stage s >= 1 with radix R and
-// Ns points already combined, row k < Ns holds exp(-2 pi i r k / (Ns R)), r < R.
-void fill_stage_table(const int* radix, int nr, float2* dst)
+// (m, n) of one table entry, per segment type (see TwSeg in internal.hpp).
+bool seg_entry(const TwSeg& g, long long e, long long* m, long long* n)
 {
-    size_t at = 0;
-    long long ns = radix[0];
-    for (int s = 1; s < nr; ++s) {
-        const int R = radix[s];
-        for (long long k = 0; k < ns; ++k)
-            for (int r = 0; r < R; ++r) dst[at++] = root_f32((long long)r * k, ns * R);
-        at = (at + 1) & ~(size_t)1;  // stage blocks start on even entries
-        ns *= R;
+    switch (g.type) {
+        case kSegRows: *m = (e % g.b) * (e / g.b); *n = g.a * g.b; return true;
+        case kSegPow: {
+            const long long i = e % g.c;
+            if (i >= g.d) return false;
+            *m = (e / g.c) << i;
+            *n = g.a * g.b;
+            return true;
+        }
+        case kSegHi: *m = e << g.b; *n = g.a; return true;
+        case kSegLo: *m = e; *n = g.a; return true;
+        case kSegCol: {
+            const long long i = e % g.c;
+            if ((1LL << i) >= g.d) return false;
+            *m = (((e / g.c) * g.b) << i) % g.a;
+            *n = g.a;
+            return true;
+        }
     }
+    return false;
 }
 
-// The same twiddles in the factorised layout of persistent kernels: a stage
-// with Ns <= 16 keeps full rows; a larger stage stores A[q][r] =
-// exp(-2 pi i r q / (Q R)), q < Q, then B[p][r] = exp(-2 pi i r p / (Ns R)),
-// p < M, where Q is the largest power of two with Q*Q <= Ns and M = Ns / Q.
-void fill_stage_table_factored(const int* radix, int nr, float2* dst)
+void eval_segments_host(const std::vector<TwSeg>& segs, float2* dst)
 {
-    size_t at = 0;
-    long long ns = radix[0];
-    for (int s = 1; s < nr; ++s) {
-        const int R = radix[s];
-        if (ns <= 16) {
-            for (long long k = 0; k < ns; ++k)
-                for (int r = 0; r < R; ++r) dst[at++] = root_f32((long long)r * k, ns * R);
+    for (const TwSeg& g : segs)
+        for (long long e = 0; e < g.count; ++e) {
+            long long m = 0, n = 1;
+            dst[g.offset + e] = seg_entry(g, e, &m, &n) ? root_f32(m, n) : make_float2(0.f, 0.f);
+        }
+}
+
+int bits_of(int v)
+{
+    int b = 0;
+    while (v > 0) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+// Segments of a kernel's stage table starting at `at` (entries); returns the end.
+long long stage_segments(const KEntry* k, long long at, std::vector<TwSeg>& segs)
+{
+    long long ns = k->radix[0];
+    for (int s = 1; s < k->nr; ++s) {
+        const long long R = k->radix[s];
+        if (k->flags & FFT_VARIANT_PERSISTENT) {
+            // factorised rows: full rows for Ns <= 16, else A (Q rows of the
+            // Q R-th roots) then B (the first M rows of the Ns R-th roots)
+            if (ns <= 16) {
+                segs.push_back({kSegRows, at, ns * R, ns, R, 0, 0});
+                at += ns * R;
+            } else {
+                long long Q = 1;
+                while (4 * Q * Q <= ns) Q *= 2;
+                const long long M = ns / Q;
+                segs.push_back({kSegRows, at, Q * R, Q, R, 0, 0});
+                at += Q * R;
+                segs.push_back({kSegRows, at, M * R, ns, R, 0, 0});
+                at += M * R;
+            }
+        } else if (k->flags & FFT_VARIANT_TWIDDLE_POWERS) {
+            // power rows: w^(2^i) for 2^i < R, padded to an even count
+            const int P = bits_of((int)R - 1);
+            const int row = (P + 1) & ~1;
+            segs.push_back({kSegPow, at, ns * row, ns, R, row, P});
+            at += ns * row;
         } else {
-            long long Q = 1;
-            while (4 * Q * Q <= ns) Q *= 2;
-            const long long M = ns / Q;
-            for (long long q = 0; q < Q; ++q)
-                for (int r = 0; r < R; ++r) dst[at++] = root_f32((long long)r * q, Q * R);
-            for (long long p = 0; p < M; ++p)
-                for (int r = 0; r < R; ++r) dst[at++] = root_f32((long long)r * p, ns * R);
+            // exact rows, each stage's block padded to an even count
+            segs.push_back({kSegRows, at, ns * R, ns, R, 0, 0});
+            at += (ns * R + 1) & ~1LL;
         }
         ns *= R;
     }
-}
-
-// Power layout: row k of stage s holds w^(2^i), i < log2(R), for
-// w = exp(-2 pi i k / (Ns R)), padded to an even number of entries.
-void fill_stage_table_powers(const int* radix, int nr, float2* dst)
-{
-    size_t at = 0;
-    long long ns = radix[0];
-    for (int s = 1; s < nr; ++s) {
-        const int R = radix[s];
-        int lg = 0;  // number of bits of R - 1: powers 2^i < R
-        while ((1 << lg) <= R - 1) ++lg;
-        const int row = (lg + 1) & ~1;
-        for (long long k = 0; k < ns; ++k)
-            for (int i = 0; i < row; ++i)
-                dst[at++] = i < lg ? root_f32((long long)(1LL << i) * k, ns * R) : make_float2(0.f, 0.f);
-        ns *= R;
-    }
-}
-
-void fill_kernel_table(const KEntry* k, float2* dst)
-{
-    if (k->flags & FFT_VARIANT_PERSISTENT)
-        fill_stage_table_factored(k->radix, k->nr, dst);
-    else if (k->flags & FFT_VARIANT_TWIDDLE_POWERS)
-        fill_stage_table_powers(k->radix, k->nr, dst);
-    else
-        fill_stage_table(k->radix, k->nr, dst);
+    return at;
 }
 
 size_t env_size(const char* name, size_t dflt)
@@ -296,6 +319,8 @@ void fft_plan_opts_init(fft_plan_opts_t* o)
     std::memset(o, 0, sizeof(*o));
     o->flags = -1;
     o->flags2 = -1;
+    o->storage = 0;
+    o->device_twiddles = 0;
 }
 
 size_t fft_block_max(size_t lds_bytes, int k)
@@ -346,7 +371,7 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
     if (n == 0 || batch == 0) return FFT_ERR_INVALID_ARG;
     if (direction != FFT_FORWARD && direction != FFT_BACKWARD) return FFT_ERR_INVALID_ARG;
     if (n > kMaxN) return FFT_ERR_UNSUPPORTED_SIZE;
-    if (!is_pow2(n) && (n > kDefaultBlockLimit || !kernel_default(kKindBlock, (int)n, 0)))
+    if (!is_pow2(n) && (n > kDefaultBlockLimit || !kernel_default(kKindBlock, (int)n, 0, 0)))
         return FFT_ERR_UNSUPPORTED_SIZE;  // other lengths: the compiled mixed-radix blocks only
     if (batch > ((size_t)1 << 40) / n) return FFT_ERR_INVALID_ARG;
     fft_plan_opts_t o;
@@ -356,20 +381,27 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
     p->n = n;
     p->batch = batch;
     p->direction = direction;
+    if (o.storage != 0 && o.storage != 1) return FFT_ERR_INVALID_ARG;
+    if (o.flags >= 0 && (((o.flags & FFT_VARIANT_FP16_STORAGE) != 0) != (o.storage != 0))) return FFT_ERR_INVALID_ARG;
+    p->storage = o.storage;
+    p->device_twiddles = o.device_twiddles ? 1 : 0;
+    const int sto = o.storage;
     const size_t limit = o.block_limit ? sanitize_limit(o.block_limit) : fft_block_limit();
-    size_t off = 0;
+    long long off = 0;
+    p->segs.clear();
     if (n == 1) {
         p->path = FFT_PATH_BLOCK;
     } else if (n <= limit || !is_pow2(n)) {
         p->path = FFT_PATH_BLOCK;
         if (o.n_radix == 0 && o.flags < 0) {
-            p->k1 = wisdom_kernel(n);
-            if (!p->k1) p->k1 = kernel_default(kKindBlock, (int)n, 0);
+            p->k1 = sto ? nullptr : wisdom_kernel(n);
+            if (!p->k1) p->k1 = kernel_default(kKindBlock, (int)n, 0, sto);
+        } else {
+            const int fl = o.flags < 0 ? (sto ? FFT_VARIANT_FP16_STORAGE : 0) : o.flags;
+            p->k1 = kernel_find(kKindBlock, (int)n, o.radix, o.n_radix, 0, fl);
         }
-        else
-            p->k1 = kernel_find(kKindBlock, (int)n, o.radix, o.n_radix, 0, o.flags < 0 ? 0 : o.flags);
         if (!p->k1) return FFT_ERR_UNSUPPORTED_SIZE;
-        off = round_up((size_t)p->k1->tw_size, 32);
+        off = stage_segments(p->k1, 0, p->segs);
     } else {
         p->path = FFT_PATH_FOURSTEP;
         const int L = ilog2(n);
@@ -378,31 +410,40 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
         const int c1 = o.c > 0 ? o.c : (int)env_size("FFTBLOCK_FOURSTEP_C", 0);
         const int c2 = o.c2 > 0 ? o.c2 : (int)env_size("FFTBLOCK_FOURSTEP_C2", 0);
         const bool explicit_opts = o.flags >= 0 || o.flags2 >= 0 || o.c > 0 || o.c2 > 0;
-        if (explicit_opts || !wisdom_pair(n, p->n1, p->n2, &p->k1, &p->k2)) {
-            p->k1 = o.flags < 0 ? kernel_default(kKindPass1, (int)p->n1, c1)
+        if (explicit_opts || sto || !wisdom_pair(n, p->n1, p->n2, &p->k1, &p->k2)) {
+            p->k1 = o.flags < 0 ? kernel_default(kKindPass1, (int)p->n1, c1, sto)
                                 : kernel_find(kKindPass1, (int)p->n1, nullptr, 0, c1, o.flags);
-            p->k2 = o.flags2 < 0 ? kernel_default(kKindPass2, (int)p->n2, c2)
+            p->k2 = o.flags2 < 0 ? kernel_default(kKindPass2, (int)p->n2, c2, sto)
                                  : kernel_find(kKindPass2, (int)p->n2, nullptr, 0, c2, o.flags2);
         }
         if (!p->k1 || !p->k2) return FFT_ERR_UNSUPPORTED_SIZE;
+        if (((p->k2->flags & FFT_VARIANT_FP16_STORAGE) != 0) != (sto != 0)) return FFT_ERR_INVALID_ARG;
         if (p->n2 % p->k1->c || p->n1 % p->k2->c) return FFT_ERR_UNSUPPORTED_SIZE;
         p->lo_bits = (L + 1) / 2;
         p->cw_bits = log2i(p->k2->c);
-        off = round_up((size_t)p->k1->tw_size, 32);
-        p->off_s2 = off;
-        off += round_up((size_t)p->k2->tw_size, 32);
-        p->off_hi = off;
-        off += round_up(n >> p->lo_bits, 32);
-        p->off_lo = off;
-        off += round_up(size_t(1) << p->lo_bits, 32);
+        const long long N = (long long)n;
+        p->off_s1 = 0;
+        off = (long long)round_up((size_t)stage_segments(p->k1, 0, p->segs), 32);
+        p->off_s2 = (size_t)off;
+        off = (long long)round_up((size_t)stage_segments(p->k2, off, p->segs), 32);
+        p->off_hi = (size_t)off;
+        p->segs.push_back({kSegHi, off, N >> p->lo_bits, N, p->lo_bits, 0, 0});
+        off += (long long)round_up((size_t)(N >> p->lo_bits), 32);
+        p->off_lo = (size_t)off;
+        p->segs.push_back({kSegLo, off, 1LL << p->lo_bits, N, 0, 0, 0});
+        off += (long long)round_up(size_t(1) << p->lo_bits, 32);
         if (p->k1->flags & FFT_VARIANT_TWIDDLE_POWERS) {
-            p->off_col = off;
-            off += round_up(p->n2 * (size_t)col_row(p->k1->e), 32);
+            // row col: exp(-2 pi i col T 2^i / N) for 2^i < E, T = N1 / E threads per column
+            const int row = col_row(p->k1->e);
+            p->off_col = (size_t)off;
+            p->segs.push_back({kSegCol, off, (long long)p->n2 * row, N, (long long)p->n1 / p->k1->e, row, p->k1->e});
+            off += (long long)round_up(p->n2 * (size_t)row, 32);
         }
         p->work_bytes = n * batch * sizeof(float2);
     }
-    p->tw_bytes = off * sizeof(float2);
-    *table_entries = off;
+    off = (long long)round_up((size_t)off, 32);
+    p->tw_bytes = (size_t)off * sizeof(float2);
+    *table_entries = (size_t)off;
     return FFT_SUCCESS;
 }
 
@@ -413,8 +454,9 @@ static KArgs make_args(const fft_plan_s* p, int pass, const float2* in, float2* 
     a.out = out;
     a.batch = (long long)p->batch;
     a.sg = p->direction == FFT_FORWARD ? 1.0f : -1.0f;
-    if (p->path == FFT_PATH_BLOCK) {
+    if (p->path == FFT_PATH_BLOCK || p->path == FFT_PATH_FILTER) {
         a.tw = p->tw + p->off_s1;
+        if (p->path == FFT_PATH_FILTER) a.flt = p->tw + p->off_flt;
         return a;
     }
     a.nbig = (long long)p->n;
@@ -448,6 +490,8 @@ static void describe(const fft_plan_s* plan, fft_plan_desc_t* d)
     d->twiddle_bytes = plan->tw_bytes;
     d->kernels_per_execute = plan->path == FFT_PATH_FOURSTEP ? 2 : 1;
     d->grid = plan->grid1;
+    d->storage = plan->storage;
+    d->device_twiddles = plan->device_twiddles;
     if (!plan->k1) {
         d->kernel_name = "copy";
         return;
@@ -496,20 +540,10 @@ static long long grid_for(const KEntry* k, const KArgs& a, int cus)
     return units < cap ? units : cap;
 }
 
-fft_status_t fft_plan_create_ex(size_t n, size_t batch, int direction, const fft_plan_opts_t* opts,
-                                fft_plan_t* plan_out)
+// Device resources of a chosen plan (table of `off` entries, workspace),
+// then registration.  Takes ownership of p (deleted on failure).
+static fft_status_t plan_materialize(fft_plan_s* p, size_t off, fft_plan_t* plan_out)
 {
-    if (plan_out == nullptr) return FFT_ERR_INVALID_ARG;
-    *plan_out = nullptr;
-    fft_plan_s* p = new (std::nothrow) fft_plan_s();
-    if (!p) return FFT_ERR_OUT_OF_MEMORY;
-    size_t off = 0;
-    const fft_status_t st = plan_choose(n, batch, direction, opts, p, &off);
-    if (st != FFT_SUCCESS) {
-        delete p;
-        return st;
-    }
-
     hipError_t e = hipGetDevice(&p->device);
     int cus = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
@@ -519,32 +553,44 @@ fft_status_t fft_plan_create_ex(size_t n, size_t batch, int direction, const fft
     }
     if (p->k1) p->grid1 = grid_for(p->k1, make_args(p, 1, nullptr, nullptr), cus);
     if (p->k2) p->grid2 = grid_for(p->k2, make_args(p, 2, nullptr, nullptr), cus);
+    p->cus = cus;
+    if (p->path == FFT_PATH_BLOCK && p->k1 && p->storage == 0 && (p->k1->flags & FFT_VARIANT_PERSISTENT) == 0) {
+        int c = 0;
+        const KEntry* t = kernel_table(&c);
+        for (int i = 0; i < c && !p->klist; ++i) {
+            const KEntry& k = t[i];
+            if (k.kind != kKindList || k.n != p->k1->n || k.e != p->k1->e || k.c != p->k1->c ||
+                k.flags != p->k1->flags || k.nr != p->k1->nr)
+                continue;
+            bool same = true;
+            for (int r = 0; r < k.nr; ++r) same = same && k.radix[r] == p->k1->radix[r];
+            if (same) p->klist = &k;
+        }
+    }
 
     if (off > 0) {
-        float2* host = (float2*)std::calloc(off, sizeof(float2));
-        if (!host) {
-            delete p;
-            return FFT_ERR_OUT_OF_MEMORY;
-        }
-        fill_kernel_table(p->k1, host + p->off_s1);
-        if (p->path == FFT_PATH_FOURSTEP) {
-            fill_kernel_table(p->k2, host + p->off_s2);
-            const long long N = (long long)n;
-            for (long long a = 0; a < (N >> p->lo_bits); ++a) host[p->off_hi + a] = root_f32(a << p->lo_bits, N);
-            for (long long b = 0; b < (1LL << p->lo_bits); ++b) host[p->off_lo + b] = root_f32(b, N);
-            if (p->off_col) {
-                // row col: exp(-2 pi i col T 2^i / N), i < log2(E), T = N1 / E threads per column
-                const int row = col_row(p->k1->e);
-                const long long T = (long long)p->n1 / p->k1->e;
-                for (long long c = 0; c < (long long)p->n2; ++c)
-                    for (int i = 0; i < row; ++i)
-                        host[p->off_col + c * row + i] =
-                            (1 << i) < p->k1->e ? root_f32((c * T * (1LL << i)) % N, N) : make_float2(0.f, 0.f);
-            }
-        }
         e = hipMalloc((void**)&p->tw, p->tw_bytes);
-        if (e == hipSuccess) e = hipMemcpy(p->tw, host, p->tw_bytes, hipMemcpyHostToDevice);
-        std::free(host);
+        if (e == hipSuccess && p->device_twiddles) {
+            // FP64 evaluation on the device (the only FP64 step on the GPU)
+            TwSeg* dsegs = nullptr;
+            e = hipMalloc((void**)&dsegs, p->segs.size() * sizeof(TwSeg));
+            if (e == hipSuccess)
+                e = hipMemcpy(dsegs, p->segs.data(), p->segs.size() * sizeof(TwSeg), hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = generate_twiddles_device(p->tw, (long long)off, dsegs, (int)p->segs.size(), nullptr);
+            if (e == hipSuccess) e = hipDeviceSynchronize();
+            if (dsegs) (void)hipFree(dsegs);
+        } else if (e == hipSuccess) {
+            float2* host = (float2*)std::calloc(off, sizeof(float2));
+            if (!host) {
+                (void)hipFree(p->tw);
+                delete p;
+                return FFT_ERR_OUT_OF_MEMORY;
+            }
+            eval_segments_host(p->segs, host);
+            e = hipMemcpy(p->tw, host, p->tw_bytes, hipMemcpyHostToDevice);
+            std::free(host);
+        }
         if (e != hipSuccess) {
             if (p->tw) (void)hipFree(p->tw);
             delete p;
@@ -564,6 +610,104 @@ fft_status_t fft_plan_create_ex(size_t n, size_t batch, int direction, const fft
         g_plans.insert(p);
     }
     *plan_out = p;
+    return FFT_SUCCESS;
+}
+
+fft_status_t fft_plan_create_ex(size_t n, size_t batch, int direction, const fft_plan_opts_t* opts,
+                                fft_plan_t* plan_out)
+{
+    if (plan_out == nullptr) return FFT_ERR_INVALID_ARG;
+    *plan_out = nullptr;
+    fft_plan_s* p = new (std::nothrow) fft_plan_s();
+    if (!p) return FFT_ERR_OUT_OF_MEMORY;
+    size_t off = 0;
+    const fft_status_t st = plan_choose(n, batch, direction, opts, p, &off);
+    if (st != FFT_SUCCESS) {
+        delete p;
+        return st;
+    }
+    return plan_materialize(p, off, plan_out);
+}
+
+// Range compression plan: the kernel, its stage table, then n entries for the
+// replica's spectrum (zero until the plan computes it).
+static fft_status_t filter_choose(size_t n, size_t batch, size_t replica_len, const fft_plan_opts_t* opts,
+                                  fft_plan_s* p, size_t* table_entries)
+{
+    if (n == 0 || batch == 0 || replica_len == 0 || replica_len > n) return FFT_ERR_INVALID_ARG;
+    if (batch > ((size_t)1 << 40) / n) return FFT_ERR_INVALID_ARG;
+    fft_plan_opts_t o;
+    fft_plan_opts_init(&o);
+    if (opts) o = *opts;
+    if (o.storage != 0 || o.n_radix < 0 || o.n_radix > 8) return FFT_ERR_INVALID_ARG;
+    if (n > (size_t)kDefaultBlockLimit) return FFT_ERR_UNSUPPORTED_SIZE;
+    p->n = n;
+    p->batch = batch;
+    p->direction = FFT_FORWARD;
+    p->path = FFT_PATH_FILTER;
+    p->device_twiddles = o.device_twiddles ? 1 : 0;
+    p->segs.clear();
+    if (o.n_radix == 0 && o.flags < 0)
+        p->k1 = kernel_default(kKindFilter, (int)n, 0, 0);
+    else
+        p->k1 = kernel_find(kKindFilter, (int)n, o.radix, o.n_radix, 0, o.flags);
+    if (!p->k1) return FFT_ERR_UNSUPPORTED_SIZE;
+    size_t off = round_up((size_t)stage_segments(p->k1, 0, p->segs), 32);
+    p->off_flt = off;
+    off = round_up(off + n, 32);
+    p->tw_bytes = off * sizeof(float2);
+    *table_entries = off;
+    return FFT_SUCCESS;
+}
+
+fft_status_t fft_filter_query(size_t n, size_t batch, size_t replica_len, const fft_plan_opts_t* opts,
+                              fft_plan_desc_t* desc)
+{
+    if (desc == nullptr) return FFT_ERR_INVALID_ARG;
+    fft_plan_s tmp;
+    size_t entries = 0;
+    const fft_status_t s = filter_choose(n, batch, replica_len, opts, &tmp, &entries);
+    if (s != FFT_SUCCESS) return s;
+    describe(&tmp, desc);
+    return FFT_SUCCESS;
+}
+
+fft_status_t fft_filter_create(size_t n, size_t batch, const void* replica, size_t replica_len,
+                               const fft_plan_opts_t* opts, fft_plan_t* plan_out)
+{
+    if (plan_out == nullptr) return FFT_ERR_INVALID_ARG;
+    *plan_out = nullptr;
+    if (replica == nullptr || ((uintptr_t)replica & 7u)) return FFT_ERR_INVALID_ARG;
+    fft_plan_s* p = new (std::nothrow) fft_plan_s();
+    if (!p) return FFT_ERR_OUT_OF_MEMORY;
+    size_t off = 0;
+    fft_status_t st = filter_choose(n, batch, replica_len, opts, p, &off);
+    if (st != FFT_SUCCESS) {
+        delete p;
+        return st;
+    }
+    fft_plan_t plan = nullptr;
+    st = plan_materialize(p, off, &plan);
+    if (st != FFT_SUCCESS) return st;
+    // spectrum of the zero-padded replica, by this library's forward transform
+    float2* spec = plan->tw + plan->off_flt;
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != plan->device) e = hipSetDevice(plan->device);
+    if (e == hipSuccess)
+        e = hipMemcpy(spec, replica, replica_len * sizeof(float2), hipMemcpyDeviceToDevice);
+    if (e != hipSuccess) st = from_hip(e);
+    fft_plan_t fwd = nullptr;
+    if (st == FFT_SUCCESS) st = fft_plan_create(n, 1, FFT_FORWARD, &fwd);
+    if (st == FFT_SUCCESS) st = fft_execute(fwd, spec, spec, nullptr);
+    if (st == FFT_SUCCESS) st = from_hip(hipDeviceSynchronize());
+    if (fwd) (void)fft_plan_destroy(fwd);
+    if (cur != plan->device) (void)hipSetDevice(cur);
+    if (st != FFT_SUCCESS) {
+        (void)fft_plan_destroy(plan);
+        return st;
+    }
+    *plan_out = plan;
     return FFT_SUCCESS;
 }
 
@@ -589,6 +733,17 @@ fft_status_t fft_plan_destroy(fft_plan_t plan)
     return from_hip(e);
 }
 
+fft_status_t fft_plan_twiddles(fft_plan_t plan, void* host_dst, size_t max_entries, size_t* n_entries)
+{
+    if (!plan_live(plan)) return FFT_ERR_INVALID_PLAN;
+    if (!n_entries) return FFT_ERR_INVALID_ARG;
+    const size_t cnt = plan->tw_bytes / sizeof(float2);
+    *n_entries = cnt;
+    if (!host_dst || cnt == 0) return FFT_SUCCESS;
+    if (max_entries < cnt) return FFT_ERR_INVALID_ARG;
+    return from_hip(hipMemcpy(host_dst, plan->tw, plan->tw_bytes, hipMemcpyDeviceToHost));
+}
+
 fft_status_t fft_plan_describe(fft_plan_t plan, fft_plan_desc_t* d)
 {
     if (!plan_live(plan)) return FFT_ERR_INVALID_PLAN;
@@ -597,15 +752,33 @@ fft_status_t fft_plan_describe(fft_plan_t plan, fft_plan_desc_t* d)
     return FFT_SUCCESS;
 }
 
-static fft_status_t execute_impl(fft_plan_t plan, int passes, const void* in, void* out, void* stream)
+// batch: transforms of this call (0 = the plan's); work: four-step workspace
+// (nullptr = the plan's own, which then bounds batch).
+static fft_status_t execute_impl(fft_plan_t plan, int passes, size_t batch, const void* in, void* out, void* work,
+                                 void* stream)
 {
     if (!plan_live(plan)) return FFT_ERR_INVALID_PLAN;
     if (in == nullptr || out == nullptr) return FFT_ERR_INVALID_ARG;
-    if (((uintptr_t)in & 7u) || ((uintptr_t)out & 7u)) return FFT_ERR_INVALID_ARG;
+    if (!plan->storage && (((uintptr_t)in & 7u) || ((uintptr_t)out & 7u))) return FFT_ERR_INVALID_ARG;
     if (passes == 2 && plan->path != FFT_PATH_FOURSTEP) return FFT_ERR_INVALID_ARG;
-    const size_t bytes = plan->n * plan->batch * sizeof(float2);
+    const size_t elem = plan->storage ? 4 : sizeof(float2);
+    if (plan->storage && (((uintptr_t)in & 3u) || ((uintptr_t)out & 3u))) return FFT_ERR_INVALID_ARG;
+    if (batch == 0) batch = plan->batch;
+    if (batch > ((size_t)1 << 40) / plan->n) return FFT_ERR_INVALID_ARG;
+    const size_t bytes = plan->n * batch * elem;
     const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
     if (a != b && a < b + bytes && b < a + bytes) return FFT_ERR_INVALID_ARG;
+    float2* ws = plan->work;
+    if (plan->path == FFT_PATH_FOURSTEP) {
+        if (work) {
+            const uintptr_t w = (uintptr_t)work, wb = plan->n * batch * sizeof(float2);
+            if (w & 7u) return FFT_ERR_INVALID_ARG;
+            if ((w < a + bytes && a < w + wb) || (w < b + bytes && b < w + wb)) return FFT_ERR_INVALID_ARG;
+            ws = (float2*)work;
+        } else if (batch > plan->batch) {
+            return FFT_ERR_INVALID_ARG;
+        }
+    }
 
     int cur = 0;
     hipError_t e = hipGetDevice(&cur);
@@ -616,16 +789,28 @@ static fft_status_t execute_impl(fft_plan_t plan, int passes, const void* in, vo
     float2* y = (float2*)out;
     const bool run1 = passes == 0 || passes == 1;
     const bool run2 = passes == 0 || passes == 2;
+    const bool own = batch == plan->batch;
+    auto grid = [&](const KEntry* k, const KArgs& ka, long long g) { return own ? g : grid_for(k, ka, plan->cus); };
 
-    if (plan->path == FFT_PATH_BLOCK) {
+    if (plan->path == FFT_PATH_BLOCK || plan->path == FFT_PATH_FILTER) {
         if (plan->n == 1) {
             e = (in == out) ? hipSuccess : hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, st);
         } else {
-            e = plan->k1->launch(make_args(plan, 1, x, y), plan->grid1, st);
+            KArgs ka = make_args(plan, 1, x, y);
+            ka.batch = (long long)batch;
+            e = plan->k1->launch(ka, grid(plan->k1, ka, plan->grid1), st);
         }
     } else {
-        if (run1) e = plan->k1->launch(make_args(plan, 1, x, plan->work), plan->grid1, st);
-        if (e == hipSuccess && run2) e = plan->k2->launch(make_args(plan, 2, plan->work, y), plan->grid2, st);
+        if (run1) {
+            KArgs ka = make_args(plan, 1, x, ws);
+            ka.batch = (long long)batch;
+            e = plan->k1->launch(ka, grid(plan->k1, ka, plan->grid1), st);
+        }
+        if (e == hipSuccess && run2) {
+            KArgs ka = make_args(plan, 2, ws, y);
+            ka.batch = (long long)batch;
+            e = plan->k2->launch(ka, grid(plan->k2, ka, plan->grid2), st);
+        }
     }
     if (cur != plan->device) (void)hipSetDevice(cur);
     return from_hip(e);
@@ -633,13 +818,48 @@ static fft_status_t execute_impl(fft_plan_t plan, int passes, const void* in, vo
 
 fft_status_t fft_execute(fft_plan_t plan, const void* in, void* out, void* stream)
 {
-    return execute_impl(plan, 0, in, out, stream);
+    return execute_impl(plan, 0, 0, in, out, nullptr, stream);
 }
+
+fft_status_t fft_execute_ex(fft_plan_t plan, size_t batch, const void* in, void* out, void* workspace, void* stream)
+{
+    return execute_impl(plan, 0, batch, in, out, workspace, stream);
+}
+
+}  // extern "C"
+
+namespace fb {
+
+hipError_t plan_launch_list(fft_plan_s* plan, const void* list, long long transforms, hipStream_t st)
+{
+    if (!plan->klist || transforms <= 0) return hipErrorNotSupported;
+    KArgs ka = make_args(plan, 1, nullptr, nullptr);
+    ka.batch = transforms;
+    ka.list = list;
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != plan->device) e = hipSetDevice(plan->device);
+    if (e == hipSuccess) e = plan->klist->launch(ka, kernel_units(*plan->klist, ka), st);
+    if (cur != plan->device) (void)hipSetDevice(cur);
+    return e;
+}
+
+void plan_shape(const fft_plan_s* plan, size_t* n, int* direction, int* path, bool* has_list)
+{
+    *n = plan->n;
+    *direction = plan->direction;
+    *path = plan->path;
+    *has_list = plan->klist != nullptr;
+}
+
+}  // namespace fb
+
+extern "C" {
 
 fft_status_t fft_execute_pass(fft_plan_t plan, int pass, const void* in, void* out, void* stream)
 {
     if (pass != 1 && pass != 2) return plan_live(plan) ? FFT_ERR_INVALID_ARG : FFT_ERR_INVALID_PLAN;
-    return execute_impl(plan, pass, in, out, stream);
+    return execute_impl(plan, pass, 0, in, out, nullptr, stream);
 }
 
 fft_status_t fft_transpose(const void* in, void* out, size_t rows, size_t cols, size_t batch, void* stream)

@@ -6,6 +6,8 @@
 
 #include <cstddef>
 
+struct fft_plan_s;
+
 namespace fb {
 
 // Arguments shared by every transform kernel (one struct so all launchers
@@ -23,16 +25,25 @@ struct KArgs {
     const float2* tw_hi;   // exp(-2 pi i hi 2^lo_bits / N)
     const float2* tw_lo;   // exp(-2 pi i lo / N)
     const float2* tw_col;  // pass 1, power variant: row col holds exp(-2 pi i col T 2^i / N)
+    const float2* flt;     // range compression: spectrum of the pulse replica (n entries)
+    const void* list;      // list kernels: one ListEnt per transform
     float sg;              // +1 forward, -1 backward (conjugation on entry and exit)
 };
 
 using KLaunch = hipError_t (*)(const KArgs& a, long long grid, hipStream_t st);
 using KOccupancy = int (*)();   // resident workgroups per CU (hipOccupancy...), 0 on error
 
-enum : int { kKindBlock = 0, kKindPass1 = 1, kKindPass2 = 2 };
+enum : int { kKindBlock = 0, kKindPass1 = 1, kKindPass2 = 2, kKindFilter = 3, kKindList = 4 };
+
+// Descriptor of one transform of a list launch (several requests' batches,
+// anywhere in memory, in one launch).
+struct ListEnt {
+    const float2* in;
+    float2* out;
+};
 
 struct KEntry {
-    int kind;          // kKindBlock, kKindPass1, kKindPass2
+    int kind;          // kKindBlock, kKindPass1, kKindPass2, kKindFilter
     int n;             // transform length handled by one group of threads
     int e;             // complex values per thread
     int c;             // transforms per workgroup (block) / columns or rows per workgroup (passes)
@@ -54,18 +65,46 @@ long long kernel_units(const KEntry& k, const KArgs& a);
 
 const KEntry* kernel_table(int* count);
 // Default kernel for (kind, n); for the passes `c` > 0 restricts the width.
-const KEntry* kernel_default(int kind, int n, int c);
+const KEntry* kernel_default(int kind, int n, int c, int storage = 0);
 // Kernel with exactly this schedule / width / flags (c or flags < 0: any).
 const KEntry* kernel_find(int kind, int n, const int* radix, int nr, int c, int flags);
 
-// Registration hooks of the two kernel translation units.
+// Registration hooks of the kernel translation units.
 const KEntry* block_entries(int* count);
 const KEntry* pass_entries(int* count);
+const KEntry* filter_entries(int* count);
+const KEntry* list_entries(int* count);
 
 // Kernel the wisdom (autotuner or FFTBLOCK_WISDOM file) chose for length n, or nullptr.
 const KEntry* wisdom_kernel(size_t n);
 // Four-step kernels the wisdom chose for length n = n1 * n2 (false if none).
 bool wisdom_pair(size_t n, size_t n1, size_t n2, const KEntry** k1, const KEntry** k2);
+
+// One segment of a plan's twiddle table: entries [offset, offset + count)
+// hold exp(-2 pi i m / n) rounded once from FP64 to FP32, with (m, n) a
+// function of the entry index e:
+//   kSegRows  (a = Ns, b = R):             k = e / R, r = e % R, m = r k, n = Ns R
+//   kSegPow   (a = Ns, b = R, c = row, d = P): k = e / row, i = e % row,
+//                                           m = k 2^i, n = Ns R (zero for i >= P)
+//   kSegHi    (a = N, b = lo_bits):         m = e 2^lo_bits, n = N
+//   kSegLo    (a = N):                      m = e, n = N
+//   kSegCol   (a = N, b = T, c = row, d = E): col = e / row, i = e % row,
+//                                           m = col T 2^i mod N, n = N (zero if 2^i >= E)
+// Entries covered by no segment are zero.
+enum : int { kSegRows = 0, kSegPow = 1, kSegHi = 2, kSegLo = 3, kSegCol = 4 };
+struct TwSeg {
+    int type;
+    long long offset, count;
+    long long a, b, c, d;
+};
+// Evaluate the segments on the device in FP64 into dst (total entries).
+hipError_t generate_twiddles_device(float2* dst, long long total, const TwSeg* segs, int nseg, hipStream_t st);
+
+// List launch of a block plan's kernel: `transforms` descriptors at `list`
+// (device memory).  hipErrorNotSupported if the plan's kernel has no list form.
+hipError_t plan_launch_list(fft_plan_s* plan, const void* list, long long transforms, hipStream_t st);
+// Length, direction and path of a plan (for the serving layer).
+void plan_shape(const fft_plan_s* plan, size_t* n, int* direction, int* path, bool* has_list);
 
 hipError_t launch_transpose(const float2* in, float2* out, long long rows, long long cols, long long batch,
                             hipStream_t st);

@@ -14,7 +14,39 @@ namespace fb {
     make_entry<N, E, C, Sched<__VA_ARGS__>, PolBlock, FL>(DEF, "block_fft<" #N ",[" #__VA_ARGS__ \
                                                                 "],v" #FL ">")
 
+#define FB_BLKH(DEF, FL, N, E, C, ...)                                                               \
+    make_entry<N, E, C, Sched<__VA_ARGS__>, PolBlockH, FL>(DEF, "block_fft_f16<" #N ",[" #__VA_ARGS__ \
+                                                                 "],v" #FL ">")
+
 static const KEntry kBlock[] = {
+    // FP16 storage, FP32 arithmetic (64 + 35)
+    FB_BLKH(true, 99, 2, 2, 256, 2),
+    FB_BLKH(true, 99, 4, 4, 256, 4),
+    FB_BLKH(true, 99, 8, 8, 256, 8),
+    FB_BLKH(true, 99, 16, 16, 256, 16),
+    FB_BLKH(true, 99, 32, 16, 128, 16, 2),
+    FB_BLKH(true, 99, 64, 16, 64, 16, 4),
+    FB_BLKH(true, 99, 128, 16, 32, 16, 8),
+    FB_BLKH(true, 99, 256, 16, 16, 16, 16),
+    FB_BLKH(true, 99, 512, 16, 8, 16, 16, 2),
+    FB_BLKH(true, 99, 1024, 8, 2, 8, 8, 4, 4),
+    FB_BLKH(true, 99, 2048, 16, 2, 16, 16, 8),
+    FB_BLKH(true, 99, 4096, 16, 1, 16, 16, 16),
+    FB_BLKH(true, 99, 8192, 16, 1, 8, 8, 8, 16),
+    FB_BLKH(true, 99, 16384, 16, 1, 16, 16, 16, 4),
+    FB_BLKH(true, 99, 3, 3, 64, 3),
+    FB_BLKH(true, 99, 5, 5, 64, 5),
+    FB_BLKH(true, 99, 6, 6, 64, 6),
+    FB_BLKH(true, 99, 10, 10, 64, 10),
+    FB_BLKH(true, 99, 12, 12, 64, 12),
+    FB_BLKH(true, 99, 15, 15, 64, 15),
+    FB_BLKH(true, 99, 20, 20, 64, 20),
+    FB_BLKH(true, 99, 60, 30, 32, 6, 10),
+    FB_BLKH(true, 99, 100, 10, 8, 10, 10),
+    FB_BLKH(true, 99, 1000, 10, 2, 10, 10, 10),
+    FB_BLKH(true, 99, 3072, 24, 2, 6, 8, 8, 8),
+    FB_BLKH(true, 99, 6000, 30, 1, 10, 10, 10, 6),
+    FB_BLKH(true, 99, 15360, 60, 1, 12, 20, 4, 4, 4),
     // planner defaults: non-temporal data access + power-row twiddles (35)
     FB_BLK(true, 3, 2, 2, 256, 2),
     FB_BLK(true, 3, 4, 4, 256, 4),

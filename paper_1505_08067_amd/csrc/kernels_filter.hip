@@ -1,0 +1,36 @@
+// Range compression kernels: per row, forward transform, product with the
+// conjugate spectrum of the pulse replica, backward transform -- one
+// LDS-resident workgroup per row (or rows), one read and one write of HBM.
+#include "fft_kernel.hpp"
+
+namespace fb {
+
+#define FB_FLT(DEF, FL, N, E, C, ...)                                                          \
+    make_entry<N, E, C, Sched<__VA_ARGS__>, PolFilt, FL>(DEF, "range_compress<" #N ",[" #__VA_ARGS__ \
+                                                               "],v" #FL ">")
+
+static const KEntry kFilter[] = {
+    FB_FLT(true, 35, 64, 16, 64, 16, 4),
+    FB_FLT(true, 35, 128, 16, 32, 16, 8),
+    FB_FLT(true, 35, 256, 16, 16, 16, 16),
+    FB_FLT(true, 35, 512, 16, 8, 16, 16, 2),
+    FB_FLT(true, 35, 1024, 8, 2, 8, 8, 4, 4),
+    FB_FLT(true, 35, 2048, 16, 2, 16, 16, 8),
+    FB_FLT(true, 35, 4096, 16, 1, 16, 16, 16),
+    FB_FLT(true, 35, 8192, 16, 1, 8, 8, 8, 16),
+    FB_FLT(true, 35, 16384, 16, 1, 16, 16, 16, 4),
+    // first radix equal to the last: no LDS round trip between the transforms
+    FB_FLT(false, 35, 1024, 16, 4, 16, 4, 16),
+    FB_FLT(false, 35, 8192, 16, 1, 16, 8, 4, 16),
+    FB_FLT(false, 35, 8192, 16, 1, 16, 2, 16, 16),
+    FB_FLT(false, 35, 16384, 16, 1, 16, 4, 16, 16),
+    FB_FLT(false, 3, 8192, 16, 1, 8, 8, 8, 16),
+};
+
+const KEntry* filter_entries(int* count)
+{
+    *count = (int)(sizeof(kFilter) / sizeof(kFilter[0]));
+    return kFilter;
+}
+
+}  // namespace fb

@@ -22,7 +22,27 @@ namespace fb {
 #define FB_P2(DEF, FL, N, E, C, ...) \
     make_entry<N, E, C, Sched<__VA_ARGS__>, PolPass2, FL>(DEF, "fourstep_pass2<" #N ",C" #C ",[" #__VA_ARGS__ "],v" #FL ">")
 
+#define FB_P1H(DEF, FL, N, E, C, ...) \
+    make_entry<N, E, C, Sched<__VA_ARGS__>, PolPass1H, FL>(DEF, "fourstep_pass1_f16<" #N ",C" #C ",[" #__VA_ARGS__ "],v" #FL ">")
+#define FB_P2H(DEF, FL, N, E, C, ...) \
+    make_entry<N, E, C, Sched<__VA_ARGS__>, PolPass2H, FL>(DEF, "fourstep_pass2_f16<" #N ",C" #C ",[" #__VA_ARGS__ "],v" #FL ">")
+
 static const KEntry kPass[] = {
+    // FP16 storage (pass 1 reads FP16, pass 2 writes FP16; workspace FP32)
+    FB_P1H(true, 113, 32, 16, 16, 16, 2),
+    FB_P1H(true, 113, 64, 16, 16, 16, 4),
+    FB_P1H(true, 113, 128, 16, 16, 16, 8),
+    FB_P1H(true, 113, 256, 16, 16, 16, 16),
+    FB_P1H(true, 113, 512, 16, 16, 16, 16, 2),
+    FB_P1H(true, 113, 1024, 16, 16, 16, 16, 4),
+    FB_P1H(true, 113, 2048, 16, 8, 16, 16, 8),
+    FB_P2H(true, 97, 32, 16, 16, 16, 2),
+    FB_P2H(true, 97, 64, 16, 16, 16, 4),
+    FB_P2H(true, 97, 128, 16, 16, 16, 8),
+    FB_P2H(true, 97, 256, 16, 16, 16, 16),
+    FB_P2H(true, 97, 512, 16, 16, 16, 16, 2),
+    FB_P2H(true, 97, 1024, 16, 8, 16, 16, 4),
+    FB_P2H(true, 97, 2048, 16, 8, 16, 16, 8),
     // planner defaults.  Pass 1: non-temporal loads, power-row twiddles
     // (stage and long), outputs staged through LDS for contiguous stores
     // (49).  Pass 2: non-temporal loads, power-row twiddles (33).

@@ -144,3 +144,80 @@ hipError_t launch_copy(const void* in, void* out, size_t bytes, hipStream_t st)
 }
 
 }  // namespace fb
+
+namespace fb {
+
+// FP64 evaluation of a plan's twiddle table on the device (the precision form:
+// the tables are the only FP64 work on the GPU).  Each entry is
+// exp(-2 pi i m / n) for the (m, n) its segment assigns, computed with an
+// exact quadrant reduction and double-precision sin/cos, then rounded once to
+// FP32; entries outside every segment are zero.
+__device__ float2 root_f64_to_f32(long long m, long long n)
+{
+    m %= n;
+    if (m < 0) m += n;
+    const long long q = (4 * m) / n, rem = 4 * m - q * n;
+    const double hp = 1.57079632679489661923132169163975144;
+    double c, s;
+    if (2 * rem <= n) {
+        const double phi = hp * ((double)rem / (double)n);
+        c = cos(phi);
+        s = sin(phi);
+    } else {
+        const double phi = hp * ((double)(n - rem) / (double)n);
+        c = sin(phi);
+        s = cos(phi);
+    }
+    const double cr = q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
+    const double sr = q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
+    return make_float2((float)cr, (float)(-sr));
+}
+
+__global__ void __launch_bounds__(256) k_twiddle_gen(float2* __restrict__ dst, long long total,
+                                                     const TwSeg* __restrict__ segs, int nseg)
+{
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < total; i += (long long)gridDim.x * 256) {
+        float2 v = make_float2(0.f, 0.f);
+        for (int g = 0; g < nseg; ++g) {
+            const TwSeg sg = segs[g];
+            if (i < sg.offset || i >= sg.offset + sg.count) continue;
+            const long long e = i - sg.offset;
+            long long m = 0, n = 1;
+            bool have = true;
+            switch (sg.type) {
+                case kSegRows: m = (e % sg.b) * (e / sg.b); n = sg.a * sg.b; break;
+                case kSegPow: {
+                    const long long k = e % sg.c;
+                    have = k < sg.d;
+                    m = (e / sg.c) << k;
+                    n = sg.a * sg.b;
+                    break;
+                }
+                case kSegHi: m = e << sg.b; n = sg.a; break;
+                case kSegLo: m = e; n = sg.a; break;
+                case kSegCol: {
+                    const long long k = e % sg.c;
+                    have = (1LL << k) < sg.d;
+                    m = (((e / sg.c) * sg.b) << k) % sg.a;
+                    n = sg.a;
+                    break;
+                }
+                default: have = false;
+            }
+            if (have) v = root_f64_to_f32(m, n);
+            break;
+        }
+        dst[i] = v;
+    }
+}
+
+hipError_t generate_twiddles_device(float2* dst, long long total, const TwSeg* segs, int nseg, hipStream_t st)
+{
+    if (total <= 0) return hipSuccess;
+    long long blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_twiddle_gen, dim3((unsigned)blocks), dim3(256), 0, st, dst, total, segs, nseg);
+    return hipGetLastError();
+}
+
+}  // namespace fb

@@ -22,6 +22,7 @@
 
 struct fft_ragged_s {
     int direction = FFT_FORWARD;
+    size_t elem = 8;  // bytes per value: 8 (complex64) or 4 (FP16 pairs)
     int device = 0;
     std::vector<size_t> sizes, counts, offsets;
     size_t total_points = 0;
@@ -86,8 +87,8 @@ fft_status_t capture(fft_ragged_s* r, const void* in, void* out)
     const size_t nb = r->branches.size();
     for (size_t b = 0; b < nb && e == hipSuccess; ++b) e = hipStreamWaitEvent(r->branches[b], r->fork, 0);
     for (size_t c = 0; c < r->plans.size() && e == hipSuccess && st == FFT_SUCCESS; ++c) {
-        const float2* x = (const float2*)in + r->offsets[c];
-        float2* y = (float2*)out + r->offsets[c];
+        const char* x = (const char*)in + r->offsets[c] * r->elem;
+        char* y = (char*)out + r->offsets[c] * r->elem;
         st = fft_execute(r->plans[c], x, y, r->branches[c % nb]);
     }
     for (size_t b = 0; b < nb && e == hipSuccess; ++b) {
@@ -119,15 +120,28 @@ extern "C" {
 fft_status_t fft_ragged_create(const size_t* sizes, const size_t* counts, size_t n_classes, int direction,
                                fft_ragged_t* out)
 {
+    return fft_ragged_create_ex(sizes, counts, n_classes, direction, nullptr, out);
+}
+
+fft_status_t fft_ragged_create_ex(const size_t* sizes, const size_t* counts, size_t n_classes, int direction,
+                                  const fft_plan_opts_t* opts, fft_ragged_t* out)
+{
     if (!out) return FFT_ERR_INVALID_ARG;
     *out = nullptr;
     if (!sizes || !counts || n_classes == 0 || n_classes > 4096) return FFT_ERR_INVALID_ARG;
     if (direction != FFT_FORWARD && direction != FFT_BACKWARD) return FFT_ERR_INVALID_ARG;
     size_t total = 0;
+    // only the storage form and the twiddle source apply to a ragged plan
+    fft_plan_opts_t po;
+    fft_plan_opts_init(&po);
+    if (opts) {
+        po.storage = opts->storage;
+        po.device_twiddles = opts->device_twiddles;
+    }
     for (size_t c = 0; c < n_classes; ++c) {
         if (counts[c] == 0 || sizes[c] == 0) return FFT_ERR_INVALID_ARG;
         fft_plan_desc_t d;
-        const fft_status_t st = fft_plan_query(sizes[c], counts[c], direction, &d);
+        const fft_status_t st = fft_plan_query_ex(sizes[c], counts[c], direction, &po, &d);
         if (st != FFT_SUCCESS) return st;
         if (sizes[c] > ((size_t)1 << 40) / counts[c] || total > ((size_t)1 << 40)) return FFT_ERR_INVALID_ARG;
         total += sizes[c] * counts[c];
@@ -135,6 +149,7 @@ fft_status_t fft_ragged_create(const size_t* sizes, const size_t* counts, size_t
     fft_ragged_s* r = new (std::nothrow) fft_ragged_s();
     if (!r) return FFT_ERR_OUT_OF_MEMORY;
     r->direction = direction;
+    r->elem = po.storage ? 4 : 8;
     r->total_points = total;
     size_t at = 0;
     for (size_t c = 0; c < n_classes; ++c) {
@@ -146,7 +161,8 @@ fft_status_t fft_ragged_create(const size_t* sizes, const size_t* counts, size_t
     hipError_t e = hipGetDevice(&r->device);
     for (size_t c = 0; c < n_classes && e == hipSuccess; ++c) {
         fft_plan_t p = nullptr;
-        const fft_status_t st = fft_plan_create(sizes[c], counts[c], direction, &p);
+        const fft_status_t st = opts ? fft_plan_create_ex(sizes[c], counts[c], direction, &po, &p)
+                                     : fft_plan_create(sizes[c], counts[c], direction, &p);
         if (st != FFT_SUCCESS) {
             release(r);
             return st;
@@ -180,8 +196,8 @@ fft_status_t fft_ragged_execute(fft_ragged_t r, const void* in, void* out, void*
 {
     if (!live(r)) return FFT_ERR_INVALID_PLAN;
     if (!in || !out || (mode != 0 && mode != 1)) return FFT_ERR_INVALID_ARG;
-    if (((uintptr_t)in & 7u) || ((uintptr_t)out & 7u)) return FFT_ERR_INVALID_ARG;
-    const size_t bytes = r->total_points * sizeof(float2);
+    if (((uintptr_t)in & (r->elem - 1)) || ((uintptr_t)out & (r->elem - 1))) return FFT_ERR_INVALID_ARG;
+    const size_t bytes = r->total_points * r->elem;
     const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
     if (a != b && a < b + bytes && b < a + bytes) return FFT_ERR_INVALID_ARG;
     int cur = 0;
@@ -192,7 +208,8 @@ fft_status_t fft_ragged_execute(fft_ragged_t r, const void* in, void* out, void*
     if (mode == 1) {
         // plain path: every class launched in order on the caller's stream
         for (size_t c = 0; c < r->plans.size() && st == FFT_SUCCESS; ++c)
-            st = fft_execute(r->plans[c], (const float2*)in + r->offsets[c], (float2*)out + r->offsets[c], stream);
+            st = fft_execute(r->plans[c], (const char*)in + r->offsets[c] * r->elem,
+                             (char*)out + r->offsets[c] * r->elem, stream);
     } else {
         if (!r->exec || r->g_in != in || r->g_out != out) st = capture(r, in, out);
         if (st == FFT_SUCCESS) st = st_of(hipGraphLaunch(r->exec, (hipStream_t)stream));

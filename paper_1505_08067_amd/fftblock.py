@@ -21,6 +21,7 @@ FORWARD = -1
 BACKWARD = +1
 PATH_BLOCK = 1
 PATH_FOURSTEP = 2
+PATH_FILTER = 3
 
 STATUS = {
     0: "FFT_SUCCESS",
@@ -39,13 +40,19 @@ EXPORTS = (
     "fft_kernel_info", "fft_schedule_search", "fft_stage_benchmark", "fft_autotune", "fft_wisdom_set",
     "fft_wisdom_get", "fft_wisdom_clear", "fft_wisdom_save", "fft_wisdom_load",
     "fft_ragged_create", "fft_ragged_execute", "fft_ragged_describe", "fft_ragged_destroy",
+    "fft_plan_twiddles", "fft_ragged_create_ex", "fft_filter_create", "fft_filter_query", "fft_execute_ex",
 )
 
 VARIANT_NT_LOAD = 1
 VARIANT_NT_STORE = 2
 VARIANT_PERSISTENT = 4
 VARIANT_SWIZZLE = 8
-KERNEL_KINDS = {0: "block", 1: "pass1", 2: "pass2"}
+VARIANT_STAGED = 16
+VARIANT_TWIDDLE_POWERS = 32
+VARIANT_FP16_STORAGE = 64
+STORAGE_C64 = 0
+STORAGE_F16 = 1
+KERNEL_KINDS = {0: "block", 1: "pass1", 2: "pass2", 3: "filter", 4: "list"}
 
 
 class FFTError(RuntimeError):
@@ -66,7 +73,7 @@ class PlanDesc(ctypes.Structure):
         ("twiddle_bytes", ctypes.c_size_t), ("kernels_per_execute", ctypes.c_int),
         ("kernel_name", ctypes.c_char_p), ("kernel_name2", ctypes.c_char_p),
         ("flags", ctypes.c_int), ("flags2", ctypes.c_int), ("c2", ctypes.c_int),
-        ("grid", ctypes.c_longlong),
+        ("grid", ctypes.c_longlong), ("storage", ctypes.c_int), ("device_twiddles", ctypes.c_int),
     ]
 
 
@@ -74,6 +81,7 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [
         ("block_limit", ctypes.c_size_t), ("n_radix", ctypes.c_int), ("radix", ctypes.c_int * 8),
         ("flags", ctypes.c_int), ("c", ctypes.c_int), ("flags2", ctypes.c_int), ("c2", ctypes.c_int),
+        ("storage", ctypes.c_int), ("device_twiddles", ctypes.c_int),
     ]
 
 
@@ -141,6 +149,9 @@ def load():
     lib.fft_plan_opts_init.restype = None
     lib.fft_plan_create_ex.argtypes = [sz, sz, i, ctypes.POINTER(PlanOpts), ctypes.POINTER(vp)]
     lib.fft_plan_query_ex.argtypes = [sz, sz, i, ctypes.POINTER(PlanOpts), ctypes.POINTER(PlanDesc)]
+    lib.fft_filter_create.argtypes = [sz, sz, vp, sz, ctypes.POINTER(PlanOpts), ctypes.POINTER(vp)]
+    lib.fft_execute_ex.argtypes = [vp, sz, vp, vp, vp, vp]
+    lib.fft_filter_query.argtypes = [sz, sz, sz, ctypes.POINTER(PlanOpts), ctypes.POINTER(PlanDesc)]
     lib.fft_kernel_count.argtypes = []
     lib.fft_kernel_count.restype = i
     lib.fft_kernel_info.argtypes = [i, ctypes.POINTER(KernelInfo)]
@@ -160,6 +171,10 @@ def load():
     lib.fft_ragged_execute.argtypes = [vp, vp, vp, vp, i]
     lib.fft_ragged_describe.argtypes = [vp, szp, szp]
     lib.fft_ragged_destroy.argtypes = [vp]
+    lib.fft_plan_twiddles.argtypes = [vp, vp, sz, szp]
+    lib.fft_ragged_create_ex.argtypes = [szp, szp, sz, i, vp, ctypes.POINTER(vp)]
+    lib.fft_ragged_create_ex.restype = ctypes.c_int
+    lib.fft_plan_twiddles.restype = ctypes.c_int
     for name in ("fft_schedule_search", "fft_stage_benchmark", "fft_autotune", "fft_wisdom_set",
                  "fft_wisdom_save", "fft_wisdom_load", "fft_ragged_create", "fft_ragged_execute",
                  "fft_ragged_describe", "fft_ragged_destroy"):
@@ -183,12 +198,13 @@ def _stream_handle(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _check_tensor(x, name: str):
+def _check_tensor(x, name: str, storage: int = 0):
     import torch
     if not isinstance(x, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
-    if x.dtype != torch.complex64:
-        raise TypeError(f"{name} must be complex64, got {x.dtype}")
+    want = torch.complex64 if storage == 0 else torch.complex32
+    if x.dtype != want:
+        raise TypeError(f"{name} must be {want}, got {x.dtype}")
     if not x.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
     if not x.is_contiguous():
@@ -208,10 +224,11 @@ def _desc_dict(d: "PlanDesc") -> dict:
         "kernel_name": d.kernel_name.decode() if d.kernel_name else None,
         "kernel_name2": d.kernel_name2.decode() if d.kernel_name2 else None,
         "flags": d.flags, "flags2": d.flags2, "c2": d.c2, "grid": d.grid,
+        "storage": d.storage, "device_twiddles": d.device_twiddles,
     }
 
 
-def make_opts(block_limit=0, radix=None, flags=-1, c=0, flags2=-1, c2=0):
+def make_opts(block_limit=0, radix=None, flags=-1, c=0, flags2=-1, c2=0, storage=0, device_twiddles=False):
     """Planner options (``fft_plan_opts_t``); every default means "planner's choice"."""
     o = PlanOpts()
     load().fft_plan_opts_init(ctypes.byref(o))
@@ -221,6 +238,7 @@ def make_opts(block_limit=0, radix=None, flags=-1, c=0, flags2=-1, c2=0):
         for k, r in enumerate(radix):
             o.radix[k] = r
     o.flags, o.c, o.flags2, o.c2 = flags, c, flags2, c2
+    o.storage, o.device_twiddles = storage, 1 if device_twiddles else 0
     return o
 
 
@@ -261,6 +279,7 @@ class Plan:
         _check(st, f"fft_plan_create(n={n}, batch={batch})")
         self._h = h
         self.n, self.batch, self.direction = int(n), int(batch), int(direction)
+        self.storage = int(opts.storage) if opts is not None else 0
 
     @property
     def handle(self):
@@ -274,12 +293,12 @@ class Plan:
     def execute(self, x, out=None, stream=None):
         """Transform ``x`` (complex64, ``batch*n`` values) into ``out`` (new tensor if None)."""
         import torch
-        _check_tensor(x, "x")
+        _check_tensor(x, "x", self.storage)
         if x.numel() != self.n * self.batch:
             raise ValueError(f"x has {x.numel()} values, plan expects {self.n * self.batch}")
         if out is None:
             out = torch.empty_like(x)
-        _check_tensor(out, "out")
+        _check_tensor(out, "out", self.storage)
         if out.numel() != x.numel():
             raise ValueError("out has the wrong size")
         if out.device != x.device:
@@ -299,6 +318,17 @@ class Plan:
         _check(load().fft_execute_pass(self._h, pass_, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
                                        ctypes.c_void_p(stream_handle)), f"fft_execute_pass({pass_})")
 
+    def twiddles(self):
+        """The plan's twiddle table as a complex64 numpy array (``fft_plan_twiddles``)."""
+        import numpy as np
+        cnt = ctypes.c_size_t()
+        _check(load().fft_plan_twiddles(self._h, None, 0, ctypes.byref(cnt)), "fft_plan_twiddles")
+        out = np.zeros(cnt.value, dtype=np.complex64)
+        if cnt.value:
+            _check(load().fft_plan_twiddles(self._h, ctypes.c_void_p(out.ctypes.data), cnt.value, ctypes.byref(cnt)),
+                   "fft_plan_twiddles")
+        return out
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
             _check(load().fft_plan_destroy(self._h), "fft_plan_destroy")
@@ -315,6 +345,36 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def filter_query(n: int, batch: int, replica_len: int, opts: "PlanOpts | None" = None) -> dict:
+    """What ``fft_filter_create`` would choose, without a device."""
+    d = PlanDesc()
+    _check(load().fft_filter_query(n, batch, replica_len, ctypes.byref(opts) if opts is not None else None,
+                                   ctypes.byref(d)), f"fft_filter_query(n={n})")
+    return _desc_dict(d)
+
+
+class RangeCompressor(Plan):
+    """Range compression of ``batch`` rows of length ``n`` against a pulse
+    replica (``fft_filter_create``): ``y = B(F(x) * conj(F(replica)))`` per
+    row, i.e. ``n`` times the circular cross-correlation with the replica,
+    in one kernel.  ``replica`` is a complex64 CUDA tensor of at most ``n``
+    values; it is only read while the plan is created."""
+
+    def __init__(self, n: int, batch: int, replica, opts: "PlanOpts | None" = None):
+        import torch
+        _check_tensor(replica, "replica")
+        if not replica.is_cuda or not replica.is_contiguous():
+            raise ValueError("replica must be a contiguous CUDA tensor")
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize(replica.device)
+        _check(load().fft_filter_create(n, batch, ctypes.c_void_p(replica.data_ptr()), replica.numel(),
+                                        ctypes.byref(opts) if opts is not None else None, ctypes.byref(h)),
+               f"fft_filter_create(n={n}, batch={batch})")
+        self._h = h
+        self.n, self.batch, self.direction = int(n), int(batch), FORWARD
+        self.storage = STORAGE_C64
 
 
 def transpose(x, out=None, stream=None):
@@ -448,14 +508,20 @@ class Ragged:
     concatenation of the classes' batches in that order.
     """
 
-    def __init__(self, classes, direction: int = FORWARD):
+    def __init__(self, classes, direction: int = FORWARD, storage: int = STORAGE_C64, device_twiddles: bool = False):
         lib = load()
         self.classes = [(int(n), int(c)) for n, c in classes]
         k = len(self.classes)
         sizes = (ctypes.c_size_t * k)(*[n for n, _ in self.classes])
         counts = (ctypes.c_size_t * k)(*[c for _, c in self.classes])
         h = ctypes.c_void_p()
-        _check(lib.fft_ragged_create(sizes, counts, k, direction, ctypes.byref(h)), "fft_ragged_create")
+        if storage == STORAGE_C64 and not device_twiddles:
+            st = lib.fft_ragged_create(sizes, counts, k, direction, ctypes.byref(h))
+        else:
+            o = make_opts(storage=storage, device_twiddles=device_twiddles)
+            st = lib.fft_ragged_create_ex(sizes, counts, k, direction, ctypes.byref(o), ctypes.byref(h))
+        _check(st, "fft_ragged_create")
+        self.storage = storage
         self._h = h
         self.direction = direction
         self.total_points = sum(n * c for n, c in self.classes)
@@ -469,12 +535,12 @@ class Ragged:
 
     def execute(self, x, out=None, stream=None, graph: bool = True):
         import torch
-        _check_tensor(x, "x")
+        _check_tensor(x, "x", self.storage)
         if x.numel() != self.total_points:
             raise ValueError(f"x has {x.numel()} values, ragged plan expects {self.total_points}")
         if out is None:
             out = torch.empty_like(x)
-        _check_tensor(out, "out")
+        _check_tensor(out, "out", self.storage)
         _check(load().fft_ragged_execute(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                          _stream_handle(stream), 0 if graph else 1), "fft_ragged_execute")
         return out

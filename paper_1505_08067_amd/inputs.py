@@ -18,6 +18,9 @@ it processes):
   scatterers) with a unit-modulus phase drawn per (pulse, target), plus
   complex Gaussian noise at the requested SNR (noise variance = mean signal
   power / 10^(snr/10)).
+* ``sar_replica(tb, alpha)`` -- the transmitted pulse the ``sar`` echoes are
+  made of (the chirp at delay 0, complex64, length L): the reference that
+  range compression correlates every row with.
 * ``ragged_sizes(seed, ...)`` -- the ragged mix: an equal share of points per
   size, shuffled with the seed.
 * ``poisson_trace(seed, ...)`` -- request arrival times and shapes for the
@@ -71,6 +74,13 @@ def sar_delays(seed: int, ranges: int = 8192, targets: int = 32, tb: float = 500
     rng = np.random.default_rng(seed)
     L = int(round(alpha * tb))
     return rng.integers(0, ranges - L + 1, size=targets)
+
+
+def sar_replica(tb: float = 500.0, alpha: float = 1.25) -> np.ndarray:
+    """complex64 pulse replica: ``exp(i pi TB (n/L - 1/2)^2)``, n < L = round(alpha*TB)."""
+    L = int(round(alpha * tb))
+    n = np.arange(L, dtype=np.float64)
+    return np.exp(1j * np.pi * tb * (n / L - 0.5) ** 2).astype(np.complex64)
 
 
 RAGGED_POW2 = tuple(2 ** k for k in range(6, 17))

@@ -145,3 +145,58 @@ def test_transpose_and_copy_argument_errors_without_device():
     assert lib.fft_copy(vp(0x10008), vp(0x20000), 32, None) == 1                 # misaligned
     assert lib.fft_copy(vp(0x10000), vp(0x10010), 32, None) == 1                 # overlap
     assert lib.fft_copy(None, vp(0x20000), 32, None) == 1
+
+
+def test_fp16_storage_planning_without_device():
+    for n in (2, 16, 60, 1000, 4096, 16384):
+        d = fb.plan_query(n, 3, opts=fb.make_opts(storage=fb.STORAGE_F16))
+        assert d["storage"] == 1 and "_f16" in d["kernel_name"], n
+        assert d["flags"] & fb.VARIANT_FP16_STORAGE
+    for L in (15, 20, 22):
+        d = fb.plan_query(1 << L, 1, opts=fb.make_opts(storage=fb.STORAGE_F16))
+        assert d["path"] == fb.PATH_FOURSTEP
+        assert "_f16" in d["kernel_name"] and "_f16" in d["kernel_name2"]
+        assert d["workspace_bytes"] == 8 << L          # the workspace stays complex64
+    # complex64 plans never pick an FP16 kernel
+    assert "_f16" not in fb.plan_query(4096, 1)["kernel_name"]
+    assert fb.plan_query(4096, 1)["storage"] == 0
+    with pytest.raises(fb.FFTError) as ei:
+        fb.plan_query(4096, 1, opts=fb.make_opts(storage=2))
+    assert ei.value.status == 1
+    with pytest.raises(fb.FFTError) as ei:                  # FP16 flag on a complex64 plan
+        fb.plan_query(4096, 1, opts=fb.make_opts(flags=fb.VARIANT_FP16_STORAGE | 35))
+    assert ei.value.status == 1
+    with pytest.raises(fb.FFTError) as ei:                  # complex64 kernel on an FP16 plan
+        fb.plan_query(4096, 1, opts=fb.make_opts(flags=35, storage=fb.STORAGE_F16))
+    assert ei.value.status == 1
+    d = fb.plan_query(4096, 1, opts=fb.make_opts(device_twiddles=True))
+    assert d["device_twiddles"] == 1 and d["storage"] == 0
+
+
+def test_plan_twiddles_argument_errors_without_device():
+    lib = fb.load()
+    cnt = ctypes.c_size_t(7)
+    assert lib.fft_plan_twiddles(None, None, 0, ctypes.byref(cnt)) == 5
+    assert lib.fft_plan_twiddles(ctypes.c_void_p(0xdead0), None, 0, ctypes.byref(cnt)) == 5
+
+
+def test_filter_planning_without_device():
+    for n in (64, 1024, 8192, 16384):
+        d = fb.filter_query(n, 7, 625 if n >= 1024 else n // 2)
+        assert d["path"] == fb.PATH_FILTER and d["kernel_name"].startswith("range_compress<")
+        assert d["workspace_bytes"] == 0 and d["kernels_per_execute"] == 1
+        assert d["twiddle_bytes"] >= 8 * n          # stage table + the replica spectrum
+    for args, status in (((8192, 0, 10), 1), ((8192, 1, 0), 1), ((8192, 1, 8193), 1),
+                         ((100, 1, 10), 2), ((32, 1, 10), 2), ((32768, 1, 10), 2)):
+        with pytest.raises(fb.FFTError) as ei:
+            fb.filter_query(*args)
+        assert ei.value.status == status, args
+    with pytest.raises(fb.FFTError) as ei:
+        fb.filter_query(8192, 1, 10, fb.make_opts(storage=fb.STORAGE_F16))
+    assert ei.value.status == 1
+    lib = fb.load()
+    h = ctypes.c_void_p(5)
+    assert lib.fft_filter_create(8192, 1, None, 10, None, ctypes.byref(h)) == 1
+    assert lib.fft_filter_create(8192, 1, ctypes.c_void_p(0x10004), 10, None, ctypes.byref(h)) == 1
+    assert lib.fft_filter_create(8192, 1, ctypes.c_void_p(0x10000), 10, None, None) == 1
+    assert h.value is None

@@ -1,0 +1,179 @@
+"""The precision form on the GPU: twiddle tables evaluated in FP64 on the
+device, and FP16 storage with FP32 arithmetic.
+
+Twiddles: the host and the device both evaluate exp(-2 pi i m / n) in FP64
+and round once to FP32, so the tables agree to one FP32 ulp (they differ only
+where the two FP64 sin/cos results straddle an FP32 rounding boundary).
+
+FP16 storage: the kernels widen FP16 inputs to FP32, run the same FP32 stages
+as the complex64 kernels of the same schedule and round the outputs once to
+FP16 (nearest even).  Stated error against the exact DFT of the FP16-valued
+input: relative L2 at most 2^-11 (the output rounding alone is at most 2^-11
+per element relative to its own magnitude, about 2^-12.8 in L2 for
+uniformly distributed rounding errors) plus the FP32 tolerance.  The
+complex64 path on the same input, rounded to FP16, agrees to one FP16 ulp and
+almost always bitwise: the two kernels share the schedule and the source of
+every stage, but the compiler may contract a different handful of multiply-add
+pairs into FMAs, which moves the FP32 value by an ulp and, rarely, across an
+FP16 rounding boundary; the bound applied is one FP16 ulp plus the FP32
+tolerance times the transform's rms magnitude.
+
+End to end (FP16 rounding of the complex64 input included) the error against
+the exact DFT of the complex64 input is bounded by 2 * 2^-11 plus the FP32
+tolerance (input and output rounding, each at most 2^-11 in relative L2, the
+DFT being a scaled isometry).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import metrics
+from paper_1505_08067_amd import fftblock as fb
+from paper_1505_08067_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP16_BOUND = 2.0 ** -11
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _f32_ulp(x):
+    return np.spacing(np.abs(x).astype(np.float32))
+
+
+TW_CASES = [
+    (4096, 8, -1),            # power rows (default)
+    (1024, 4, 0),             # exact rows
+    (4096, 8, fb.VARIANT_PERSISTENT | 3),   # factorised rows
+    (6000, 2, -1),            # mixed radix rows
+    (1 << 20, 1, -1),         # four-step: stages, hi/lo, column powers
+    (1 << 22, 1, -1),
+]
+
+
+@pytest.mark.parametrize("n,batch,flags", TW_CASES)
+def test_device_twiddles_match_host_tables(n, batch, flags):
+    say(f"case: twiddle table n={n} flags={flags}")
+    fb.wisdom_clear()
+    o_host = fb.make_opts(flags=flags)
+    o_dev = fb.make_opts(flags=flags, device_twiddles=True)
+    with fb.Plan(n, batch, opts=o_host) as p_host, fb.Plan(n, batch, opts=o_dev) as p_dev:
+        assert p_dev.describe()["device_twiddles"] == 1
+        assert p_dev.describe()["kernel_name"] == p_host.describe()["kernel_name"]
+        th, td = p_host.twiddles(), p_dev.twiddles()
+        assert th.shape == td.shape and th.size > 0
+        same = np.mean(th.view(np.uint32) == td.view(np.uint32))
+        dre = np.abs(th.real.astype(np.float64) - td.real)
+        dim = np.abs(th.imag.astype(np.float64) - td.imag)
+        say(f"  {th.size} entries, bitwise identical {same:.6f}, max |diff| {max(dre.max(), dim.max()):.2e}")
+        assert np.all(dre <= _f32_ulp(th.real)) and np.all(dim <= _f32_ulp(th.imag))
+        assert same >= 0.999
+        # unit modulus where an entry is set (zero padding elsewhere)
+        mag = np.abs(td.astype(np.complex128))
+        set_ = mag > 0
+        assert np.all(np.abs(mag[set_] - 1.0) < 3e-7)
+        # transforms with the device tables against the oracle
+        x = inputs.uniform(n + 3, batch, n)
+        for sign in (fb.FORWARD, fb.BACKWARD):
+            with fb.Plan(n, batch, sign, opts=fb.make_opts(flags=flags, device_twiddles=True)) as q:
+                y = q.execute(torch.from_numpy(x).to("cuda")).cpu().numpy()
+            mx, _, tol = metrics.check(y, oracle.fft(x.astype(np.complex128), sign), n)
+            say(f"  sign {sign}: max rel L2 {mx:.2e} (tol {tol:.1e})")
+        if same == 1.0:
+            xd = torch.from_numpy(x).to("cuda")
+            a = p_host.execute(xd).cpu().numpy()
+            b = p_dev.execute(xd).cpu().numpy()
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def _to_half(x):
+    """complex64 numpy -> complex32 device tensor and its exact complex128 value."""
+    t = torch.from_numpy(x).to("cuda").to(torch.complex32)
+    exact = torch.view_as_real(t).float().cpu().numpy().astype(np.float64)
+    return t, exact[..., 0] + 1j * exact[..., 1]
+
+
+def _from_half(t):
+    r = torch.view_as_real(t).float().cpu().numpy().astype(np.float64)
+    return r[..., 0] + 1j * r[..., 1]
+
+
+FP16_SIZES = [(2, 64), (16, 64), (64, 33), (256, 17), (1024, 9), (4096, 5), (8192, 3), (16384, 2),
+              (3, 50), (15, 20), (60, 9), (100, 7), (1000, 5), (3072, 3), (6000, 2), (15360, 2),
+              (1 << 15, 2), (1 << 20, 1), (1 << 22, 1)]
+
+
+@pytest.mark.parametrize("n,batch", FP16_SIZES)
+def test_fp16_storage_error_and_equivalence(n, batch):
+    say(f"case: fp16 storage n={n} batch={batch}")
+    fb.wisdom_clear()
+    x = inputs.uniform(n * 7 + 1, batch, n)
+    xh, xexact = _to_half(x)
+    oh = fb.make_opts(storage=fb.STORAGE_F16)
+    for sign in (fb.FORWARD, fb.BACKWARD):
+        with fb.Plan(n, batch, sign, opts=oh) as p:
+            d = p.describe()
+            assert d["storage"] == 1
+            y = p.execute(xh)
+            torch.cuda.synchronize()
+            assert y.dtype == torch.complex32
+            yn = _from_half(y)
+        ref = oracle.fft(xexact.reshape(batch, n), sign)
+        err = metrics.rel_l2_per_transform(yn.reshape(batch, n), ref)
+        tol = FP16_BOUND + metrics.tolerance(max(n, 2))
+        say(f"  sign {sign}: {d['kernel_name']} max rel L2 {err.max():.3e} (bound {tol:.3e})")
+        assert np.all(err <= tol)
+        e2e = metrics.rel_l2_per_transform(yn.reshape(batch, n), oracle.fft(x.astype(np.complex128), sign))
+        say(f"  end to end (FP32 input rounded to FP16): max rel L2 {e2e.max():.3e} (bound {tol + FP16_BOUND:.3e})")
+        assert np.all(e2e <= tol + FP16_BOUND)
+        # the complex64 path on the same FP16-valued input, rounded once
+        with fb.Plan(n, batch, sign) as q:
+            y32 = q.execute(xh.to(torch.complex64))
+            y32h = y32.to(torch.complex32)
+            torch.cuda.synchronize()
+        a16 = torch.view_as_real(y).cpu().numpy().reshape(batch, n, 2)
+        b16 = torch.view_as_real(y32h).cpu().numpy().reshape(batch, n, 2)
+        same = np.mean(a16.view(np.int16) == b16.view(np.int16))
+        ulp = np.spacing(np.maximum(np.abs(a16), np.abs(b16))).astype(np.float64)
+        diff = np.abs(a16.astype(np.float64) - b16.astype(np.float64))
+        # an FMA moves the FP32 value by rounding error of the transform's scale
+        rms = np.sqrt(np.mean(np.abs(ref) ** 2, axis=1))[:, None, None]
+        slack = metrics.tolerance(max(n, 2)) * rms
+        say(f"  vs complex64 path rounded: bitwise identical {same:.5f}, "
+            f"max diff {np.max(diff / (ulp + slack)):.2f} of (1 ulp + FP32 tolerance x rms)")
+        assert np.all(diff <= ulp + slack) and same >= 0.99
+
+
+def test_fp16_storage_in_place_and_closed_form():
+    n, batch = 4096, 4
+    oh = fb.make_opts(storage=fb.STORAGE_F16)
+    # delta at index 0 -> all ones, exactly representable
+    x = np.zeros((batch, n), np.complex64)
+    x[:, 0] = 1.0
+    xh, _ = _to_half(x)
+    with fb.Plan(n, batch, opts=oh) as p:
+        p.execute(xh, out=xh)
+        torch.cuda.synchronize()
+    y = _from_half(xh)
+    assert np.array_equal(y, np.ones((batch, n)))
+    # roundtrip of an FP16 signal: n * x within the stated bound twice over
+    x = inputs.uniform(5, batch, n)
+    xh, xexact = _to_half(x)
+    with fb.Plan(n, batch, fb.FORWARD, opts=oh) as f, fb.Plan(n, batch, fb.BACKWARD, opts=oh) as b:
+        z = _from_half(b.execute(f.execute(xh))) / n
+    err = metrics.rel_l2_per_transform(z.reshape(batch, n), xexact.reshape(batch, n))
+    say(f"  fp16 roundtrip rel L2 {err.max():.3e}")
+    assert np.all(err <= 2 * FP16_BOUND + 2 * metrics.tolerance(n))
+
+
+def test_fp16_storage_rejects_complex64_buffers():
+    with fb.Plan(256, 2, opts=fb.make_opts(storage=fb.STORAGE_F16)) as p:
+        with pytest.raises(TypeError):
+            p.execute(torch.zeros(512, dtype=torch.complex64, device="cuda"))
+    with fb.Plan(256, 2) as p:
+        with pytest.raises(TypeError):
+            p.execute(torch.zeros(512, dtype=torch.complex32, device="cuda"))

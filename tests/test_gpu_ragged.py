@@ -114,3 +114,33 @@ def test_autotune_sets_wisdom_and_stays_correct(tmp_path):
     txt = path.read_text()
     assert "\n1024\t" in txt and "\n6000\t" in txt and "\n1048576\t" in txt
     fb.wisdom_clear()
+
+
+def test_ragged_fp16_storage():
+    """The ragged mix in the FP16-storage form: graph == plain == each class
+    alone (bitwise), and every class within 2^-11 + the FP32 tolerance of the
+    exact DFT of its FP16-valued input."""
+    classes = CLASSES
+    say(f"case: ragged fp16 {classes}")
+    x = _ragged_input(classes, 950)
+    xh = torch.from_numpy(x).to("cuda").to(torch.complex32)
+    xr = torch.view_as_real(xh).float().cpu().numpy().astype(np.float64)
+    xexact = xr[..., 0] + 1j * xr[..., 1]
+    with fb.Ragged(classes, storage=fb.STORAGE_F16) as r:
+        yg = r.execute(xh)
+        yp = r.execute(xh, graph=False)
+        torch.cuda.synchronize()
+        g16 = torch.view_as_real(yg).cpu().numpy()
+        assert np.array_equal(g16.view(np.int16), torch.view_as_real(yp).cpu().numpy().view(np.int16))
+    y = g16.astype(np.float64)
+    y = y[..., 0] + 1j * y[..., 1]
+    at = 0
+    for n, c in classes:
+        ref = oracle.fft(xexact[at:at + n * c].reshape(c, n))
+        err = metrics.rel_l2_per_transform(y[at:at + n * c].reshape(c, n), ref)
+        say(f"  class N={n} x{c}: max rel L2 {err.max():.2e}")
+        assert np.all(err <= 2.0 ** -11 + metrics.tolerance(n))
+        with fb.Plan(n, c, opts=fb.make_opts(storage=fb.STORAGE_F16)) as p:
+            alone = torch.view_as_real(p.execute(xh[at:at + n * c].clone())).cpu().numpy()
+        assert np.array_equal(alone.view(np.int16), g16[at:at + n * c].view(np.int16)), n
+        at += n * c

@@ -46,12 +46,25 @@ def test_block_variant(k):
     batch = 2 * k["c"] + 1
     if persistent:
         batch = max(batch, (1 << 24) // n + 3)   # more units than resident workgroups
-    opts = fb.make_opts(radix=k["radix"], flags=k["flags"])
+    fp16 = bool(k["flags"] & fb.VARIANT_FP16_STORAGE)
+    opts = fb.make_opts(radix=k["radix"], flags=k["flags"], storage=fb.STORAGE_F16 if fp16 else fb.STORAGE_C64)
     x = inputs.uniform(300 + n, batch, n)
     for sign in (fb.FORWARD, fb.BACKWARD):
+        say(f"{k['name']} batch={batch} sign={sign}")
+        if fp16:
+            # FP16 storage: against the exact DFT of the FP16-valued input
+            with fb.Plan(n, batch, sign, opts) as p:
+                d = p.describe()
+                xh = torch.from_numpy(x).to("cuda").to(torch.complex32)
+                y = torch.view_as_real(p.execute(xh)).float().cpu().numpy().astype(np.float64)
+                xr = torch.view_as_real(xh).float().cpu().numpy().astype(np.float64)
+            assert d["kernel_name"] == k["name"]
+            ref = oracle.fft(xr[..., 0] + 1j * xr[..., 1], sign)
+            err = metrics.rel_l2_per_transform(y[..., 0] + 1j * y[..., 1], ref)
+            assert np.all(err <= 2.0 ** -11 + metrics.tolerance(max(n, 2)))
+            continue
         y, d = run(n, batch, sign, opts, x)
         assert d["kernel_name"] == k["name"]
-        say(f"{k['name']} batch={batch} grid={d['grid']} sign={sign}")
         ref = oracle.fft(x.astype(np.complex128), sign)
         metrics.check(y, ref, n)
 
@@ -59,7 +72,9 @@ def test_block_variant(k):
 def _pass_combos():
     # every pass-1 kernel with a plain pass 2 of each workspace width, and
     # every pass-2 kernel with the default pass 1
-    ks = fb.kernels()
+    # (FP16-storage passes pair only with each other: their defaults are covered
+    # with the precision tests)
+    ks = [k for k in fb.kernels() if not k["flags"] & fb.VARIANT_FP16_STORAGE]
     p1 = [k for k in ks if k["kind"] == "pass1" and k["n"] == 1024]
     p2 = [k for k in ks if k["kind"] == "pass2" and k["n"] == 1024]
     plain2 = [k for k in p2 if k["flags"] == 0]

@@ -328,3 +328,18 @@ def test_range_compress_shift_and_linearity():
                        atol=1e-10)
     with pytest.raises(ValueError):
         oracle.range_compress(x, np.ones(n + 1))
+
+
+def test_range_compress_sar_rows_peak_at_every_delay():
+    # the SAR rows (32 chirps, random phases, 10 dB noise): exactly the samples
+    # at the target delays rise above 0.6 n L after compression
+    from paper_1505_08067_amd import inputs
+    n, L = 8192, 625
+    x = inputs.sar(2, pulses=4)
+    ref = inputs.sar_replica()
+    assert ref.size == L and np.allclose(np.abs(ref), 1.0)
+    y = oracle.range_compress(x.astype(np.complex128), ref.astype(np.complex128))
+    delays = set(int(d) for d in inputs.sar_delays(2))
+    for row in range(4):
+        peaks = set(np.nonzero(np.abs(y[row]) > 0.6 * n * L)[0].tolist())
+        assert peaks == delays
