@@ -318,12 +318,131 @@ def run_extras(torch, fb, inputs, stream):
     sar["forward_frac_hbm_at_48B_per_point"] = round(48.0 * pts / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
     sar["shape"] = f"{P} pulses x {R} range samples"
     out["sar_chain"] = sar
+    # range compression (matched filter), fused into one pass over the rows,
+    # then the corner turn and the azimuth FFT: the compressed forward chain
+    rep = torch.from_numpy(inputs.sar_replica()).to("cuda")
+    with fb.RangeCompressor(R, P, rep) as rc:
+        kname = rc.describe()["kernel_name"]
+        chain = [("range_compress", lambda: rc.execute_ptr(x.data_ptr(), t1.data_ptr(), sh)),
+                 ("corner_turn", lambda: fb.transpose(t1.view(P, R), out=t2.view(R, P))),
+                 ("azimuth_fft", lambda: af.execute_ptr(t2.data_ptr(), t3.data_ptr(), sh))]
+        for _ in range(2):
+            for _, f in chain:
+                f()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(chain) + 1)] for _ in range(reps)]
+        for r in range(reps):
+            for i, (_, f) in enumerate(chain):
+                evs[r][i].record(stream)
+                f()
+            evs[r][len(chain)].record(stream)
+        torch.cuda.synchronize()
+    comp = {"kernel": kname}
+    for i, (name, _) in enumerate(chain):
+        ms = sum(evs[r][i].elapsed_time(evs[r][i + 1]) for r in range(reps)) / reps
+        comp[name] = {"us": round(ms * 1e3, 1), "GBps": round(16.0 * pts / (ms * 1e-3) / 1e9, 1),
+                      "frac_hbm_peak": round(16.0 * pts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+    rc_s = comp["range_compress"]["us"] * 1e-6
+    # two transforms per row (forward and backward) plus the product
+    comp["range_compress"]["GFLOPs"] = round(2 * 5.0 * pts * math.log2(R) / rc_s / 1e9, 1)
+    out["sar_range_compression"] = comp
+    log("range compression", json.dumps(comp))
     for p in (rf, af, ab, rb):
         p.close()
     del x, t1, t2, t3
     log("SAR", json.dumps(sar))
+    out["fp16_storage"] = run_fp16(torch, fb, inputs, stream)
     out["ragged"] = run_ragged(torch, fb, inputs, stream)
+    out["serving"] = run_serving(torch, fb, inputs)
     return out
+
+
+def _timed(torch, stream, fn, reps=10):
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def run_fp16(torch, fb, inputs, stream):
+    """FP16 storage (FP32 arithmetic): 4096 x 4096 and 2^20 x 16 forward, 8 B per point per pass."""
+    res = {}
+    sh = stream.cuda_stream
+    for n, batch in ((4096, 4096), (1 << 20, 16)):
+        x = torch.from_numpy(inputs.uniform(1, batch, n)).to("cuda").to(torch.complex32)
+        y = torch.empty_like(x)
+        with fb.Plan(n, batch, fb.FORWARD, fb.make_opts(storage=fb.STORAGE_F16)) as p:
+            d = p.describe()
+            t = _timed(torch, stream, lambda: p.execute_ptr(x.data_ptr(), y.data_ptr(), sh))
+        passes = 2 if d["path"] == fb.PATH_FOURSTEP else 1
+        res[f"{n}x{batch}"] = {
+            "kernels": [d["kernel_name"]] + ([d["kernel_name2"]] if passes == 2 else []),
+            "us": round(t * 1e6, 1), "GFLOPs": round(5.0 * n * math.log2(n) * batch / t / 1e9, 1),
+            "GBps_storage": round(8.0 * n * batch * passes / t / 1e9, 1),
+            "note": "pass-1 output and pass-2 input stay complex64 on the four-step path" if passes == 2 else ""}
+        del x, y
+    sizes = inputs.ragged_sizes(3)
+    classes = [(int(n), int((sizes == n).sum())) for n in inputs.RAGGED_POW2 + inputs.RAGGED_MIXED]
+    total = sum(n * c for n, c in classes)
+    x = torch.randn(total, dtype=torch.complex64, device="cuda").to(torch.complex32)
+    y = torch.empty_like(x)
+    with fb.Ragged(classes, fb.FORWARD, storage=fb.STORAGE_F16) as r:
+        t = _timed(torch, stream, lambda: r.execute(x, out=y))
+    fl = sum(5.0 * n * math.log2(n) * c for n, c in classes)
+    res["ragged_mix"] = {"total_points": total, "t_graph_us": round(t * 1e6, 1), "GFLOPs": round(fl / t / 1e9, 1)}
+    log("fp16", json.dumps(res))
+    return res
+
+
+def run_serving(torch, fb, inputs):
+    """Poisson arrivals at 2000 requests/s for 10 s (after a 1 s warm-up on a
+    separate server): N = 2^k, k uniform on 8..22, batch log-uniform on
+    [1, 512], direction 50/50, inputs from a pre-generated pool; 64 GiB HBM
+    admission budget.  The pooled server (4 streams, continuous batching) and
+    the plain path (one stream, one launch at a time) replay the same trace."""
+    from paper_1505_08067_amd import serving as sv
+
+    def trace_of(seed, duration):
+        t, n, b, sg = inputs.poisson_trace(seed, 2000.0, duration, 8, 22, 512)
+        return [{"t": float(t[i]), "n": int(n[i]), "batch": int(b[i]), "direction": int(sg[i])}
+                for i in range(t.size)]
+
+    pool_points = (1 << 22) * 512
+    pool = torch.empty(pool_points, dtype=torch.complex64, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4)
+    pool.real.uniform_(-1.0, 1.0, generator=gen)
+    pool.imag.uniform_(-1.0, 1.0, generator=gen)
+    warm, trace = trace_of(40, 1.0), trace_of(4, 10.0)
+    w_offs, offs = sv.trace_offsets(41, warm, pool_points), sv.trace_offsets(5, trace, pool_points)
+    pts = sum(r["n"] * r["batch"] for r in trace)
+    fl = sum(5.0 * r["n"] * math.log2(r["n"]) * r["batch"] for r in trace)
+    res = {"requests": len(trace), "rate_per_s": 2000.0, "duration_s": 10.0, "budget_bytes": 64 << 30}
+    for name, kw in (("pooled", {}), ("plain", {"n_streams": 1, "max_inflight": 1, "max_coalesce": 1})):
+        for phase, tr, of in (("warmup", warm, w_offs), ("timed", trace, offs)):
+            with sv.Server(hbm_budget=64 << 30, auto_release=True, **kw) as srv:
+                for k in range(8, 23):
+                    srv.prepare(1 << k, fb.FORWARD)
+                    srv.prepare(1 << k, fb.BACKWARD)
+                st = sv.replay(srv, tr, pool, of)
+            log(f"serving {name} {phase}: {st['completed']} requests in {st['wall']:.2f} s")
+        res[name] = {
+            "completed": st["completed"], "rejected": st["rejected"], "launches": st["launches"],
+            "coalesced_requests": st["coalesced_requests"],
+            "p50_ms": round(st["latency_p50"] * 1e3, 3), "p99_ms": round(st["latency_p99"] * 1e3, 3),
+            "mean_ms": round(st["latency_mean"] * 1e3, 3), "max_ms": round(st["latency_max"] * 1e3, 3),
+            "peak_inflight_GiB": round(st["peak_inflight_bytes"] / 2 ** 30, 2),
+            "wall_s": round(st["wall"], 3), "GFLOPs": round(fl / st["wall"] / 1e9, 1),
+            "points_per_s": round(pts / st["wall"], 1)}
+    del pool
+    log("serving", json.dumps(res))
+    return res
 
 
 def run_ragged(torch, fb, inputs, stream):

@@ -54,7 +54,8 @@ typedef enum {
     FFT_ERR_UNSUPPORTED_SIZE = 2,  /* a length the library has no kernels for */
     FFT_ERR_OUT_OF_MEMORY = 3,     /* hipMalloc failed */
     FFT_ERR_DEVICE = 4,            /* any other HIP runtime error (launch, copy, device query) */
-    FFT_ERR_INVALID_PLAN = 5       /* null or destroyed plan handle */
+    FFT_ERR_INVALID_PLAN = 5,      /* null or destroyed plan (or scheduler / server) handle */
+    FFT_ERR_TIMEOUT = 6            /* a wait of the serving layer ran out of time */
 } fft_status_t;
 
 /* Direction = sign of the exponent in the definition above. */
@@ -423,6 +424,131 @@ fft_status_t fft_ragged_describe(fft_ragged_t r, size_t* total_points, size_t* g
 
 /* Synchronise the device and free the plans, graph, streams and events. */
 fft_status_t fft_ragged_destroy(fft_ragged_t r);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a request scheduler and a GPU server built on it.
+ *
+ * Requests (n, batch, direction) arrive over time.  The scheduler admits them
+ * in arrival order while the bytes of the requests in flight (input, output
+ * and four-step workspace) stay within an HBM budget; a request larger than
+ * the budget is rejected, one that does not fit yet waits at the head of the
+ * queue.  Each launch goes to the stream with the fewest outstanding bytes
+ * among those with fewer than max_inflight launches outstanding.  Continuous
+ * batching: queued requests of the same (n, direction) on the single-block
+ * path join the head request's launch (one list launch), in arrival order,
+ * up to max_coalesce requests and max_transforms transforms.  Latency =
+ * completion time - arrival time.
+ *
+ * The scheduler alone (fft_sched_*) is a host-only state machine: it makes
+ * no HIP call and takes every time as an argument (seconds, any monotonic
+ * clock), so it can be driven by a simulated executor.  The server
+ * (fft_server_*) runs it on a dispatcher thread against the device.
+ * ------------------------------------------------------------------------- */
+#define FFT_LAUNCH_MAX_REQUESTS 64
+
+/* Request states. */
+#define FFT_REQ_QUEUED 0
+#define FFT_REQ_RUNNING 1
+#define FFT_REQ_DONE 2
+#define FFT_REQ_REJECTED 3   /* larger than the whole budget */
+
+typedef struct {
+    size_t hbm_budget;   /* bytes in flight at most (default 64 GiB) */
+    int n_streams;       /* 1..16 (default 4) */
+    int max_inflight;    /* launches outstanding per stream, >= 1 (default 2) */
+    int max_coalesce;    /* requests per launch, 1..FFT_LAUNCH_MAX_REQUESTS (default 32; 1 = off) */
+    size_t max_transforms;  /* transforms per coalesced launch (default 16384) */
+} fft_sched_opts_t;
+
+typedef struct {
+    long long id;        /* launch id, for fft_sched_complete */
+    int stream;          /* 0..n_streams-1 */
+    size_t n;
+    int direction;
+    size_t batch;        /* transforms of the launch (sum over its requests) */
+    size_t bytes;        /* budget bytes of the launch */
+    int n_requests;
+    uint64_t requests[FFT_LAUNCH_MAX_REQUESTS];   /* request ids, arrival order */
+} fft_launch_t;
+
+typedef struct {
+    uint64_t id;
+    size_t n, batch;
+    int direction;
+    int state;           /* FFT_REQ_* */
+    size_t bytes;
+    double t_arrive, t_launch, t_done;   /* seconds; -1 = not yet */
+    long long launch;    /* -1 until launched */
+    int stream;
+    int group_size;      /* requests in its launch */
+} fft_request_info_t;
+
+typedef struct {
+    size_t submitted, completed, rejected, queued;
+    size_t running_launches, launches;
+    size_t coalesced_requests;    /* requests that shared a launch with others */
+    size_t inflight_bytes, peak_inflight_bytes;
+    double points;                /* transform points completed (n * batch summed) */
+    double t_last_done;
+    double latency_p50, latency_p99, latency_mean, latency_max;   /* seconds, nearest rank */
+} fft_sched_stats_t;
+
+typedef struct fft_sched_s* fft_sched_t;
+
+void fft_sched_opts_init(fft_sched_opts_t* opts);
+/* INVALID_ARG for options out of range. */
+fft_status_t fft_sched_create(const fft_sched_opts_t* opts, fft_sched_t* out);
+fft_status_t fft_sched_destroy(fft_sched_t s);
+/* Queue a request (ids must be unique); `coalescible` marks requests that may
+ * share a list launch.  INVALID_ARG for zero sizes, a bad direction or a
+ * duplicate id. */
+fft_status_t fft_sched_submit(fft_sched_t s, uint64_t id, size_t n, size_t batch, int direction, size_t bytes,
+                              int coalescible, double now);
+/* The next launch to issue at time `now`, if any (*got = 1).  The caller
+ * issues it and reports its completion with fft_sched_complete. */
+fft_status_t fft_sched_next(fft_sched_t s, double now, fft_launch_t* launch, int* got);
+fft_status_t fft_sched_complete(fft_sched_t s, long long launch_id, double now);
+fft_status_t fft_sched_request(fft_sched_t s, uint64_t id, fft_request_info_t* info);
+fft_status_t fft_sched_stats(fft_sched_t s, fft_sched_stats_t* stats);
+
+typedef struct {
+    fft_sched_opts_t sched;
+    size_t arena_bytes;  /* device memory for outputs and workspaces; 0 = sched.hbm_budget */
+    int auto_release;    /* nonzero: outputs are dropped at completion (load generation) */
+} fft_server_opts_t;
+
+typedef struct fft_server_s* fft_server_t;
+
+void fft_server_opts_init(fft_server_opts_t* opts);
+/* Allocates the arena, the stream pool and the list-descriptor buffers on the
+ * current device and starts the dispatcher thread. */
+fft_status_t fft_server_create(const fft_server_opts_t* opts, fft_server_t* out);
+/* Create the plan for (n, direction) now rather than at its first request
+ * (plans and twiddle tables stay resident for the server's lifetime). */
+fft_status_t fft_server_prepare(fft_server_t s, size_t n, int direction);
+/* Queue a request; `in` is a DEVICE pointer to batch * n complex64 values that
+ * must stay valid and unchanged until the request completes.  The output is
+ * allocated from the server's arena.  Non-blocking. */
+fft_status_t fft_server_submit(fft_server_t s, size_t n, size_t batch, int direction, const void* in,
+                               uint64_t* ticket);
+/* Block until the request completes (TIMEOUT after timeout_s seconds);
+ * *out = its output in the arena (valid until fft_server_release), *info its
+ * record.  OUT_OF_MEMORY for a rejected request.  Not for auto_release
+ * servers. */
+fft_status_t fft_server_wait(fft_server_t s, uint64_t ticket, double timeout_s, void** out,
+                             fft_request_info_t* info);
+/* Copy a completed request's output (batch * n complex64) to the DEVICE
+ * pointer dst on `stream` (asynchronous; NULL = the null stream). */
+fft_status_t fft_server_read(fft_server_t s, uint64_t ticket, void* dst, void* stream);
+/* Free a completed request's output and record. */
+fft_status_t fft_server_release(fft_server_t s, uint64_t ticket);
+/* Block until every submitted request has completed. */
+fft_status_t fft_server_drain(fft_server_t s, double timeout_s);
+fft_status_t fft_server_stats(fft_server_t s, fft_sched_stats_t* stats);
+/* The server's clock (seconds since creation), the time base of its records. */
+double fft_server_clock(fft_server_t s);
+/* Drain, stop the dispatcher and free everything. */
+fft_status_t fft_server_destroy(fft_server_t s);
 
 #ifdef __cplusplus
 }

@@ -307,6 +307,7 @@ const char* fft_status_string(fft_status_t s)
         case FFT_ERR_OUT_OF_MEMORY: return "device out of memory";
         case FFT_ERR_DEVICE: return "HIP runtime error";
         case FFT_ERR_INVALID_PLAN: return "invalid plan handle";
+        case FFT_ERR_TIMEOUT: return "timed out";
     }
     return "unknown status";
 }

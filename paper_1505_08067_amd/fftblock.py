@@ -41,6 +41,10 @@ EXPORTS = (
     "fft_wisdom_get", "fft_wisdom_clear", "fft_wisdom_save", "fft_wisdom_load",
     "fft_ragged_create", "fft_ragged_execute", "fft_ragged_describe", "fft_ragged_destroy",
     "fft_plan_twiddles", "fft_ragged_create_ex", "fft_filter_create", "fft_filter_query", "fft_execute_ex",
+    "fft_sched_opts_init", "fft_sched_create", "fft_sched_destroy", "fft_sched_submit", "fft_sched_next",
+    "fft_sched_complete", "fft_sched_request", "fft_sched_stats",
+    "fft_server_opts_init", "fft_server_create", "fft_server_prepare", "fft_server_submit", "fft_server_wait",
+    "fft_server_read", "fft_server_release", "fft_server_drain", "fft_server_stats", "fft_server_clock", "fft_server_destroy",
 )
 
 VARIANT_NT_LOAD = 1
@@ -117,6 +121,57 @@ class TuneReport(ctypes.Structure):
     ]
 
 
+class SchedOpts(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_size_t), ("n_streams", ctypes.c_int), ("max_inflight", ctypes.c_int),
+        ("max_coalesce", ctypes.c_int), ("max_transforms", ctypes.c_size_t),
+    ]
+
+
+LAUNCH_MAX_REQUESTS = 64
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_REJECTED = 0, 1, 2, 3
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_longlong), ("stream", ctypes.c_int), ("n", ctypes.c_size_t), ("direction", ctypes.c_int),
+        ("batch", ctypes.c_size_t), ("bytes", ctypes.c_size_t), ("n_requests", ctypes.c_int),
+        ("requests", ctypes.c_uint64 * LAUNCH_MAX_REQUESTS),
+    ]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [
+        ("id", ctypes.c_uint64), ("n", ctypes.c_size_t), ("batch", ctypes.c_size_t), ("direction", ctypes.c_int),
+        ("state", ctypes.c_int), ("bytes", ctypes.c_size_t), ("t_arrive", ctypes.c_double),
+        ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double), ("launch", ctypes.c_longlong),
+        ("stream", ctypes.c_int), ("group_size", ctypes.c_int),
+    ]
+
+
+class SchedStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_size_t), ("completed", ctypes.c_size_t), ("rejected", ctypes.c_size_t),
+        ("queued", ctypes.c_size_t), ("running_launches", ctypes.c_size_t), ("launches", ctypes.c_size_t),
+        ("coalesced_requests", ctypes.c_size_t), ("inflight_bytes", ctypes.c_size_t),
+        ("peak_inflight_bytes", ctypes.c_size_t), ("points", ctypes.c_double), ("t_last_done", ctypes.c_double),
+        ("latency_p50", ctypes.c_double), ("latency_p99", ctypes.c_double), ("latency_mean", ctypes.c_double),
+        ("latency_max", ctypes.c_double),
+    ]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("sched", SchedOpts), ("arena_bytes", ctypes.c_size_t), ("auto_release", ctypes.c_int)]
+
+
+def _struct_dict(st) -> dict:
+    out = {}
+    for name, _ in st._fields_:
+        v = getattr(st, name)
+        out[name] = list(v) if isinstance(v, ctypes.Array) else v
+    return out
+
+
 _lib = None
 
 
@@ -175,6 +230,29 @@ def load():
     lib.fft_ragged_create_ex.argtypes = [szp, szp, sz, i, vp, ctypes.POINTER(vp)]
     lib.fft_ragged_create_ex.restype = ctypes.c_int
     lib.fft_plan_twiddles.restype = ctypes.c_int
+    u64, dbl = ctypes.c_uint64, ctypes.c_double
+    lib.fft_sched_opts_init.argtypes = [ctypes.POINTER(SchedOpts)]
+    lib.fft_sched_opts_init.restype = None
+    lib.fft_sched_create.argtypes = [ctypes.POINTER(SchedOpts), ctypes.POINTER(vp)]
+    lib.fft_sched_destroy.argtypes = [vp]
+    lib.fft_sched_submit.argtypes = [vp, u64, sz, sz, i, sz, i, dbl]
+    lib.fft_sched_next.argtypes = [vp, dbl, ctypes.POINTER(Launch), ctypes.POINTER(i)]
+    lib.fft_sched_complete.argtypes = [vp, ctypes.c_longlong, dbl]
+    lib.fft_sched_request.argtypes = [vp, u64, ctypes.POINTER(RequestInfo)]
+    lib.fft_sched_stats.argtypes = [vp, ctypes.POINTER(SchedStats)]
+    lib.fft_server_opts_init.argtypes = [ctypes.POINTER(ServerOpts)]
+    lib.fft_server_opts_init.restype = None
+    lib.fft_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    lib.fft_server_prepare.argtypes = [vp, sz, i]
+    lib.fft_server_submit.argtypes = [vp, sz, sz, i, vp, ctypes.POINTER(u64)]
+    lib.fft_server_wait.argtypes = [vp, u64, dbl, ctypes.POINTER(vp), ctypes.POINTER(RequestInfo)]
+    lib.fft_server_release.argtypes = [vp, u64]
+    lib.fft_server_read.argtypes = [vp, u64, vp, vp]
+    lib.fft_server_drain.argtypes = [vp, dbl]
+    lib.fft_server_stats.argtypes = [vp, ctypes.POINTER(SchedStats)]
+    lib.fft_server_clock.argtypes = [vp]
+    lib.fft_server_clock.restype = dbl
+    lib.fft_server_destroy.argtypes = [vp]
     for name in ("fft_schedule_search", "fft_stage_benchmark", "fft_autotune", "fft_wisdom_set",
                  "fft_wisdom_save", "fft_wisdom_load", "fft_ragged_create", "fft_ragged_execute",
                  "fft_ragged_describe", "fft_ragged_destroy"):
