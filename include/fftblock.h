@@ -183,6 +183,7 @@ typedef struct {
     int c;               /* four-step pass-1 columns per workgroup; 0 = default */
     int flags2;          /* variant of pass 2; -1 = default */
     int c2;              /* pass-2 rows per workgroup (workspace block width); 0 = default */
+    size_t n1;           /* four-step split n = n1 * n2 (a power of two); 0 = default 2^ceil(log2(n)/2) */
     int storage;         /* FFT_STORAGE_C64 (default) or FFT_STORAGE_F16 */
     int device_twiddles; /* nonzero: evaluate the twiddle tables in FP64 on the GPU
                             (default: FP64 on the host); both round once to FP32 */

@@ -160,7 +160,7 @@ const KEntry* wisdom_kernel(size_t n)
     return find_named(kKindBlock, n, name);
 }
 
-bool wisdom_pair(size_t n, size_t n1, size_t n2, const KEntry** k1, const KEntry** k2)
+bool wisdom_pair(size_t n, const KEntry** k1, const KEntry** k2)
 {
     load_env_wisdom();
     Wisdom& w = wisdom();
@@ -171,9 +171,14 @@ bool wisdom_pair(size_t n, size_t n1, size_t n2, const KEntry** k1, const KEntry
         if (it == w.choice.end() || it->second.second.empty()) return false;
         names = it->second;
     }
-    *k1 = find_named(kKindPass1, n1, names.first);
-    *k2 = find_named(kKindPass2, n2, names.second);
-    return *k1 && *k2;
+    int c = 0;
+    const KEntry* t = kernel_table(&c);
+    *k1 = *k2 = nullptr;
+    for (int i = 0; i < c; ++i) {
+        if (t[i].kind == kKindPass1 && names.first == t[i].name && wisdom_eligible(t[i])) *k1 = &t[i];
+        if (t[i].kind == kKindPass2 && names.second == t[i].name && wisdom_eligible(t[i])) *k2 = &t[i];
+    }
+    return *k1 && *k2 && (size_t)(*k1)->n * (size_t)(*k2)->n == n;
 }
 
 }  // namespace fb
@@ -357,13 +362,23 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
     fft_plan_desc_t dq;
     const bool four = fft_plan_query(n, batch, FFT_FORWARD, &dq) == FFT_SUCCESS && dq.path == FFT_PATH_FOURSTEP;
     if (four) {
-        // pass-1 x pass-2 pairs (schedules, column/row widths, variants)
+        // the default split with every pass-1 x pass-2 pair (schedules,
+        // column/row widths, variants), then the neighbouring splits with
+        // their default passes
+        const size_t d1 = dq.n1;
+        const size_t splits[3] = {d1, d1 / 2, d1 * 2};
+        for (int sp = 0; sp < 3; ++sp) {
+        const size_t n1 = splits[sp], n2 = n / n1;
+        if (n1 < 2 || n2 < 2 || n1 * n2 != n) continue;
         for (int i = 0; i < count && e == hipSuccess; ++i) {
-            if (t[i].kind != kKindPass1 || (size_t)t[i].n != dq.n1 || dq.n2 % t[i].c || !wisdom_eligible(t[i])) continue;
-            for (int j = 0; j < count && e == hipSuccess && rep->n_candidates < 32; ++j) {
-                if (t[j].kind != kKindPass2 || (size_t)t[j].n != dq.n2 || dq.n1 % t[j].c || !wisdom_eligible(t[j])) continue;
+            if (t[i].kind != kKindPass1 || (size_t)t[i].n != n1 || n2 % t[i].c || !wisdom_eligible(t[i])) continue;
+            if (sp > 0 && !t[i].is_default) continue;
+            for (int j = 0; j < count && e == hipSuccess && rep->n_candidates < (sp == 0 ? 28 : 32); ++j) {
+                if (t[j].kind != kKindPass2 || (size_t)t[j].n != n2 || n1 % t[j].c || !wisdom_eligible(t[j])) continue;
+                if (sp > 0 && !t[j].is_default) continue;
                 fft_plan_opts_t o;
                 fft_plan_opts_init(&o);
+                o.n1 = n1;
                 o.flags = t[i].flags;
                 o.c = t[i].c;
                 o.flags2 = t[j].flags;
@@ -387,6 +402,7 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
                     rep->chosen_us = us;
                 }
             }
+        }
         }
     }
     for (int i = 0; i < count && e == hipSuccess && rep->n_candidates < 32 && !four; ++i) {

@@ -77,8 +77,9 @@ const KEntry* list_entries(int* count);
 
 // Kernel the wisdom (autotuner or FFTBLOCK_WISDOM file) chose for length n, or nullptr.
 const KEntry* wisdom_kernel(size_t n);
-// Four-step kernels the wisdom chose for length n = n1 * n2 (false if none).
-bool wisdom_pair(size_t n, size_t n1, size_t n2, const KEntry** k1, const KEntry** k2);
+// Four-step kernels the wisdom chose for length n (false if none); their
+// lengths give the split n = k1->n * k2->n.
+bool wisdom_pair(size_t n, const KEntry** k1, const KEntry** k2);
 
 // One segment of a plan's twiddle table: entries [offset, offset + count)
 // hold exp(-2 pi i m / n) rounded once from FP64 to FP32, with (m, n) a

@@ -85,7 +85,7 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [
         ("block_limit", ctypes.c_size_t), ("n_radix", ctypes.c_int), ("radix", ctypes.c_int * 8),
         ("flags", ctypes.c_int), ("c", ctypes.c_int), ("flags2", ctypes.c_int), ("c2", ctypes.c_int),
-        ("storage", ctypes.c_int), ("device_twiddles", ctypes.c_int),
+        ("n1", ctypes.c_size_t), ("storage", ctypes.c_int), ("device_twiddles", ctypes.c_int),
     ]
 
 
@@ -306,7 +306,7 @@ def _desc_dict(d: "PlanDesc") -> dict:
     }
 
 
-def make_opts(block_limit=0, radix=None, flags=-1, c=0, flags2=-1, c2=0, storage=0, device_twiddles=False):
+def make_opts(block_limit=0, radix=None, flags=-1, c=0, flags2=-1, c2=0, storage=0, device_twiddles=False, n1=0):
     """Planner options (``fft_plan_opts_t``); every default means "planner's choice"."""
     o = PlanOpts()
     load().fft_plan_opts_init(ctypes.byref(o))
@@ -317,6 +317,7 @@ def make_opts(block_limit=0, radix=None, flags=-1, c=0, flags2=-1, c2=0, storage
             o.radix[k] = r
     o.flags, o.c, o.flags2, o.c2 = flags, c, flags2, c2
     o.storage, o.device_twiddles = storage, 1 if device_twiddles else 0
+    o.n1 = int(n1)
     return o
 
 

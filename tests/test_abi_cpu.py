@@ -88,12 +88,18 @@ def test_plan_query_block_and_fourstep():
             assert d["lds_bytes"] <= 160 * 1024
         else:
             assert d["path"] == fb.PATH_FOURSTEP and d["kernels_per_execute"] == 2
-            assert d["n1"] * d["n2"] == n and d["n1"] >= d["n2"]
+            assert d["n1"] * d["n2"] == n
+            # rows (pass 2) up to 2048, columns (pass 1) at least 256
+            assert d["n2"] == min(2048, n // 256) and d["n1"] == n // d["n2"]
             assert math.prod(d["radix"]) == d["n1"] and math.prod(d["radix2"]) == d["n2"]
             assert d["workspace_bytes"] == 8 * n * 3
             assert d["lds_bytes"] <= 160 * 1024
     d = fb.plan_query(1 << 20, 16)
+    assert (d["n1"], d["n2"]) == (512, 2048)
+    d = fb.plan_query(1 << 20, 16, opts=fb.make_opts(n1=1024))
     assert (d["n1"], d["n2"]) == (1024, 1024)
+    with pytest.raises(fb.FFTError):
+        fb.plan_query(1 << 20, 16, opts=fb.make_opts(n1=3))
     assert fb.plan_query(1, 5)["path"] == fb.PATH_BLOCK
 
 

@@ -90,7 +90,7 @@ def _pass_combos():
 @pytest.mark.parametrize("k1,k2", _pass_combos())
 def test_fourstep_variant_pairs(k1, k2):
     n, batch = 1 << 20, 3
-    opts = fb.make_opts(flags=k1["flags"], c=k1["c"], flags2=k2["flags"], c2=k2["c"])
+    opts = fb.make_opts(flags=k1["flags"], c=k1["c"], flags2=k2["flags"], c2=k2["c"], n1=1024)
     x = inputs.uniform(400, batch, n)
     y, d = run(n, batch, fb.FORWARD, opts, x)
     assert (d["kernel_name"], d["kernel_name2"]) == (k1["name"], k2["name"])
