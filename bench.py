@@ -48,6 +48,7 @@ def parse():
     p.add_argument("--no-extras", action="store_true", help="skip copy probe and SAR chain timing")
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.md"),
                    help="rocprofv3 traffic summary (measured HBM bytes per launch per kernel)")
+    p.add_argument("--no-serving", action="store_true", help="skip the serving stream (profiling runs)")
     p.add_argument("--calibrate", action="store_true",
                    help="also run the copy kernel on 256 MiB three times (counter calibration)")
     return p.parse_args()
@@ -212,7 +213,7 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        extras = run_extras(torch, fb, inputs, stream)
+        extras = run_extras(torch, fb, inputs, stream, serving=not args.no_serving)
     if args.calibrate:
         src = torch.empty((1 << 28) // 8, dtype=torch.complex64, device="cuda")
         dst = torch.empty_like(src)
@@ -260,7 +261,7 @@ def main():
         p.close()
 
 
-def run_extras(torch, fb, inputs, stream):
+def run_extras(torch, fb, inputs, stream, serving=True):
     out = {}
     # HBM copy probe: 1 GiB, read + write counted
     nbytes = 1 << 30
@@ -353,9 +354,11 @@ def run_extras(torch, fb, inputs, stream):
         p.close()
     del x, t1, t2, t3
     log("SAR", json.dumps(sar))
-    for key, fn in (("fp16_storage", lambda: run_fp16(torch, fb, inputs, stream)),
-                    ("ragged", lambda: run_ragged(torch, fb, inputs, stream)),
-                    ("serving", lambda: run_serving(torch, fb, inputs))):
+    todo = [("fp16_storage", lambda: run_fp16(torch, fb, inputs, stream)),
+            ("ragged", lambda: run_ragged(torch, fb, inputs, stream))]
+    if serving:
+        todo.append(("serving", lambda: run_serving(torch, fb, inputs)))
+    for key, fn in todo:
         try:
             out[key] = fn()
         except fb.FFTError as e:

@@ -32,7 +32,18 @@
 
 namespace fb {
 
-enum : int { kSwz = 8, kStaged = 16, kTwPow = 32 };
+enum : int { kSwz = 8, kStaged = 16, kTwPow = 32, kXcd = 128 };
+
+// Workgroup b of a grid of G is dispatched to XCD b mod 8.  The XCD-ordered
+// variants give each XCD a contiguous range of work units, so neighbouring
+// units (which share cache lines at the edges of their column or row
+// ranges) meet in the same L2.  A bijection on [0, G) when 8 divides G, the
+// identity otherwise.
+__device__ __forceinline__ long long xcd_unit(long long b, long long G)
+{
+    if ((G & 7) != 0) return b;
+    return (b & 7) * (G >> 3) + (b >> 3);
+}
 
 // LDS index map: padded (default) or XOR-swizzled within 16-value groups.
 template <int FL>
@@ -482,8 +493,10 @@ k_fft(KArgs a)
 
     if constexpr ((FL & kPipe) == 0) {
         float2 v[E];
-        load(v, blockIdx.x);
-        finish(v, blockIdx.x);
+        long long unit = blockIdx.x;
+        if constexpr ((FL & kXcd) != 0) unit = xcd_unit(unit, gridDim.x);
+        load(v, unit);
+        finish(v, unit);
     } else {
         const long long units = P::units(a, C);
         long long u = blockIdx.x;

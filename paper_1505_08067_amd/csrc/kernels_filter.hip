@@ -14,16 +14,19 @@ static const KEntry kFilter[] = {
     FB_FLT(true, 35, 128, 16, 32, 16, 8),
     FB_FLT(true, 35, 256, 16, 16, 16, 16),
     FB_FLT(true, 35, 512, 16, 8, 16, 16, 2),
-    FB_FLT(true, 35, 1024, 8, 2, 8, 8, 4, 4),
-    FB_FLT(true, 35, 2048, 16, 2, 16, 16, 8),
+    FB_FLT(false, 35, 1024, 8, 2, 8, 8, 4, 4),
+    FB_FLT(false, 35, 2048, 16, 2, 16, 16, 8),
     FB_FLT(true, 35, 4096, 16, 1, 16, 16, 16),
-    FB_FLT(true, 35, 8192, 16, 1, 8, 8, 8, 16),
-    FB_FLT(true, 35, 16384, 16, 1, 16, 16, 16, 4),
+    FB_FLT(false, 35, 8192, 16, 1, 8, 8, 8, 16),
+    FB_FLT(false, 35, 16384, 16, 1, 16, 16, 16, 4),
     // first radix equal to the last: no LDS round trip between the transforms
-    FB_FLT(false, 35, 1024, 16, 4, 16, 4, 16),
+    // (measured faster at 1024, 2048, 8192 and 16384)
+    FB_FLT(true, 35, 1024, 16, 4, 16, 4, 16),
     FB_FLT(false, 35, 8192, 16, 1, 16, 8, 4, 16),
-    FB_FLT(false, 35, 8192, 16, 1, 16, 2, 16, 16),
-    FB_FLT(false, 35, 16384, 16, 1, 16, 4, 16, 16),
+    FB_FLT(true, 35, 8192, 16, 1, 16, 2, 16, 16),
+    FB_FLT(false, 43, 8192, 16, 1, 16, 2, 16, 16),
+    FB_FLT(true, 35, 2048, 16, 2, 16, 8, 16),
+    FB_FLT(true, 35, 16384, 16, 1, 16, 4, 16, 16),
     FB_FLT(false, 3, 8192, 16, 1, 8, 8, 8, 16),
 };
 

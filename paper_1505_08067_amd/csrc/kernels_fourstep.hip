@@ -28,6 +28,19 @@ namespace fb {
     make_entry<N, E, C, Sched<__VA_ARGS__>, PolPass2H, FL>(DEF, "fourstep_pass2_f16<" #N ",C" #C ",[" #__VA_ARGS__ "],v" #FL ">")
 
 static const KEntry kPass[] = {
+    // narrower tiles (more workgroups per CU, half-line runs), plain and
+    // XCD-ordered so the neighbouring tiles that complete a cache line run in
+    // the same L2: measured slower than the defaults at 2^19..2^21
+    FB_P1(false, 177, 512, 16, 8, 16, 16, 2),
+    FB_P1(false, 177, 1024, 16, 8, 16, 16, 4),
+    FB_P2(false, 161, 2048, 16, 4, 16, 16, 8),
+    // pass 2 reads the workspace pass 1 has just written (partly still in the
+    // Infinity Cache): cached loads, power-row twiddles, with / without
+    // streaming stores
+    FB_P2(false, 32, 512, 16, 16, 16, 16, 2),
+    FB_P2(false, 32, 1024, 16, 8, 16, 16, 4),
+    FB_P2(false, 32, 2048, 16, 8, 16, 16, 8),
+    FB_P2(false, 0, 512, 16, 16, 16, 16, 2),
     // FP16 storage (pass 1 reads FP16, pass 2 writes FP16; workspace FP32)
     FB_P1H(true, 113, 32, 16, 16, 16, 2),
     FB_P1H(true, 113, 64, 16, 16, 16, 4),
@@ -36,13 +49,13 @@ static const KEntry kPass[] = {
     FB_P1H(true, 113, 512, 16, 16, 16, 16, 2),
     FB_P1H(true, 113, 1024, 16, 16, 16, 16, 4),
     FB_P1H(true, 113, 2048, 16, 8, 16, 16, 8),
-    FB_P2H(true, 97, 32, 16, 16, 16, 2),
-    FB_P2H(true, 97, 64, 16, 16, 16, 4),
-    FB_P2H(true, 97, 128, 16, 16, 16, 8),
-    FB_P2H(true, 97, 256, 16, 16, 16, 16),
-    FB_P2H(true, 97, 512, 16, 16, 16, 16, 2),
-    FB_P2H(true, 97, 1024, 16, 8, 16, 16, 4),
-    FB_P2H(true, 97, 2048, 16, 8, 16, 16, 8),
+    FB_P2H(true, 98, 32, 16, 16, 16, 2),
+    FB_P2H(true, 98, 64, 16, 16, 16, 4),
+    FB_P2H(true, 98, 128, 16, 16, 16, 8),
+    FB_P2H(true, 98, 256, 16, 16, 16, 16),
+    FB_P2H(true, 98, 512, 16, 16, 16, 16, 2),
+    FB_P2H(true, 98, 1024, 16, 8, 16, 16, 4),
+    FB_P2H(true, 98, 2048, 16, 8, 16, 16, 8),
     // planner defaults.  Pass 1: non-temporal loads, power-row twiddles
     // (stage and long), outputs staged through LDS for contiguous stores
     // (49).  Pass 2: non-temporal loads, power-row twiddles (33).
@@ -53,13 +66,22 @@ static const KEntry kPass[] = {
     FB_P1(true, 49, 512, 16, 16, 16, 16, 2),
     FB_P1(true, 49, 1024, 16, 16, 16, 16, 4),
     FB_P1(true, 49, 2048, 16, 8, 16, 16, 8),
-    FB_P2(true, 33, 32, 16, 16, 16, 2),
-    FB_P2(true, 33, 64, 16, 16, 16, 4),
-    FB_P2(true, 33, 128, 16, 16, 16, 8),
-    FB_P2(true, 33, 256, 16, 16, 16, 16),
-    FB_P2(true, 33, 512, 16, 16, 16, 16, 2),
-    FB_P2(true, 33, 1024, 16, 8, 16, 16, 4),
-    FB_P2(true, 33, 2048, 16, 8, 16, 16, 8),
+    // pass 2: cached loads of the workspace pass 1 has just written (partly
+    // still in the Infinity Cache), streaming stores of the result
+    FB_P2(true, 34, 32, 16, 16, 16, 2),
+    FB_P2(true, 34, 64, 16, 16, 16, 4),
+    FB_P2(true, 34, 128, 16, 16, 16, 8),
+    FB_P2(true, 34, 256, 16, 16, 16, 16),
+    FB_P2(true, 34, 512, 16, 16, 16, 16, 2),
+    FB_P2(true, 34, 1024, 16, 8, 16, 16, 4),
+    FB_P2(true, 34, 2048, 16, 8, 16, 16, 8),
+    FB_P2(false, 33, 32, 16, 16, 16, 2),
+    FB_P2(false, 33, 64, 16, 16, 16, 4),
+    FB_P2(false, 33, 128, 16, 16, 16, 8),
+    FB_P2(false, 33, 256, 16, 16, 16, 16),
+    FB_P2(false, 33, 512, 16, 16, 16, 16, 2),
+    FB_P2(false, 33, 1024, 16, 8, 16, 16, 4),
+    FB_P2(false, 33, 2048, 16, 8, 16, 16, 8),
     // plain and other variants (1: nt load, 16: staged store, 32: power twiddles)
     FB_P1(false, 0, 1024, 16, 16, 16, 16, 4),
     FB_P1(false, 0, 1024, 16, 8, 16, 16, 4),
@@ -74,6 +96,9 @@ static const KEntry kPass[] = {
     FB_P2(false, 1, 1024, 16, 8, 16, 16, 4),
     FB_P2(false, 33, 1024, 16, 16, 16, 16, 4),
     FB_P2(false, 0, 2048, 16, 8, 16, 16, 8),
+    // half-line tiles (found by explicit width only)
+    FB_P1(false, 49, 512, 16, 8, 16, 16, 2),
+    FB_P2(false, 33, 2048, 16, 4, 16, 16, 8),
 };
 
 const KEntry* pass_entries(int* count)

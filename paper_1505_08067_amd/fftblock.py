@@ -54,6 +54,7 @@ VARIANT_SWIZZLE = 8
 VARIANT_STAGED = 16
 VARIANT_TWIDDLE_POWERS = 32
 VARIANT_FP16_STORAGE = 64
+VARIANT_XCD_ORDER = 128
 STORAGE_C64 = 0
 STORAGE_F16 = 1
 KERNEL_KINDS = {0: "block", 1: "pass1", 2: "pass2", 3: "filter", 4: "list"}
