@@ -49,6 +49,8 @@ def parse():
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.md"),
                    help="rocprofv3 traffic summary (measured HBM bytes per launch per kernel)")
     p.add_argument("--no-serving", action="store_true", help="skip the serving stream (profiling runs)")
+    p.add_argument("--extras", default=",".join(("copy", "sar", "fp16", "ragged", "serving")),
+                   help="comma list of extras to run: copy, sar, fp16, ragged, serving")
     p.add_argument("--calibrate", action="store_true",
                    help="also run the copy kernel on 256 MiB three times (counter calibration)")
     return p.parse_args()
@@ -213,7 +215,10 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        extras = run_extras(torch, fb, inputs, stream, serving=not args.no_serving)
+        which = set(t for t in args.extras.split(",") if t)
+        if args.no_serving:
+            which.discard("serving")
+        extras = run_extras(torch, fb, inputs, stream, which)
     if args.calibrate:
         src = torch.empty((1 << 28) // 8, dtype=torch.complex64, device="cuda")
         dst = torch.empty_like(src)
@@ -261,9 +266,35 @@ def main():
         p.close()
 
 
-def run_extras(torch, fb, inputs, stream, serving=True):
+EXTRAS = ("copy", "sar", "fp16", "ragged", "serving")
+
+
+def run_extras(torch, fb, inputs, stream, which=EXTRAS):
     out = {}
-    # HBM copy probe: 1 GiB, read + write counted
+    todo = [("copy_probe", "copy", lambda: run_copy(torch, fb, stream)),
+            ("sar", "sar", lambda: run_sar(torch, fb, inputs, stream)),
+            ("fp16_storage", "fp16", lambda: run_fp16(torch, fb, inputs, stream)),
+            ("ragged", "ragged", lambda: run_ragged(torch, fb, inputs, stream)),
+            ("serving", "serving", lambda: run_serving(torch, fb, inputs))]
+    for key, tag, fn in todo:
+        if tag not in which:
+            continue
+        try:
+            res = fn()
+        except fb.FFTError as e:
+            # a failed extra is reported, not fatal to the headline line
+            res = {"error": str(e)}
+            log(f"{key} failed: {e}")
+            torch.cuda.synchronize()
+        if key == "sar" and "error" not in res:
+            out.update(res)
+        else:
+            out[key] = res
+    return out
+
+
+def run_copy(torch, fb, stream):
+    """HBM copy probe: 1 GiB, read + write counted."""
     nbytes = 1 << 30
     a = torch.empty(nbytes // 8, dtype=torch.complex64, device="cuda")
     b = torch.empty_like(a)
@@ -279,10 +310,15 @@ def run_extras(torch, fb, inputs, stream, serving=True):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    out["copy_probe"] = {"bytes": nbytes, "GBps_read_plus_write": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+    res = {"bytes": nbytes, "GBps_read_plus_write": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
     del a, b
-    log("copy probe", out["copy_probe"])
+    log("copy probe", res)
+    return res
 
+
+def run_sar(torch, fb, inputs, stream):
+    """The radar chain on 4096 pulses x 8192 range samples, and range compression."""
+    out = {}
     # SAR chain: range FFT (8192 x 4096) -> corner turn -> azimuth FFT (4096 x 8192), and back
     P, R = 4096, 8192
     x = torch.from_numpy(inputs.sar(2, pulses=P, ranges=R)).to("cuda")
@@ -354,18 +390,6 @@ def run_extras(torch, fb, inputs, stream, serving=True):
         p.close()
     del x, t1, t2, t3
     log("SAR", json.dumps(sar))
-    todo = [("fp16_storage", lambda: run_fp16(torch, fb, inputs, stream)),
-            ("ragged", lambda: run_ragged(torch, fb, inputs, stream))]
-    if serving:
-        todo.append(("serving", lambda: run_serving(torch, fb, inputs)))
-    for key, fn in todo:
-        try:
-            out[key] = fn()
-        except fb.FFTError as e:
-            # a failed extra is reported, not fatal to the headline line
-            out[key] = {"error": str(e)}
-            log(f"{key} failed: {e}")
-            torch.cuda.synchronize()
     return out
 
 
@@ -418,8 +442,10 @@ def run_serving(torch, fb, inputs):
     """Poisson arrivals at 2000 requests/s for 10 s (after a 1 s warm-up on a
     separate server): N = 2^k, k uniform on 8..22, batch log-uniform on
     [1, 512], direction 50/50, inputs from a pre-generated pool; 64 GiB HBM
-    admission budget.  The pooled server (4 streams, continuous batching) and
-    the plain path (one stream, one launch at a time) replay the same trace."""
+    admission budget.  The pooled server (4 streams, continuous batching,
+    bounded backfill of requests up to 1 GiB past a waiting head) and the
+    plain path (one stream, one launch at a time, strict FIFO) replay the
+    same trace."""
     from paper_1505_08067_amd import serving as sv
 
     def trace_of(seed, duration):
@@ -438,7 +464,7 @@ def run_serving(torch, fb, inputs):
     pts = sum(r["n"] * r["batch"] for r in trace)
     fl = sum(5.0 * r["n"] * math.log2(r["n"]) * r["batch"] for r in trace)
     res = {"requests": len(trace), "rate_per_s": 2000.0, "duration_s": 10.0, "budget_bytes": 64 << 30}
-    for name, kw in (("pooled", {}), ("plain", {"n_streams": 1, "max_inflight": 1, "max_coalesce": 1})):
+    for name, kw in (("pooled", {}), ("plain", {"n_streams": 1, "max_inflight": 1, "max_coalesce": 1, "backfill_bytes": 0})):
         for phase, tr, of in (("warmup", warm, w_offs), ("timed", trace, offs)):
             with sv.Server(hbm_budget=64 << 30, auto_release=True, **kw) as srv:
                 for k in range(8, 23):
@@ -448,7 +474,7 @@ def run_serving(torch, fb, inputs):
             log(f"serving {name} {phase}: {st['completed']} requests in {st['wall']:.2f} s")
         res[name] = {
             "completed": st["completed"], "rejected": st["rejected"], "launches": st["launches"],
-            "coalesced_requests": st["coalesced_requests"],
+            "coalesced_requests": st["coalesced_requests"], "backfilled_requests": st["backfilled_requests"],
             "p50_ms": round(st["latency_p50"] * 1e3, 3), "p99_ms": round(st["latency_p99"] * 1e3, 3),
             "mean_ms": round(st["latency_mean"] * 1e3, 3), "max_ms": round(st["latency_max"] * 1e3, 3),
             "peak_inflight_GiB": round(st["peak_inflight_bytes"] / 2 ** 30, 2),

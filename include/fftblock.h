@@ -434,7 +434,7 @@ fft_status_t fft_ragged_destroy(fft_ragged_t r);
  * in arrival order while the bytes of the requests in flight (input, output
  * and four-step workspace) stay within an HBM budget; a request larger than
  * the budget is rejected, one that does not fit yet waits at the head of the
- * queue.  Each launch goes to the stream with the fewest outstanding bytes
+ * queue, and while it waits only small requests (backfill_bytes) may pass it.  Each launch goes to the stream with the fewest outstanding bytes
  * among those with fewer than max_inflight launches outstanding.  Continuous
  * batching: queued requests of the same (n, direction) on the single-block
  * path join the head request's launch (one list launch), in arrival order,
@@ -460,6 +460,9 @@ typedef struct {
     int max_inflight;    /* launches outstanding per stream, >= 1 (default 2) */
     int max_coalesce;    /* requests per launch, 1..FFT_LAUNCH_MAX_REQUESTS (default 32; 1 = off) */
     size_t max_transforms;  /* transforms per coalesced launch (default 16384) */
+    size_t backfill_bytes;  /* while the head request waits for room, later requests of at most this
+                               many bytes may pass it, at most this many bytes of them in flight
+                               (default 1 GiB; 0 = strict FIFO) */
 } fft_sched_opts_t;
 
 typedef struct {
@@ -489,6 +492,7 @@ typedef struct {
     size_t submitted, completed, rejected, queued;
     size_t running_launches, launches;
     size_t coalesced_requests;    /* requests that shared a launch with others */
+    size_t backfilled_requests;   /* requests admitted past a waiting head */
     size_t inflight_bytes, peak_inflight_bytes;
     double points;                /* transform points completed (n * batch summed) */
     double t_last_done;

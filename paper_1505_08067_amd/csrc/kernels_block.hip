@@ -19,6 +19,10 @@ namespace fb {
                                                                  "],v" #FL ">")
 
 static const KEntry kBlock[] = {
+    // eight values per thread: twice the waves per workgroup at the same LDS
+    FB_BLK(false, 35, 4096, 8, 1, 8, 8, 8, 8),
+    FB_BLK(false, 35, 8192, 8, 1, 8, 8, 8, 8, 2),
+    FB_BLK(false, 35, 2048, 8, 2, 8, 8, 4, 8),
     // FP16 storage, FP32 arithmetic (64 + 35)
     FB_BLKH(true, 99, 2, 2, 256, 2),
     FB_BLKH(true, 99, 4, 4, 256, 4),

@@ -49,6 +49,9 @@ static const KEntry kPass[] = {
     FB_P1H(true, 113, 512, 16, 16, 16, 16, 2),
     FB_P1H(true, 113, 1024, 16, 16, 16, 16, 4),
     FB_P1H(true, 113, 2048, 16, 8, 16, 16, 8),
+    // 32 FP16 columns = 128-byte runs
+    FB_P1H(false, 113, 256, 16, 32, 16, 16),
+    FB_P1H(false, 113, 512, 16, 32, 16, 16, 2),
     FB_P2H(true, 98, 32, 16, 16, 16, 2),
     FB_P2H(true, 98, 64, 16, 16, 16, 4),
     FB_P2H(true, 98, 128, 16, 16, 16, 8),

@@ -5,8 +5,11 @@
 // Scheduling rules (fft_sched_next):
 //   * requests are admitted in arrival order (FIFO); a request larger than
 //     the whole budget is rejected, a request that does not fit the bytes
-//     still free waits at the head of the queue (no bypass, so large requests
-//     cannot starve);
+//     still free waits at the head of the queue;
+//   * while the head waits, later requests of at most backfill_bytes may
+//     pass it, with at most backfill_bytes of such requests in flight at a
+//     time, so the head is delayed by little and never starved
+//     (backfill_bytes = 0: strict FIFO);
 //   * the launch goes to the stream with the fewest outstanding bytes among
 //     those with fewer than max_inflight launches outstanding;
 //   * continuous batching: queued requests of the same (n, direction) that
@@ -46,6 +49,7 @@ struct SReq {
     long long launch = -1;
     int stream = -1;
     int group = 0;
+    uint64_t seq = 0;   // arrival order
 };
 
 struct SLaunch {
@@ -53,6 +57,7 @@ struct SLaunch {
     int stream = 0;
     size_t n = 0, batch = 0, bytes = 0;
     int dir = FFT_FORWARD;
+    bool backfill = false;
     std::vector<uint64_t> reqs;
 };
 
@@ -75,6 +80,7 @@ public:
         r.bytes = bytes;
         r.coalescible = coalescible && batch <= o_.max_transforms;
         r.t_arrive = now;
+        r.seq = next_seq_++;
         reqs_[id] = r;
         queue_.push_back(id);
         ++submitted_;
@@ -91,25 +97,39 @@ public:
             queue_.pop_front();
         }
         if (queue_.empty()) return false;
-        SReq& head = reqs_[queue_.front()];
-        if (inflight_ + head.bytes > o_.hbm_budget) return false;
         int s = -1;
         for (int i = 0; i < o_.n_streams; ++i)
             if (out_[(size_t)i] < o_.max_inflight && (s < 0 || outb_[(size_t)i] < outb_[(size_t)s])) s = i;
         if (s < 0) return false;
+        // the head, or -- while the head waits for room -- the first small
+        // request that fits (backfill, bounded so the head is not starved)
+        auto pick = queue_.begin();
+        bool backfill = false;
+        if (inflight_ + reqs_[*pick].bytes > o_.hbm_budget) {
+            if (o_.backfill_bytes == 0) return false;
+            for (++pick; pick != queue_.end(); ++pick) {
+                const SReq& r = reqs_[*pick];
+                if (r.bytes + backfill_inflight_ <= o_.backfill_bytes && inflight_ + r.bytes <= o_.hbm_budget) break;
+            }
+            if (pick == queue_.end()) return false;
+            backfill = true;
+        }
+        SReq& head = reqs_[*pick];
         L->id = next_launch_++;
         L->stream = s;
         L->n = head.n;
         L->dir = head.dir;
         L->batch = head.batch;
         L->bytes = head.bytes;
+        L->backfill = backfill;
         L->reqs.assign(1, head.id);
-        queue_.pop_front();
+        auto after = queue_.erase(pick);
         if (head.coalescible && o_.max_coalesce > 1) {
-            for (auto it = queue_.begin(); it != queue_.end() && (int)L->reqs.size() < o_.max_coalesce;) {
+            for (auto it = backfill ? after : queue_.begin(); it != queue_.end() && (int)L->reqs.size() < o_.max_coalesce;) {
                 const SReq& r = reqs_[*it];
+                const bool room = backfill ? backfill_inflight_ + L->bytes + r.bytes <= o_.backfill_bytes : true;
                 if (r.coalescible && r.n == L->n && r.dir == L->dir && L->batch + r.batch <= o_.max_transforms &&
-                    inflight_ + L->bytes + r.bytes <= o_.hbm_budget) {
+                    room && inflight_ + L->bytes + r.bytes <= o_.hbm_budget) {
                     L->reqs.push_back(r.id);
                     L->batch += r.batch;
                     L->bytes += r.bytes;
@@ -120,6 +140,10 @@ public:
             }
         }
         inflight_ += L->bytes;
+        if (backfill) {
+            backfill_inflight_ += L->bytes;
+            backfilled_ += L->reqs.size();
+        }
         peak_ = std::max(peak_, inflight_);
         out_[(size_t)s] += 1;
         outb_[(size_t)s] += L->bytes;
@@ -143,14 +167,21 @@ public:
     {
         auto it = running_.find(L.id);
         if (it == running_.end()) return;
-        for (auto r = L.reqs.rbegin(); r != L.reqs.rend(); ++r) {
-            SReq& q = reqs_[*r];
+        for (uint64_t id : L.reqs) {
+            SReq& q = reqs_[id];
             q.state = FFT_REQ_QUEUED;
             q.t_launch = -1.0;
             q.launch = -1;
             q.stream = -1;
             q.group = 0;
-            queue_.push_front(*r);
+            // back to its place in arrival order
+            auto at = queue_.begin();
+            while (at != queue_.end() && reqs_[*at].seq < q.seq) ++at;
+            queue_.insert(at, id);
+        }
+        if (L.backfill) {
+            backfill_inflight_ -= L.bytes;
+            backfilled_ -= L.reqs.size();
         }
         inflight_ -= L.bytes;
         out_[(size_t)L.stream] -= 1;
@@ -175,6 +206,7 @@ public:
             if (done) done->push_back(id);
         }
         inflight_ -= L.bytes;
+        if (L.backfill) backfill_inflight_ -= L.bytes;
         out_[(size_t)L.stream] -= 1;
         outb_[(size_t)L.stream] -= L.bytes;
         t_last_ = std::max(t_last_, now);
@@ -216,6 +248,7 @@ public:
         s->running_launches = running_.size();
         s->launches = launches_;
         s->coalesced_requests = coalesced_;
+        s->backfilled_requests = backfilled_;
         s->inflight_bytes = inflight_;
         s->peak_inflight_bytes = peak_;
         s->points = points_;
@@ -245,7 +278,8 @@ private:
     std::map<long long, SLaunch> running_;
     std::vector<int> out_;
     std::vector<size_t> outb_;
-    size_t inflight_ = 0, peak_ = 0;
+    size_t inflight_ = 0, peak_ = 0, backfill_inflight_ = 0, backfilled_ = 0;
+    uint64_t next_seq_ = 0;
     size_t submitted_ = 0, completed_ = 0, rejected_ = 0, launches_ = 0, coalesced_ = 0;
     long long next_launch_ = 0;
     double points_ = 0.0, t_last_ = 0.0;
@@ -312,6 +346,7 @@ void fft_sched_opts_init(fft_sched_opts_t* o)
     o->max_inflight = 2;
     o->max_coalesce = 32;
     o->max_transforms = 16384;
+    o->backfill_bytes = (size_t)1 << 30;
 }
 
 fft_status_t fft_sched_create(const fft_sched_opts_t* opts, fft_sched_t* out)

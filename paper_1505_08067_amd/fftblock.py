@@ -125,7 +125,7 @@ class TuneReport(ctypes.Structure):
 class SchedOpts(ctypes.Structure):
     _fields_ = [
         ("hbm_budget", ctypes.c_size_t), ("n_streams", ctypes.c_int), ("max_inflight", ctypes.c_int),
-        ("max_coalesce", ctypes.c_int), ("max_transforms", ctypes.c_size_t),
+        ("max_coalesce", ctypes.c_int), ("max_transforms", ctypes.c_size_t), ("backfill_bytes", ctypes.c_size_t),
     ]
 
 
@@ -154,7 +154,8 @@ class SchedStats(ctypes.Structure):
     _fields_ = [
         ("submitted", ctypes.c_size_t), ("completed", ctypes.c_size_t), ("rejected", ctypes.c_size_t),
         ("queued", ctypes.c_size_t), ("running_launches", ctypes.c_size_t), ("launches", ctypes.c_size_t),
-        ("coalesced_requests", ctypes.c_size_t), ("inflight_bytes", ctypes.c_size_t),
+        ("coalesced_requests", ctypes.c_size_t), ("backfilled_requests", ctypes.c_size_t),
+        ("inflight_bytes", ctypes.c_size_t),
         ("peak_inflight_bytes", ctypes.c_size_t), ("points", ctypes.c_double), ("t_last_done", ctypes.c_double),
         ("latency_p50", ctypes.c_double), ("latency_p99", ctypes.c_double), ("latency_mean", ctypes.c_double),
         ("latency_max", ctypes.c_double),

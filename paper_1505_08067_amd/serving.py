@@ -18,11 +18,13 @@ import time
 from . import fftblock as fb
 
 
-def sched_opts(hbm_budget=64 << 30, n_streams=4, max_inflight=2, max_coalesce=32, max_transforms=16384):
+def sched_opts(hbm_budget=64 << 30, n_streams=4, max_inflight=2, max_coalesce=32, max_transforms=16384,
+               backfill_bytes=1 << 30):
     o = fb.SchedOpts()
     fb.load().fft_sched_opts_init(ctypes.byref(o))
     o.hbm_budget, o.n_streams, o.max_inflight = int(hbm_budget), int(n_streams), int(max_inflight)
     o.max_coalesce, o.max_transforms = int(max_coalesce), int(max_transforms)
+    o.backfill_bytes = int(backfill_bytes)
     return o
 
 

@@ -119,7 +119,7 @@ def test_replay_short_poisson_stream_pooled_and_plain():
     pool = torch.randn(pool_points, dtype=torch.complex64, device="cuda")
     offs = sv.trace_offsets(5, trace, pool_points)
     res = {}
-    for name, kw in (("pooled", {}), ("plain", {"n_streams": 1, "max_inflight": 1, "max_coalesce": 1})):
+    for name, kw in (("pooled", {}), ("plain", {"n_streams": 1, "max_inflight": 1, "max_coalesce": 1, "backfill_bytes": 0})):
         with sv.Server(hbm_budget=4 << 30, auto_release=True, **kw) as srv:
             for k in range(8, 19):
                 srv.prepare(1 << k, -1)

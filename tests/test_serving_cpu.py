@@ -21,7 +21,7 @@ def test_options_are_checked():
 
 
 def test_fifo_admission_under_budget_without_bypass():
-    with sv.Scheduler(hbm_budget=1000, n_streams=4, max_inflight=4, max_coalesce=1) as s:
+    with sv.Scheduler(hbm_budget=1000, n_streams=4, max_inflight=4, max_coalesce=1, backfill_bytes=0) as s:
         s.submit(1, 64, 1, F, 600, False, 0.0)
         s.submit(2, 128, 1, F, 600, False, 0.1)
         s.submit(3, 256, 1, F, 300, False, 0.2)
@@ -43,6 +43,31 @@ def test_fifo_admission_under_budget_without_bypass():
         lat = sorted([1.0, 2.0 - 0.1, 1.5 - 0.2])
         assert st["latency_p50"] == pytest.approx(lat[1]) and st["latency_max"] == pytest.approx(lat[2])
         assert s.request(2)["t_launch"] == pytest.approx(1.0) and s.request(2)["state"] == fb.REQ_DONE
+
+
+def test_bounded_backfill_past_a_waiting_head():
+    # budget 1000, backfill 250: while the 600-byte head waits, requests of at
+    # most 250 bytes pass it, with at most 250 bytes of them in flight
+    with sv.Scheduler(hbm_budget=1000, n_streams=4, max_inflight=8, max_coalesce=1, backfill_bytes=250) as s:
+        s.submit(1, 64, 1, F, 600, False, 0.0)
+        s.submit(2, 128, 1, F, 600, False, 0.1)     # waits behind 1
+        s.submit(3, 256, 1, F, 300, False, 0.2)     # too large to pass
+        s.submit(4, 512, 1, F, 200, False, 0.3)     # passes
+        s.submit(5, 1024, 1, F, 100, False, 0.4)    # would exceed 250 in flight by backfill
+        a = s.next(0.5)
+        assert a["requests"] == [1]
+        b = s.next(0.5)
+        assert b["requests"] == [4]
+        assert s.next(0.5) is None
+        assert s.request(4)["state"] == fb.REQ_RUNNING and s.request(2)["state"] == fb.REQ_QUEUED
+        s.complete(b["id"], 0.6)
+        c = s.next(0.6)
+        assert c["requests"] == [5]                 # backfill room again
+        s.complete(a["id"], 1.0)
+        d = s.next(1.0)
+        assert d["requests"] == [2]                 # the head goes first once it fits
+        st = s.stats()
+        assert st["backfilled_requests"] == 2
 
 
 def test_oversized_request_is_rejected_and_others_proceed():
@@ -142,7 +167,7 @@ def test_simulated_cfg5_trace_accounting():
         assert st["latency_p50"] == pytest.approx(k(0.5)) and st["latency_p99"] == pytest.approx(k(0.99))
         assert st["points"] == pytest.approx(sum(r["n"] * r["batch"] for r in trace))
     # the plain path (one stream, one launch at a time, no batching) is never faster at p99
-    with sv.Scheduler(hbm_budget=budget, n_streams=1, max_inflight=1, max_coalesce=1) as s:
+    with sv.Scheduler(hbm_budget=budget, n_streams=1, max_inflight=1, max_coalesce=1, backfill_bytes=0) as s:
         plain = sv.simulate(s, trace, _duration)
     assert plain["completed"] == len(trace) and plain["coalesced_requests"] == 0
     assert st["latency_p99"] <= plain["latency_p99"] * (1 + 1e-9)
