@@ -178,7 +178,7 @@ typedef struct {
 
 typedef struct {
     size_t block_limit;  /* longest single-block length; 0 = fft_block_limit() */
-    int n_radix;         /* single-block schedule: 0 = default, else radix[0..n_radix) */
+    int n_radix;         /* schedule of the single block (four-step: of pass 1): 0 = default, else radix[0..n_radix) */
     int radix[8];
     int flags;           /* variant of the block kernel / pass 1; -1 = default */
     int c;               /* four-step pass-1 columns per workgroup; 0 = default */

@@ -379,6 +379,8 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
                 fft_plan_opts_t o;
                 fft_plan_opts_init(&o);
                 o.n1 = n1;
+                o.n_radix = t[i].nr;
+                for (int r = 0; r < t[i].nr; ++r) o.radix[r] = t[i].radix[r];
                 o.flags = t[i].flags;
                 o.c = t[i].c;
                 o.flags2 = t[j].flags;

@@ -422,17 +422,22 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
         p->n2 = n / p->n1;
         const int c1 = o.c > 0 ? o.c : (int)env_size("FFTBLOCK_FOURSTEP_C", 0);
         const int c2 = o.c2 > 0 ? o.c2 : (int)env_size("FFTBLOCK_FOURSTEP_C2", 0);
-        const bool explicit_opts = o.flags >= 0 || o.flags2 >= 0 || o.c > 0 || o.c2 > 0 || o.n1 != 0;
+        const bool explicit_opts = o.flags >= 0 || o.flags2 >= 0 || o.c > 0 || o.c2 > 0 || o.n1 != 0 || o.n_radix > 0;
         if (!explicit_opts && !sto && wisdom_pair(n, &p->k1, &p->k2)) {
             p->n1 = (size_t)p->k1->n;   // the wisdom fixes the split too
             p->n2 = (size_t)p->k2->n;
         } else {
-            p->k1 = o.flags < 0 ? kernel_default(kKindPass1, (int)p->n1, c1, sto)
-                                : kernel_find(kKindPass1, (int)p->n1, nullptr, 0, c1, o.flags);
+            // radix / n_radix select the pass-1 schedule on this path
+            const KEntry* d1 = kernel_default(kKindPass1, (int)p->n1, c1, sto);
+            const int fl1 = o.flags >= 0 ? o.flags : d1 ? d1->flags : -1;
+            p->k1 = (o.flags < 0 && o.n_radix == 0)
+                        ? kernel_default(kKindPass1, (int)p->n1, c1, sto)
+                        : kernel_find(kKindPass1, (int)p->n1, o.n_radix ? o.radix : nullptr, o.n_radix, c1, fl1);
             p->k2 = o.flags2 < 0 ? kernel_default(kKindPass2, (int)p->n2, c2, sto)
                                  : kernel_find(kKindPass2, (int)p->n2, nullptr, 0, c2, o.flags2);
         }
         if (!p->k1 || !p->k2) return FFT_ERR_UNSUPPORTED_SIZE;
+        if (((p->k1->flags & FFT_VARIANT_FP16_STORAGE) != 0) != (sto != 0)) return FFT_ERR_INVALID_ARG;
         if (((p->k2->flags & FFT_VARIANT_FP16_STORAGE) != 0) != (sto != 0)) return FFT_ERR_INVALID_ARG;
         if (p->n2 % p->k1->c || p->n1 % p->k2->c) return FFT_ERR_UNSUPPORTED_SIZE;
         p->lo_bits = (L + 1) / 2;

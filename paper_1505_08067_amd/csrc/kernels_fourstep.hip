@@ -31,6 +31,9 @@ static const KEntry kPass[] = {
     // narrower tiles (more workgroups per CU, half-line runs), plain and
     // XCD-ordered so the neighbouring tiles that complete a cache line run in
     // the same L2: measured slower than the defaults at 2^19..2^21
+    // 32 values per thread: one LDS exchange instead of two
+    FB_P1(false, 49, 512, 32, 16, 32, 16),
+    FB_P1(false, 49, 512, 32, 16, 16, 32),
     FB_P1(false, 177, 512, 16, 8, 16, 16, 2),
     FB_P1(false, 177, 1024, 16, 8, 16, 16, 4),
     FB_P2(false, 161, 2048, 16, 4, 16, 16, 8),
@@ -49,9 +52,10 @@ static const KEntry kPass[] = {
     FB_P1H(true, 113, 512, 16, 16, 16, 16, 2),
     FB_P1H(true, 113, 1024, 16, 16, 16, 16, 4),
     FB_P1H(true, 113, 2048, 16, 8, 16, 16, 8),
-    // 32 FP16 columns = 128-byte runs
+    // 32 FP16 columns = 128-byte runs; 16 FP16 rows = 64-byte output runs
     FB_P1H(false, 113, 256, 16, 32, 16, 16),
     FB_P1H(false, 113, 512, 16, 32, 16, 16, 2),
+    FB_P2H(false, 98, 1024, 16, 16, 16, 16, 4),
     FB_P2H(true, 98, 32, 16, 16, 16, 2),
     FB_P2H(true, 98, 64, 16, 16, 16, 4),
     FB_P2H(true, 98, 128, 16, 16, 16, 8),

@@ -66,7 +66,7 @@ def test_wisdom_roundtrip(tmp_path):
 
 def test_wisdom_pair_for_fourstep(tmp_path):
     fb.wisdom_clear()
-    ks = fb.kernels()
+    ks = [k for k in fb.kernels() if not k["flags"] & fb.VARIANT_FP16_STORAGE]   # wisdom is for complex64
     p1 = [k["name"] for k in ks if k["kind"] == "pass1" and k["n"] == 1024 and not k["is_default"] and k["c"] == 8][0]
     p2 = [k["name"] for k in ks if k["kind"] == "pass2" and k["n"] == 1024 and not k["is_default"] and k["c"] == 16][0]
     path = tmp_path / "w.txt"

@@ -130,3 +130,23 @@ def test_replay_short_poisson_stream_pooled_and_plain():
         assert st["completed"] == len(trace) and st["rejected"] == 0
         res[name] = st
     assert res["pooled"]["latency_p50"] > 0
+
+
+def test_server_edge_lengths():
+    # n = 1 (a copy), a mixed-radix length through its list kernel, the
+    # longest four-step length with its workspace from the arena
+    cases = [(1, 5, -1), (6000, 3, 1), (1 << 22, 2, -1), (3, 7, 1)]
+    data = [torch.from_numpy(inputs.uniform(3000 + i, b, n)).to("cuda") for i, (n, b, _) in enumerate(cases)]
+    with sv.Server(hbm_budget=1 << 30) as srv:
+        tickets = [srv.submit(data[i], n, b, d) for i, (n, b, d) in enumerate(cases)]
+        for i, ((n, b, d), tk) in enumerate(zip(cases, tickets)):
+            say(f"case: server edge n={n} batch={b} sign={d}")
+            y, info = srv.result(tk)
+            x = data[i].cpu().numpy().astype(np.complex128)
+            if n == 1:
+                assert np.array_equal(y.cpu().numpy().reshape(-1), data[i].cpu().numpy())
+            else:
+                metrics.check(y.cpu().numpy(), oracle.fft(x, d), n)
+            srv.release(tk)
+        with pytest.raises(fb.FFTError):
+            srv.release(tickets[0])                    # already released
