@@ -32,7 +32,7 @@
 
 namespace fb {
 
-enum : int { kSwz = 8, kStaged = 16, kTwPow = 32, kXcd = 128 };
+enum : int { kSwz = 8, kStaged = 16, kTwPow = 32, kXcd = 128, kStageStride = 256 };
 
 // Workgroup b of a grid of G is dispatched to XCD b mod 8.  The XCD-ordered
 // variants give each XCD a contiguous range of work units, so neighbouring
@@ -68,7 +68,11 @@ __host__ __device__ constexpr int lds_stride()
     if constexpr ((FL & kSwz) != 0) {
         return N;
     } else {
-        const int want = FFAST ? (C < 16 ? 16 / C : 1) : (T < 16 ? T : 1);
+        int want = FFAST ? (C < 16 ? 16 / C : 1) : (T < 16 ? T : 1);
+        // staged pass-1 stores read 16-lane groups spanning two transforms
+        // CW = 8 values apart: a residue 8 larger (still odd for C = 16, so
+        // the exchanges keep 16 distinct bank pairs) separates the two halves
+        if constexpr ((FL & kStageStride) != 0) want += 8;
         int s = lds_pad(N);
         while ((s & 15) != (want & 15)) ++s;
         return s;

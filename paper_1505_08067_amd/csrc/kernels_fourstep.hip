@@ -31,6 +31,11 @@ static const KEntry kPass[] = {
     // narrower tiles (more workgroups per CU, half-line runs), plain and
     // XCD-ordered so the neighbouring tiles that complete a cache line run in
     // the same L2: measured slower than the defaults at 2^19..2^21
+    // LDS stride residue shifted by 8 for the staged store (flag 256)
+    FB_P1(false, 305, 512, 16, 16, 16, 16, 2),
+    FB_P1(false, 305, 1024, 16, 16, 16, 16, 4),
+    FB_P1(false, 305, 256, 16, 16, 16, 16),
+    FB_P1(false, 305, 2048, 16, 8, 16, 16, 8),
     // 32 values per thread: one LDS exchange instead of two
     FB_P1(false, 49, 512, 32, 16, 32, 16),
     FB_P1(false, 49, 512, 32, 16, 16, 32),

@@ -70,28 +70,64 @@ def test_block_variant(k):
 
 
 def _pass_combos():
-    # every pass-1 kernel with a plain pass 2 of each workspace width, and
-    # every pass-2 kernel with the default pass 1
-    # (FP16-storage passes pair only with each other: their defaults are covered
-    # with the precision tests)
-    ks = [k for k in fb.kernels() if not k["flags"] & fb.VARIANT_FP16_STORAGE]
-    p1 = [k for k in ks if k["kind"] == "pass1" and k["n"] == 1024]
-    p2 = [k for k in ks if k["kind"] == "pass2" and k["n"] == 1024]
+    # 1) at 2^20 = 1024 x 1024: every complex64 pass-1 kernel with a plain pass 2
+    #    of each workspace width, and every pass-2 kernel with the default pass 1;
+    # 2) every other pass kernel (any length, FP16 storage included) with the
+    #    default partner of its storage form, at a split that fits both
+    ks = fb.kernels()
+    c64 = [k for k in ks if not k["flags"] & fb.VARIANT_FP16_STORAGE]
+    p1 = [k for k in c64 if k["kind"] == "pass1" and k["n"] == 1024]
+    p2 = [k for k in c64 if k["kind"] == "pass2" and k["n"] == 1024]
     plain2 = [k for k in p2 if k["flags"] == 0]
     default1 = [k for k in p1 if k["is_default"]]
     combos, seen = [], set()
-    for a, b in [(a, b) for a in p1 for b in plain2] + [(a, b) for a in default1 for b in p2]:
+
+    def add(n1, a, b):
         if (a["name"], b["name"]) not in seen:
             seen.add((a["name"], b["name"]))
-            combos.append(pytest.param(a, b, id=f"{a['name']}+{b['name']}"))
+            combos.append(pytest.param(n1, a, b, id=f"{a['name']}+{b['name']}"))
+
+    for a, b in [(a, b) for a in p1 for b in plain2] + [(a, b) for a in default1 for b in p2]:
+        add(1024, a, b)
+    dflt = {}
+    for k in ks:
+        if k["kind"] in ("pass1", "pass2") and k["is_default"]:
+            dflt[(k["kind"], k["n"], bool(k["flags"] & fb.VARIANT_FP16_STORAGE))] = k
+    for k in ks:
+        half = bool(k["flags"] & fb.VARIANT_FP16_STORAGE)
+        if k["kind"] == "pass1":
+            n1, n2 = k["n"], (2048 if k["n"] <= 1024 else 1024)
+            b = dflt.get(("pass2", n2, half))
+            if b and n2 % k["c"] == 0 and n1 % b["c"] == 0:
+                add(n1, k, b)
+        elif k["kind"] == "pass2":
+            n1 = 512 if k["n"] <= 2048 else 256
+            a = dflt.get(("pass1", n1, half))
+            if a and k["n"] % a["c"] == 0 and n1 % k["c"] == 0:
+                add(n1, a, k)
     return combos
 
 
-@pytest.mark.parametrize("k1,k2", _pass_combos())
-def test_fourstep_variant_pairs(k1, k2):
-    n, batch = 1 << 20, 3
-    opts = fb.make_opts(flags=k1["flags"], c=k1["c"], flags2=k2["flags"], c2=k2["c"], n1=1024)
-    x = inputs.uniform(400, batch, n)
+@pytest.mark.parametrize("n1,k1,k2", _pass_combos())
+def test_fourstep_variant_pairs(n1, k1, k2):
+    n2 = k2["n"]
+    n, batch = n1 * n2, 2
+    half = bool(k1["flags"] & fb.VARIANT_FP16_STORAGE)
+    opts = fb.make_opts(radix=k1["radix"], flags=k1["flags"], c=k1["c"], flags2=k2["flags"], c2=k2["c"], n1=n1,
+                        storage=fb.STORAGE_F16 if half else fb.STORAGE_C64)
+    say(f"case: four-step {n1} x {n2} {k1['name']} + {k2['name']}")
+    x = inputs.uniform(400 + n1, batch, n)
+    if half:
+        with fb.Plan(n, batch, fb.FORWARD, opts) as p:
+            d = p.describe()
+            xh = torch.from_numpy(x).to("cuda").to(torch.complex32)
+            y = torch.view_as_real(p.execute(xh)).float().cpu().numpy().astype(np.float64)
+            xr = torch.view_as_real(xh).float().cpu().numpy().astype(np.float64)
+        assert (d["kernel_name"], d["kernel_name2"]) == (k1["name"], k2["name"])
+        ref = oracle.fft(xr[..., 0] + 1j * xr[..., 1], fb.FORWARD)
+        err = metrics.rel_l2_per_transform(y[..., 0] + 1j * y[..., 1], ref)
+        assert np.all(err <= 2.0 ** -11 + metrics.tolerance(n))
+        return
     y, d = run(n, batch, fb.FORWARD, opts, x)
     assert (d["kernel_name"], d["kernel_name2"]) == (k1["name"], k2["name"])
     ref = oracle.fft(x.astype(np.complex128), fb.FORWARD)
