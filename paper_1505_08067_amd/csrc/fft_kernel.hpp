@@ -32,7 +32,24 @@
 
 namespace fb {
 
-enum : int { kSwz = 8, kStaged = 16, kTwPow = 32, kXcd = 128, kStageStride = 256 };
+enum : int { kSwz = 8, kStaged = 16, kTwPow = 32, kXcd = 128, kStageStride = 256, kWaveSync = 512 };
+
+// Synchronisation of an LDS exchange.  When every thread that exchanges
+// through a buffer belongs to one wavefront (a whole transform per wave), its
+// LDS operations are performed in issue order, so a compiler-level barrier
+// is enough and the workgroup barrier is skipped: the wavefronts of a
+// workgroup then run their stages independently.
+template <bool WS>
+__device__ __forceinline__ void exch_sync()
+{
+    if constexpr (WS) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
 
 // Workgroup b of a grid of G is dispatched to XCD b mod 8.  The XCD-ordered
 // variants give each XCD a contiguous range of work units, so neighbouring
@@ -318,7 +335,7 @@ __device__ __forceinline__ void apply_lds_tw(float2* v, const float2* Ltw, int k
     }
 }
 
-template <int N, int E, class S, int FL>
+template <int N, int E, class S, int FL, bool WS = false>
 __device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const float2* __restrict__ tw,
                                            const float2* Ltw, int t)
 {
@@ -347,7 +364,7 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const floa
 #pragma unroll
         for (int i = 0; i < E / R; ++i) Dft<R>::run(&v[i * R]);
         if constexpr (s < NST - 1) {
-            if constexpr (s > 0) __syncthreads();
+            if constexpr (s > 0) exch_sync<WS>();
 #pragma unroll
             for (int i = 0; i < E / R; ++i) {
                 const int j = t + i * T;
@@ -355,7 +372,7 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const floa
 #pragma unroll
                 for (int q = 0; q < R; ++q) L[lds_at<FL>(base + q * Ns)] = v[i * R + q];
             }
-            __syncthreads();
+            exch_sync<WS>();
         }
     });
 }
@@ -400,6 +417,8 @@ k_fft(KArgs a)
     constexpr int NsL = S::ns(NST - 1);
     static_assert(S::n() == N, "schedule does not multiply to N");
     constexpr int TWB = k_tw_base<N, C, S, FL, P::f_fast, T>();
+    // wave-synchronous exchanges: t-fast lanes, whole transforms per wavefront
+    constexpr bool WS = (FL & kWaveSync) != 0 && !P::f_fast && T <= 64 && 64 % T == 0 && (FL & kPipe) == 0;
     __shared__ __attribute__((aligned(16))) float2 lds[k_lds_elems<N, C, S, FL, P::f_fast, T>()];
 
     const int tid = threadIdx.x;
@@ -431,7 +450,7 @@ k_fft(KArgs a)
         }
     };
     auto finish = [&](float2(&v)[E], long long unit) {
-        run_stages<N, E, S, FL>(v, L, a.tw, Ltw, t);
+        run_stages<N, E, S, FL, WS>(v, L, a.tw, Ltw, t);
         if constexpr (P::kind == kKindFilter) {
             // Z = X conj(H) is transformed back as conj(F(conj Z)), and
             // conj Z = conj(X) H: X[k] sits at v[i RL + q], k = t + i T + q NsL.
@@ -444,23 +463,23 @@ k_fft(KArgs a)
                     v[i * RL + q] = cmul(make_float2(x.x, -x.y), h);
                 }
             if constexpr (NST > 1) {
-                __syncthreads();  // every read of the last stage precedes the next writes
+                exch_sync<WS>();  // every read of the last stage precedes the next writes
                 if constexpr (R0 != RL) {
                     // natural order through LDS, then the stage-0 gather
 #pragma unroll
                     for (int i = 0; i < E / RL; ++i)
 #pragma unroll
                         for (int q = 0; q < RL; ++q) L[lds_at<FL>(t + i * T + q * NsL)] = v[i * RL + q];
-                    __syncthreads();
+                    exch_sync<WS>();
 #pragma unroll
                     for (int i = 0; i < E / R0; ++i)
 #pragma unroll
                         for (int r = 0; r < R0; ++r) v[i * R0 + r] = L[lds_at<FL>(t + i * T + r * (N / R0))];
-                    __syncthreads();
+                    exch_sync<WS>();
                 }
                 // with R0 == RL the outputs already sit where stage 0 wants its inputs
             }
-            run_stages<N, E, S, FL>(v, L, a.tw, Ltw, t);
+            run_stages<N, E, S, FL, WS>(v, L, a.tw, Ltw, t);
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
         }

@@ -19,6 +19,13 @@ namespace fb {
                                                                  "],v" #FL ">")
 
 static const KEntry kBlock[] = {
+    // wave-synchronous exchanges (whole transforms per wavefront, no barriers)
+    FB_BLK(false, 547, 32, 16, 128, 16, 2),
+    FB_BLK(false, 547, 64, 16, 64, 16, 4),
+    FB_BLK(false, 547, 128, 16, 32, 16, 8),
+    FB_BLK(false, 547, 256, 16, 16, 16, 16),
+    FB_BLK(false, 547, 512, 16, 8, 16, 16, 2),
+    FB_BLK(false, 547, 1024, 16, 4, 16, 16, 4),
     // eight values per thread: twice the waves per workgroup at the same LDS
     FB_BLK(false, 35, 4096, 8, 1, 8, 8, 8, 8),
     FB_BLK(false, 35, 8192, 8, 1, 8, 8, 8, 8, 2),

@@ -22,6 +22,8 @@ static const KEntry kFilter[] = {
     // first radix equal to the last: no LDS round trip between the transforms
     // (measured faster at 1024, 2048, 8192 and 16384)
     FB_FLT(true, 35, 1024, 16, 4, 16, 4, 16),
+    FB_FLT(false, 547, 1024, 16, 4, 16, 4, 16),
+    FB_FLT(false, 547, 512, 16, 8, 16, 16, 2),
     FB_FLT(false, 35, 8192, 16, 1, 16, 8, 4, 16),
     FB_FLT(true, 35, 8192, 16, 1, 16, 2, 16, 16),
     FB_FLT(false, 43, 8192, 16, 1, 16, 2, 16, 16),
