@@ -272,6 +272,7 @@ EXTRAS = ("copy", "sar", "fp16", "ragged", "serving")
 def run_extras(torch, fb, inputs, stream, which=EXTRAS):
     out = {}
     todo = [("copy_probe", "copy", lambda: run_copy(torch, fb, stream)),
+            ("fourstep_1024x1024", "copy", lambda: run_split(torch, fb, inputs, stream)),
             ("sar", "sar", lambda: run_sar(torch, fb, inputs, stream)),
             ("fp16_storage", "fp16", lambda: run_fp16(torch, fb, inputs, stream)),
             ("ragged", "ragged", lambda: run_ragged(torch, fb, inputs, stream)),
@@ -291,6 +292,37 @@ def run_extras(torch, fb, inputs, stream, which=EXTRAS):
         else:
             out[key] = res
     return out
+
+
+def run_split(torch, fb, inputs, stream):
+    """N = 2^20 x 16 forward + inverse at the balanced split 1024 x 1024 (the
+    planner's default is measured faster and is what the step uses)."""
+    n, batch = 1 << 20, 16
+    sets = [(torch.from_numpy(inputs.uniform(1, batch, n)).to("cuda"), None) for _ in range(1)]
+    x = sets[0][0]
+    xs = [x.clone() for _ in range(4)]
+    ys = [torch.empty_like(x) for _ in range(4)]
+    sh = stream.cuda_stream
+    res = {}
+    for name, n1 in (("balanced", 1024), ("planner", 0)):
+        with fb.Plan(n, batch, fb.FORWARD, fb.make_opts(n1=n1)) as pf, \
+                fb.Plan(n, batch, fb.BACKWARD, fb.make_opts(n1=n1)) as pb:
+            d = pf.describe()
+            k = [0]
+
+            def step():
+                i = k[0] % 4
+                k[0] += 1
+                pf.execute_ptr(xs[i].data_ptr(), ys[i].data_ptr(), sh)
+                pb.execute_ptr(xs[i].data_ptr(), ys[i].data_ptr(), sh)
+            t = _timed(torch, stream, step, reps=20)
+        res[name] = {"split": f"{d['n1']}x{d['n2']}", "kernels": [d["kernel_name"], d["kernel_name2"]],
+                     "us_fwd_plus_inv": round(t * 1e6, 1),
+                     "GFLOPs": round(2 * 5.0 * n * 20 * batch / t / 1e9, 1),
+                     "frac_hbm_peak": round(2 * 32.0 * n * batch / t / 1e9 / HBM_PEAK_GBPS, 4)}
+    del xs, ys, x
+    log("four-step splits", json.dumps(res))
+    return res
 
 
 def run_copy(torch, fb, stream):

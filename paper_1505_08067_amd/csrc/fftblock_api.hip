@@ -414,10 +414,12 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
         // columns over many rows.  Measured on 2^15..2^22 it is the fastest
         // split everywhere (e.g. 2^21: 1024 x 2048 121 us vs 2048 x 1024
         // 144 us).  Short forced four-step lengths keep the balanced split.
+        // FP16 storage halves the output runs of pass 2 (CW rows x 4 bytes), so
+        // its rows stop at 1024 where 16-row tiles still fit the LDS
         size_t n1 = size_t(1) << ((L + 1) / 2);
-        const size_t rows_max = std::min<size_t>(2048, limit);
+        const size_t rows_max = std::min<size_t>(o.storage ? 1024 : 2048, limit);
         const size_t cand = std::max<size_t>(256, n / rows_max);
-        if (cand <= limit && n / cand >= 32 && n / cand <= rows_max) n1 = cand;
+        if (cand <= std::min<size_t>(2048, limit) && n / cand >= 32 && n / cand <= rows_max) n1 = cand;
         p->n1 = o.n1 ? o.n1 : n1;
         p->n2 = n / p->n1;
         const int c1 = o.c > 0 ? o.c : (int)env_size("FFTBLOCK_FOURSTEP_C", 0);

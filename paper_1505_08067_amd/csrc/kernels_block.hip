@@ -27,78 +27,89 @@ static const KEntry kBlock[] = {
     FB_BLK(false, 547, 512, 16, 8, 16, 16, 2),
     FB_BLK(false, 547, 1024, 16, 4, 16, 16, 4),
     // eight values per thread: twice the waves per workgroup at the same LDS
-    FB_BLK(false, 35, 4096, 8, 1, 8, 8, 8, 8),
     FB_BLK(false, 35, 8192, 8, 1, 8, 8, 8, 8, 2),
     FB_BLK(false, 35, 2048, 8, 2, 8, 8, 4, 8),
-    // FP16 storage, FP32 arithmetic (64 + 35)
-    FB_BLKH(true, 99, 2, 2, 256, 2),
-    FB_BLKH(true, 99, 4, 4, 256, 4),
-    FB_BLKH(true, 99, 8, 8, 256, 8),
-    FB_BLKH(true, 99, 16, 16, 256, 16),
-    FB_BLKH(true, 99, 32, 16, 128, 16, 2),
-    FB_BLKH(true, 99, 64, 16, 64, 16, 4),
-    FB_BLKH(true, 99, 128, 16, 32, 16, 8),
+    // FP16 storage, FP32 arithmetic (64 + 35; plain 64 where streaming hints
+    // hurt: few threads per transform, so one load instruction spans many lines)
+    FB_BLKH(true, 64, 2, 2, 256, 2),
+    FB_BLKH(true, 64, 4, 4, 256, 4),
+    FB_BLKH(true, 64, 8, 8, 256, 8),
+    FB_BLKH(true, 64, 16, 16, 256, 16),
+    FB_BLKH(true, 64, 32, 16, 128, 16, 2),
+    FB_BLKH(true, 64, 64, 16, 64, 16, 4),
+    FB_BLKH(true, 64, 128, 16, 32, 16, 8),
     FB_BLKH(true, 99, 256, 16, 16, 16, 16),
-    FB_BLKH(true, 99, 512, 16, 8, 16, 16, 2),
-    FB_BLKH(true, 99, 1024, 8, 2, 8, 8, 4, 4),
+    FB_BLKH(true, 99, 512, 8, 4, 8, 8, 8),
+    FB_BLKH(true, 99, 1024, 16, 4, 16, 16, 4),
     FB_BLKH(true, 99, 2048, 16, 2, 16, 16, 8),
     FB_BLKH(true, 99, 4096, 16, 1, 16, 16, 16),
     FB_BLKH(true, 99, 8192, 16, 1, 8, 8, 8, 16),
     FB_BLKH(true, 99, 16384, 16, 1, 16, 16, 16, 4),
-    FB_BLKH(true, 99, 3, 3, 64, 3),
-    FB_BLKH(true, 99, 5, 5, 64, 5),
-    FB_BLKH(true, 99, 6, 6, 64, 6),
-    FB_BLKH(true, 99, 10, 10, 64, 10),
-    FB_BLKH(true, 99, 12, 12, 64, 12),
-    FB_BLKH(true, 99, 15, 15, 64, 15),
-    FB_BLKH(true, 99, 20, 20, 64, 20),
-    FB_BLKH(true, 99, 60, 30, 32, 6, 10),
-    FB_BLKH(true, 99, 100, 10, 8, 10, 10),
-    FB_BLKH(true, 99, 1000, 10, 2, 10, 10, 10),
+    FB_BLKH(true, 64, 3, 3, 64, 3),
+    FB_BLKH(true, 64, 5, 5, 64, 5),
+    FB_BLKH(true, 64, 6, 6, 64, 6),
+    FB_BLKH(true, 64, 10, 10, 64, 10),
+    FB_BLKH(true, 64, 12, 12, 64, 12),
+    FB_BLKH(true, 64, 15, 15, 64, 15),
+    FB_BLKH(true, 64, 20, 20, 64, 20),
+    FB_BLKH(true, 64, 60, 30, 32, 6, 10),
+    FB_BLKH(true, 64, 100, 10, 8, 10, 10),
+    FB_BLKH(true, 64, 1000, 10, 2, 10, 10, 10),
     FB_BLKH(true, 99, 3072, 24, 2, 6, 8, 8, 8),
     FB_BLKH(true, 99, 6000, 30, 1, 10, 10, 10, 6),
     FB_BLKH(true, 99, 15360, 60, 1, 12, 20, 4, 4, 4),
     // planner defaults: non-temporal data access + power-row twiddles (35)
-    FB_BLK(true, 3, 2, 2, 256, 2),
-    FB_BLK(true, 3, 4, 4, 256, 4),
-    FB_BLK(true, 3, 8, 8, 256, 8),
-    FB_BLK(true, 3, 16, 16, 256, 16),
-    FB_BLK(true, 35, 32, 16, 128, 16, 2),
-    FB_BLK(true, 35, 64, 16, 64, 16, 4),
-    FB_BLK(true, 35, 128, 16, 32, 16, 8),
+    FB_BLK(true, 0, 2, 2, 256, 2),
+    FB_BLK(false, 3, 2, 2, 256, 2),
+    FB_BLK(true, 0, 4, 4, 256, 4),
+    FB_BLK(false, 3, 4, 4, 256, 4),
+    FB_BLK(true, 0, 8, 8, 256, 8),
+    FB_BLK(false, 3, 8, 8, 256, 8),
+    FB_BLK(true, 0, 16, 16, 256, 16),
+    FB_BLK(false, 3, 16, 16, 256, 16),
+    FB_BLK(true, 0, 32, 16, 128, 16, 2),
+    FB_BLK(false, 35, 32, 16, 128, 16, 2),
+    FB_BLK(true, 0, 64, 16, 64, 16, 4),
+    FB_BLK(false, 35, 64, 16, 64, 16, 4),
+    FB_BLK(true, 0, 128, 16, 32, 16, 8),
+    FB_BLK(false, 35, 128, 16, 32, 16, 8),
     FB_BLK(true, 35, 256, 16, 16, 16, 16),
-    FB_BLK(true, 35, 512, 16, 8, 16, 16, 2),
-    FB_BLK(true, 35, 1024, 8, 2, 8, 8, 4, 4),
+    FB_BLK(true, 35, 512, 8, 4, 8, 8, 8),
+    FB_BLK(false, 35, 512, 16, 8, 16, 16, 2),
+    FB_BLK(true, 35, 1024, 16, 4, 16, 16, 4),
+    FB_BLK(false, 35, 1024, 8, 2, 8, 8, 4, 4),
     FB_BLK(true, 35, 2048, 16, 2, 16, 16, 8),
     FB_BLK(true, 35, 4096, 16, 1, 16, 16, 16),
     FB_BLK(true, 35, 8192, 16, 1, 8, 8, 8, 16),
     FB_BLK(true, 35, 16384, 16, 1, 16, 16, 16, 4),
     // mixed-radix lengths (radix 3 and 5 butterflies and their products)
-    FB_BLK(true, 35, 3, 3, 64, 3),
-    FB_BLK(true, 35, 5, 5, 64, 5),
-    FB_BLK(true, 35, 6, 6, 64, 6),
-    FB_BLK(true, 35, 10, 10, 64, 10),
-    FB_BLK(true, 35, 12, 12, 64, 12),
-    FB_BLK(true, 35, 15, 15, 64, 15),
-    FB_BLK(true, 35, 20, 20, 64, 20),
-    FB_BLK(true, 35, 60, 30, 32, 6, 10),
-    FB_BLK(true, 35, 100, 10, 8, 10, 10),
-    FB_BLK(true, 35, 1000, 10, 2, 10, 10, 10),
+    FB_BLK(true, 0, 3, 3, 64, 3),
+    FB_BLK(false, 35, 3, 3, 64, 3),
+    FB_BLK(true, 0, 5, 5, 64, 5),
+    FB_BLK(false, 35, 5, 5, 64, 5),
+    FB_BLK(true, 0, 6, 6, 64, 6),
+    FB_BLK(false, 35, 6, 6, 64, 6),
+    FB_BLK(true, 0, 10, 10, 64, 10),
+    FB_BLK(false, 35, 10, 10, 64, 10),
+    FB_BLK(true, 0, 12, 12, 64, 12),
+    FB_BLK(false, 35, 12, 12, 64, 12),
+    FB_BLK(true, 0, 15, 15, 64, 15),
+    FB_BLK(false, 35, 15, 15, 64, 15),
+    FB_BLK(true, 0, 20, 20, 64, 20),
+    FB_BLK(false, 35, 20, 20, 64, 20),
+    FB_BLK(true, 0, 60, 30, 32, 6, 10),
+    FB_BLK(false, 35, 60, 30, 32, 6, 10),
+    FB_BLK(true, 0, 100, 10, 8, 10, 10),
+    FB_BLK(false, 35, 100, 10, 8, 10, 10),
+    FB_BLK(true, 0, 1000, 10, 2, 10, 10, 10),
+    FB_BLK(false, 35, 1000, 10, 2, 10, 10, 10),
     FB_BLK(true, 35, 3072, 24, 2, 6, 8, 8, 8),
     FB_BLK(true, 35, 6000, 30, 1, 10, 10, 10, 6),
     FB_BLK(true, 35, 15360, 60, 1, 12, 20, 4, 4, 4),
-    FB_BLK(false, 0, 15, 15, 64, 15),
-    FB_BLK(false, 0, 60, 30, 32, 6, 10),
-    FB_BLK(false, 0, 1000, 10, 2, 10, 10, 10),
     FB_BLK(false, 3, 3072, 24, 2, 6, 8, 8, 8),
     FB_BLK(false, 0, 6000, 30, 1, 10, 10, 10, 6),
     FB_BLK(false, 3, 15360, 60, 1, 12, 20, 4, 4, 4),
     // plain variants (full twiddle rows, ordinary loads/stores)
-    FB_BLK(false, 0, 2, 2, 256, 2),
-    FB_BLK(false, 0, 16, 16, 256, 16),
-    FB_BLK(false, 0, 32, 16, 128, 16, 2),
-    FB_BLK(false, 0, 64, 16, 64, 16, 4),
-    FB_BLK(false, 0, 128, 16, 32, 16, 8),
     FB_BLK(false, 0, 256, 16, 16, 16, 16),
     FB_BLK(false, 0, 512, 16, 8, 16, 16, 2),
     FB_BLK(false, 0, 1024, 16, 4, 16, 16, 4),
@@ -109,7 +120,6 @@ static const KEntry kBlock[] = {
     // other variants of the main sizes: non-temporal (1|2), persistent with
     // LDS twiddles (4), swizzled LDS (8), power-row twiddles (32)
     FB_BLK(false, 3, 1024, 16, 4, 16, 16, 4),
-    FB_BLK(false, 35, 1024, 16, 4, 16, 16, 4),
     FB_BLK(false, 0, 1024, 8, 2, 8, 8, 4, 4),
     FB_BLK(false, 3, 1024, 8, 2, 8, 8, 4, 4),
     FB_BLK(false, 32, 1024, 8, 2, 8, 8, 4, 4),
@@ -130,7 +140,6 @@ static const KEntry kBlock[] = {
     FB_BLK(false, 7, 16384, 16, 1, 16, 16, 16, 4),
     // alternative schedules (radix search)
     FB_BLK(false, 0, 512, 8, 4, 8, 8, 8),
-    FB_BLK(false, 35, 512, 8, 4, 8, 8, 8),
     FB_BLK(false, 0, 1024, 16, 4, 4, 16, 16),
     FB_BLK(false, 0, 1024, 8, 2, 4, 8, 8, 4),
     FB_BLK(false, 35, 1024, 8, 2, 4, 8, 8, 4),

@@ -10,10 +10,11 @@ namespace fb {
                                                                "],v" #FL ">")
 
 static const KEntry kFilter[] = {
-    FB_FLT(true, 35, 64, 16, 64, 16, 4),
-    FB_FLT(true, 35, 128, 16, 32, 16, 8),
+    FB_FLT(true, 0, 64, 16, 64, 16, 4),
+    FB_FLT(true, 0, 128, 16, 32, 16, 8),
     FB_FLT(true, 35, 256, 16, 16, 16, 16),
-    FB_FLT(true, 35, 512, 16, 8, 16, 16, 2),
+    FB_FLT(true, 35, 512, 8, 4, 8, 8, 8),
+    FB_FLT(false, 35, 512, 16, 8, 16, 16, 2),
     FB_FLT(false, 35, 1024, 8, 2, 8, 8, 4, 4),
     FB_FLT(false, 35, 2048, 16, 2, 16, 16, 8),
     FB_FLT(true, 35, 4096, 16, 1, 16, 16, 16),

@@ -38,7 +38,6 @@ static const KEntry kPass[] = {
     FB_P1(false, 305, 2048, 16, 8, 16, 16, 8),
     // 32 values per thread: one LDS exchange instead of two
     FB_P1(false, 49, 512, 32, 16, 32, 16),
-    FB_P1(false, 49, 512, 32, 16, 16, 32),
     FB_P1(false, 177, 512, 16, 8, 16, 16, 2),
     FB_P1(false, 177, 1024, 16, 8, 16, 16, 4),
     FB_P2(false, 161, 2048, 16, 4, 16, 16, 8),
@@ -53,20 +52,20 @@ static const KEntry kPass[] = {
     FB_P1H(true, 113, 32, 16, 16, 16, 2),
     FB_P1H(true, 113, 64, 16, 16, 16, 4),
     FB_P1H(true, 113, 128, 16, 16, 16, 8),
-    FB_P1H(true, 113, 256, 16, 16, 16, 16),
-    FB_P1H(true, 113, 512, 16, 16, 16, 16, 2),
+    FB_P1H(false, 113, 256, 16, 16, 16, 16),
+    FB_P1H(false, 113, 512, 16, 16, 16, 16, 2),
     FB_P1H(true, 113, 1024, 16, 16, 16, 16, 4),
     FB_P1H(true, 113, 2048, 16, 8, 16, 16, 8),
     // 32 FP16 columns = 128-byte runs; 16 FP16 rows = 64-byte output runs
-    FB_P1H(false, 113, 256, 16, 32, 16, 16),
-    FB_P1H(false, 113, 512, 16, 32, 16, 16, 2),
-    FB_P2H(false, 98, 1024, 16, 16, 16, 16, 4),
+    FB_P1H(true, 113, 256, 16, 32, 16, 16),
+    FB_P1H(true, 113, 512, 16, 32, 16, 16, 2),
+    FB_P2H(true, 98, 1024, 16, 16, 16, 16, 4),
     FB_P2H(true, 98, 32, 16, 16, 16, 2),
     FB_P2H(true, 98, 64, 16, 16, 16, 4),
     FB_P2H(true, 98, 128, 16, 16, 16, 8),
     FB_P2H(true, 98, 256, 16, 16, 16, 16),
     FB_P2H(true, 98, 512, 16, 16, 16, 16, 2),
-    FB_P2H(true, 98, 1024, 16, 8, 16, 16, 4),
+    FB_P2H(false, 98, 1024, 16, 8, 16, 16, 4),
     FB_P2H(true, 98, 2048, 16, 8, 16, 16, 8),
     // planner defaults.  Pass 1: non-temporal loads, power-row twiddles
     // (stage and long), outputs staged through LDS for contiguous stores
@@ -75,7 +74,8 @@ static const KEntry kPass[] = {
     FB_P1(true, 49, 64, 16, 16, 16, 4),
     FB_P1(true, 49, 128, 16, 16, 16, 8),
     FB_P1(true, 49, 256, 16, 16, 16, 16),
-    FB_P1(true, 49, 512, 16, 16, 16, 16, 2),
+    FB_P1(true, 49, 512, 32, 16, 16, 32),
+    FB_P1(false, 49, 512, 16, 16, 16, 16, 2),
     FB_P1(true, 49, 1024, 16, 16, 16, 16, 4),
     FB_P1(true, 49, 2048, 16, 8, 16, 16, 8),
     // pass 2: cached loads of the workspace pass 1 has just written (partly

@@ -9,30 +9,30 @@ namespace fb {
     make_entry<N, E, C, Sched<__VA_ARGS__>, PolList, FL>(true, "block_fft_list<" #N ",[" #__VA_ARGS__ "],v" #FL ">")
 
 static const KEntry kList[] = {
-    FB_LST(3, 2, 2, 256, 2),
-    FB_LST(3, 4, 4, 256, 4),
-    FB_LST(3, 8, 8, 256, 8),
-    FB_LST(3, 16, 16, 256, 16),
-    FB_LST(35, 32, 16, 128, 16, 2),
-    FB_LST(35, 64, 16, 64, 16, 4),
-    FB_LST(35, 128, 16, 32, 16, 8),
+    FB_LST(0, 2, 2, 256, 2),
+    FB_LST(0, 4, 4, 256, 4),
+    FB_LST(0, 8, 8, 256, 8),
+    FB_LST(0, 16, 16, 256, 16),
+    FB_LST(0, 32, 16, 128, 16, 2),
+    FB_LST(0, 64, 16, 64, 16, 4),
+    FB_LST(0, 128, 16, 32, 16, 8),
     FB_LST(35, 256, 16, 16, 16, 16),
-    FB_LST(35, 512, 16, 8, 16, 16, 2),
-    FB_LST(35, 1024, 8, 2, 8, 8, 4, 4),
+    FB_LST(35, 512, 8, 4, 8, 8, 8),
+    FB_LST(35, 1024, 16, 4, 16, 16, 4),
     FB_LST(35, 2048, 16, 2, 16, 16, 8),
     FB_LST(35, 4096, 16, 1, 16, 16, 16),
     FB_LST(35, 8192, 16, 1, 8, 8, 8, 16),
     FB_LST(35, 16384, 16, 1, 16, 16, 16, 4),
-    FB_LST(35, 3, 3, 64, 3),
-    FB_LST(35, 5, 5, 64, 5),
-    FB_LST(35, 6, 6, 64, 6),
-    FB_LST(35, 10, 10, 64, 10),
-    FB_LST(35, 12, 12, 64, 12),
-    FB_LST(35, 15, 15, 64, 15),
-    FB_LST(35, 20, 20, 64, 20),
-    FB_LST(35, 60, 30, 32, 6, 10),
-    FB_LST(35, 100, 10, 8, 10, 10),
-    FB_LST(35, 1000, 10, 2, 10, 10, 10),
+    FB_LST(0, 3, 3, 64, 3),
+    FB_LST(0, 5, 5, 64, 5),
+    FB_LST(0, 6, 6, 64, 6),
+    FB_LST(0, 10, 10, 64, 10),
+    FB_LST(0, 12, 12, 64, 12),
+    FB_LST(0, 15, 15, 64, 15),
+    FB_LST(0, 20, 20, 64, 20),
+    FB_LST(0, 60, 30, 32, 6, 10),
+    FB_LST(0, 100, 10, 8, 10, 10),
+    FB_LST(0, 1000, 10, 2, 10, 10, 10),
     FB_LST(35, 3072, 24, 2, 6, 8, 8, 8),
     FB_LST(35, 6000, 30, 1, 10, 10, 10, 6),
     FB_LST(35, 15360, 60, 1, 12, 20, 4, 4, 4),
