@@ -144,7 +144,7 @@ def test_server_edge_lengths():
             y, info = srv.result(tk)
             x = data[i].cpu().numpy().astype(np.complex128)
             if n == 1:
-                assert np.array_equal(y.cpu().numpy().reshape(-1), data[i].cpu().numpy())
+                assert np.array_equal(y.cpu().numpy().reshape(-1), data[i].cpu().numpy().reshape(-1))
             else:
                 metrics.check(y.cpu().numpy(), oracle.fft(x, d), n)
             srv.release(tk)
