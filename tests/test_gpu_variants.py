@@ -113,8 +113,10 @@ def test_fourstep_variant_pairs(n1, k1, k2):
     n2 = k2["n"]
     n, batch = n1 * n2, 2
     half = bool(k1["flags"] & fb.VARIANT_FP16_STORAGE)
+    # lengths a single block would take are forced onto the four-step path
+    limit = 0 if n > fb.block_limit() else max(1024, n // 2)
     opts = fb.make_opts(radix=k1["radix"], flags=k1["flags"], c=k1["c"], flags2=k2["flags"], c2=k2["c"], n1=n1,
-                        storage=fb.STORAGE_F16 if half else fb.STORAGE_C64)
+                        storage=fb.STORAGE_F16 if half else fb.STORAGE_C64, block_limit=limit)
     say(f"case: four-step {n1} x {n2} {k1['name']} + {k2['name']}")
     x = inputs.uniform(400 + n1, batch, n)
     if half:
