@@ -9,11 +9,12 @@ Inputs are seeded uniform[-1,1] complex64, resident in HBM before timing;
 the step rotates over several (in, out) buffer sets so the footprint exceeds
 the 256 MB Infinity Cache (cold-cache timing).
 
-Metric: GFLOP/s counted as 5 N log2 N per transform.  Per-kernel durations
-are taken live with events between launches on the launch stream; the
-dominant kernel's algorithmic HBM bytes (16 N per transform and pass: the
-data read once and written once) over its average duration give the
-roofline fraction against 8 TB/s.  The FP64 oracle is timed on the host
+Metric: GFLOP/s counted as 5 N log2 N per transform, over the event-timed
+steps.  Per-kernel durations come from events the device stamps at each
+dispatch's own start and end on the launch stream (what a kernel trace
+reports); the dominant kernel's algorithmic HBM bytes (16 N per transform and
+pass: the data read once and written once) over its average duration give
+the roofline fraction against 8 TB/s.  The FP64 oracle is timed on the host
 cores on the same step (CPU baseline).  Prints ONE JSON line on stdout.
 """
 from __future__ import annotations
@@ -158,11 +159,11 @@ def main():
         k = s % args.rotate
         for li, (_, name, pass_, key) in enumerate(launches):
             xin, xout = bufs[key][k]
-            if evs is not None:
-                evs[li].record(stream)
-            plans[name].execute_pass_ptr(pass_, xin.data_ptr(), xout.data_ptr(), sh)
-        if evs is not None:
-            evs[len(launches)].record(stream)
+            if evs is None:
+                plans[name].execute_pass_ptr(pass_, xin.data_ptr(), xout.data_ptr(), sh)
+            else:
+                # the device stamps the pair at this dispatch's own start and end
+                plans[name].execute_pass_timed_ptr(pass_, xin.data_ptr(), xout.data_ptr(), sh, *evs[li])
 
     for s in range(args.warmup):
         run_step(s)
@@ -170,22 +171,29 @@ def main():
     log(f"warmup {args.warmup} steps done")
 
     K = args.steps
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(launches) + 1)] for _ in range(K)]
+    evs = [[(fb.Event(), fb.Event()) for _ in range(len(launches))] for _ in range(K)]
+    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    t_start.record(stream)
     for s in range(K):
         run_step(s, evs[s])
+    t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log(f"timed {K} steps in {wall:.3f} s wall")
 
-    total_ms = evs[0][0].elapsed_time(evs[K - 1][len(launches)])
+    total_ms = t_start.elapsed_time(t_end)
     ms_per_step = total_ms / K
     per = {}
     for s in range(K):
         for li, (kname, name, pass_, key) in enumerate(launches):
-            dt = evs[s][li].elapsed_time(evs[s][li + 1])
-            per.setdefault(li, []).append(dt)
+            e0, e1 = evs[s][li]
+            per.setdefault(li, []).append(e0.elapsed_ms(e1))
+    for row in evs:
+        for e0, e1 in row:
+            e0.close()
+            e1.close()
     fl_step = sum(flops(n, b) for _, n, b, _ in items)
     value = fl_step / (ms_per_step * 1e-3) / 1e9
 

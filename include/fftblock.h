@@ -112,6 +112,22 @@ fft_status_t fft_execute(fft_plan_t plan, const void* in, void* out, void* strea
 fft_status_t fft_execute_pass(fft_plan_t plan, int pass, const void* in, void* out, void* stream);
 
 /*
+ * fft_execute_pass_timed -- fft_execute_pass with two events (from
+ * fft_event_create) that the device stamps at the start and at the end of
+ * the kernel's dispatch itself, so their difference is the kernel's duration
+ * without the gaps between launches (what a kernel-trace profiler reports).
+ * Both events are required (INVALID_ARG otherwise).
+ */
+fft_status_t fft_execute_pass_timed(fft_plan_t plan, int pass, const void* in, void* out, void* stream,
+                                    void* start_event, void* stop_event);
+
+/* Timing events of the library's runtime: create, destroy, and the time in
+ * milliseconds between two recorded events (waits for stop_event). */
+fft_status_t fft_event_create(void** event);
+fft_status_t fft_event_destroy(void* event);
+fft_status_t fft_event_elapsed(void* start_event, void* stop_event, float* ms);
+
+/*
  * fft_transpose -- corner turn of `batch` row-major complex64 matrices:
  *     out[b][c][r] = in[b][r][c],  0 <= r < rows, 0 <= c < cols.
  * The values are copied bit for bit.  `in` and `out` must not overlap

@@ -27,6 +27,8 @@
 // layout (one transform per 16-aligned bank group).
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "fft_device.hpp"
 #include "internal.hpp"
 
@@ -553,10 +555,14 @@ k_fft(KArgs a)
 }
 
 template <int N, int E, int C, class S, class P, int FL>
-hipError_t launch_fft(const KArgs& a, long long grid, hipStream_t st)
+hipError_t launch_fft(const KArgs& a, long long grid, hipStream_t st, hipEvent_t start, hipEvent_t stop)
 {
     if (grid <= 0 || grid > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_fft<N, E, C, S, P, FL>), dim3((unsigned)grid), dim3((N / E) * C), 0, st, a);
+    if (start || stop)
+        hipExtLaunchKernelGGL((k_fft<N, E, C, S, P, FL>), dim3((unsigned)grid), dim3((N / E) * C), 0, st, start,
+                              stop, 0, a);
+    else
+        hipLaunchKernelGGL((k_fft<N, E, C, S, P, FL>), dim3((unsigned)grid), dim3((N / E) * C), 0, st, a);
     return hipGetLastError();
 }
 

@@ -778,7 +778,7 @@ fft_status_t fft_plan_describe(fft_plan_t plan, fft_plan_desc_t* d)
 // batch: transforms of this call (0 = the plan's); work: four-step workspace
 // (nullptr = the plan's own, which then bounds batch).
 static fft_status_t execute_impl(fft_plan_t plan, int passes, size_t batch, const void* in, void* out, void* work,
-                                 void* stream)
+                                 void* stream, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
     if (!plan_live(plan)) return FFT_ERR_INVALID_PLAN;
     if (in == nullptr || out == nullptr) return FFT_ERR_INVALID_ARG;
@@ -821,18 +821,18 @@ static fft_status_t execute_impl(fft_plan_t plan, int passes, size_t batch, cons
         } else {
             KArgs ka = make_args(plan, 1, x, y);
             ka.batch = (long long)batch;
-            e = plan->k1->launch(ka, grid(plan->k1, ka, plan->grid1), st);
+            e = plan->k1->launch(ka, grid(plan->k1, ka, plan->grid1), st, ev0, ev1);
         }
     } else {
         if (run1) {
             KArgs ka = make_args(plan, 1, x, ws);
             ka.batch = (long long)batch;
-            e = plan->k1->launch(ka, grid(plan->k1, ka, plan->grid1), st);
+            e = plan->k1->launch(ka, grid(plan->k1, ka, plan->grid1), st, ev0, ev1);
         }
         if (e == hipSuccess && run2) {
             KArgs ka = make_args(plan, 2, ws, y);
             ka.batch = (long long)batch;
-            e = plan->k2->launch(ka, grid(plan->k2, ka, plan->grid2), st);
+            e = plan->k2->launch(ka, grid(plan->k2, ka, plan->grid2), st, ev0, ev1);
         }
     }
     if (cur != plan->device) (void)hipSetDevice(cur);
@@ -842,6 +842,39 @@ static fft_status_t execute_impl(fft_plan_t plan, int passes, size_t batch, cons
 fft_status_t fft_execute(fft_plan_t plan, const void* in, void* out, void* stream)
 {
     return execute_impl(plan, 0, 0, in, out, nullptr, stream);
+}
+
+fft_status_t fft_execute_pass_timed(fft_plan_t plan, int pass, const void* in, void* out, void* stream,
+                                    void* start_event, void* stop_event)
+{
+    if (pass != 1 && pass != 2) return plan_live(plan) ? FFT_ERR_INVALID_ARG : FFT_ERR_INVALID_PLAN;
+    if (!start_event || !stop_event) return FFT_ERR_INVALID_ARG;
+    return execute_impl(plan, pass, 0, in, out, nullptr, stream, (hipEvent_t)start_event, (hipEvent_t)stop_event);
+}
+
+fft_status_t fft_event_create(void** event)
+{
+    if (!event) return FFT_ERR_INVALID_ARG;
+    *event = nullptr;
+    hipEvent_t e = nullptr;
+    const hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return from_hip(r);
+    *event = e;
+    return FFT_SUCCESS;
+}
+
+fft_status_t fft_event_destroy(void* event)
+{
+    if (!event) return FFT_ERR_INVALID_ARG;
+    return from_hip(hipEventDestroy((hipEvent_t)event));
+}
+
+fft_status_t fft_event_elapsed(void* start_event, void* stop_event, float* ms)
+{
+    if (!start_event || !stop_event || !ms) return FFT_ERR_INVALID_ARG;
+    hipError_t r = hipEventSynchronize((hipEvent_t)stop_event);
+    if (r == hipSuccess) r = hipEventElapsedTime(ms, (hipEvent_t)start_event, (hipEvent_t)stop_event);
+    return from_hip(r);
 }
 
 fft_status_t fft_execute_ex(fft_plan_t plan, size_t batch, const void* in, void* out, void* workspace, void* stream)
@@ -862,7 +895,7 @@ hipError_t plan_launch_list(fft_plan_s* plan, const void* list, long long transf
     int cur = 0;
     hipError_t e = hipGetDevice(&cur);
     if (e == hipSuccess && cur != plan->device) e = hipSetDevice(plan->device);
-    if (e == hipSuccess) e = plan->klist->launch(ka, kernel_units(*plan->klist, ka), st);
+    if (e == hipSuccess) e = plan->klist->launch(ka, kernel_units(*plan->klist, ka), st, nullptr, nullptr);
     if (cur != plan->device) (void)hipSetDevice(cur);
     return e;
 }

@@ -30,7 +30,9 @@ struct KArgs {
     float sg;              // +1 forward, -1 backward (conjugation on entry and exit)
 };
 
-using KLaunch = hipError_t (*)(const KArgs& a, long long grid, hipStream_t st);
+// start / stop: optional events the device stamps at the dispatch's own start
+// and end (nullptr: an ordinary launch).
+using KLaunch = hipError_t (*)(const KArgs& a, long long grid, hipStream_t st, hipEvent_t start, hipEvent_t stop);
 using KOccupancy = int (*)();   // resident workgroups per CU (hipOccupancy...), 0 on error
 
 enum : int { kKindBlock = 0, kKindPass1 = 1, kKindPass2 = 2, kKindFilter = 3, kKindList = 4 };

@@ -43,6 +43,7 @@ EXPORTS = (
     "fft_plan_twiddles", "fft_ragged_create_ex", "fft_filter_create", "fft_filter_query", "fft_execute_ex",
     "fft_sched_opts_init", "fft_sched_create", "fft_sched_destroy", "fft_sched_submit", "fft_sched_next",
     "fft_sched_complete", "fft_sched_request", "fft_sched_stats",
+    "fft_execute_pass_timed", "fft_event_create", "fft_event_destroy", "fft_event_elapsed",
     "fft_server_opts_init", "fft_server_create", "fft_server_prepare", "fft_server_submit", "fft_server_wait",
     "fft_server_read", "fft_server_release", "fft_server_drain", "fft_server_stats", "fft_server_clock", "fft_server_destroy",
 )
@@ -208,6 +209,10 @@ def load():
     lib.fft_plan_query_ex.argtypes = [sz, sz, i, ctypes.POINTER(PlanOpts), ctypes.POINTER(PlanDesc)]
     lib.fft_filter_create.argtypes = [sz, sz, vp, sz, ctypes.POINTER(PlanOpts), ctypes.POINTER(vp)]
     lib.fft_execute_ex.argtypes = [vp, sz, vp, vp, vp, vp]
+    lib.fft_execute_pass_timed.argtypes = [vp, i, vp, vp, vp, vp, vp]
+    lib.fft_event_create.argtypes = [ctypes.POINTER(vp)]
+    lib.fft_event_destroy.argtypes = [vp]
+    lib.fft_event_elapsed.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_float)]
     lib.fft_filter_query.argtypes = [sz, sz, sz, ctypes.POINTER(PlanOpts), ctypes.POINTER(PlanDesc)]
     lib.fft_kernel_count.argtypes = []
     lib.fft_kernel_count.restype = i
@@ -394,6 +399,13 @@ class Plan:
         _check(load().fft_execute(self._h, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
                                   ctypes.c_void_p(stream_handle)), "fft_execute")
 
+    def execute_pass_timed_ptr(self, pass_: int, in_ptr: int, out_ptr: int, stream_handle, start, stop) -> None:
+        """``fft_execute_pass_timed``: the device stamps ``start`` / ``stop`` (Event objects) at the
+        kernel's own start and end."""
+        _check(load().fft_execute_pass_timed(self._h, pass_, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
+                                             ctypes.c_void_p(stream_handle), start.handle, stop.handle),
+               f"fft_execute_pass_timed({pass_})")
+
     def execute_pass_ptr(self, pass_: int, in_ptr: int, out_ptr: int, stream_handle: int = 0) -> None:
         """Run one kernel of the plan (``fft_execute_pass``): 1 = block / four-step pass 1, 2 = pass 2."""
         _check(load().fft_execute_pass(self._h, pass_, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
@@ -420,6 +432,32 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Event:
+    """A timing event of the library's HIP runtime (``fft_event_*``)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(load().fft_event_create(ctypes.byref(h)), "fft_event_create")
+        self.handle = h
+
+    def elapsed_ms(self, stop: "Event") -> float:
+        """Milliseconds from this event to ``stop`` (waits for ``stop``)."""
+        ms = ctypes.c_float()
+        _check(load().fft_event_elapsed(self.handle, stop.handle, ctypes.byref(ms)), "fft_event_elapsed")
+        return ms.value
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load().fft_event_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
 
     def __del__(self):
         try:

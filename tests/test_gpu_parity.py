@@ -240,3 +240,30 @@ def test_sar_range_azimuth_chain_and_roundtrip():
         torch.cuda.synchronize()
         back = z.cpu().numpy().reshape(P, R) / (P * R)
         check(back[None], x.astype(np.complex128)[None], P * R, n_axes=2, factor=2.0, label="SAR round trip")
+
+
+def test_execute_pass_timed_matches_and_stamps():
+    # the dispatch-stamped launch computes the same result and gives a positive duration
+    for n, batch in ((4096, 64), (1 << 20, 2)):
+        say(f"case: timed passes n={n} batch={batch}")
+        x = to_dev(inputs.uniform(21, batch, n))
+        with fb.Plan(n, batch) as p:
+            d = p.describe()
+            y0 = torch.empty_like(x)
+            y1 = torch.empty_like(x)
+            sh = torch.cuda.current_stream().cuda_stream
+            passes = (1, 2) if d["path"] == fb.PATH_FOURSTEP else (1,)
+            for ps in passes:
+                p.execute_pass_ptr(ps, x.data_ptr(), y0.data_ptr(), sh)
+            torch.cuda.synchronize()
+            evs = []
+            for ps in passes:
+                e0, e1 = fb.Event(), fb.Event()
+                p.execute_pass_timed_ptr(ps, x.data_ptr(), y1.data_ptr(), sh, e0, e1)
+                evs.append((e0, e1))
+            torch.cuda.synchronize()
+            for e0, e1 in evs:
+                ms = e0.elapsed_ms(e1)
+                say(f"  {ms * 1e3:.1f} us")
+                assert 0.0 < ms < 1000.0
+            assert np.array_equal(y0.cpu().numpy().view(np.uint32), y1.cpu().numpy().view(np.uint32))
