@@ -10,9 +10,9 @@ the step rotates over several (in, out) buffer sets so the footprint exceeds
 the 256 MB Infinity Cache (cold-cache timing).
 
 Metric: GFLOP/s counted as 5 N log2 N per transform, over the event-timed
-steps.  Per-kernel durations come from events the device stamps at each
-dispatch's own start and end on the launch stream (what a kernel trace
-reports); the dominant kernel's algorithmic HBM bytes (16 N per transform and
+steps.  Per-kernel durations come from the same steps run again with events
+the device stamps at each dispatch's own start and end on the launch stream
+(what a kernel trace reports); the dominant kernel's algorithmic HBM bytes (16 N per transform and
 pass: the data read once and written once) over its average duration give
 the roofline fraction against 8 TB/s.  The FP64 oracle is timed on the host
 cores on the same step (CPU baseline).  Prints ONE JSON line on stdout.
@@ -170,21 +170,28 @@ def main():
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} steps done")
 
+    # timed region: K steps of ordinary launches between two events
     K = args.steps
-    evs = [[(fb.Event(), fb.Event()) for _ in range(len(launches))] for _ in range(K)]
     t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     t_start.record(stream)
     for s in range(K):
-        run_step(s, evs[s])
+        run_step(s)
     t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log(f"timed {K} steps in {wall:.3f} s wall")
-
     total_ms = t_start.elapsed_time(t_end)
     ms_per_step = total_ms / K
+
+    # the same K steps again with every dispatch stamped (start and end of the
+    # kernel itself), for the per-kernel durations
+    evs = [[(fb.Event(), fb.Event()) for _ in range(len(launches))] for _ in range(K)]
+    torch.cuda.synchronize()
+    for s in range(K):
+        run_step(s, evs[s])
+    torch.cuda.synchronize()
     per = {}
     for s in range(K):
         for li, (kname, name, pass_, key) in enumerate(launches):
