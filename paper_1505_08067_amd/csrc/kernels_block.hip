@@ -26,6 +26,10 @@ static const KEntry kBlock[] = {
     FB_BLK(false, 547, 256, 16, 16, 16, 16),
     FB_BLK(false, 547, 512, 16, 8, 16, 16, 2),
     FB_BLK(false, 547, 1024, 16, 4, 16, 16, 4),
+    // thirty-two values per thread: one exchange fewer
+    FB_BLK(false, 35, 8192, 32, 1, 16, 32, 16),
+    FB_BLK(false, 35, 8192, 32, 1, 32, 8, 32),
+    FB_BLK(false, 35, 16384, 32, 1, 32, 16, 32),
     // eight values per thread: twice the waves per workgroup at the same LDS
     FB_BLK(false, 35, 8192, 8, 1, 8, 8, 8, 8, 2),
     FB_BLK(false, 35, 2048, 8, 2, 8, 8, 4, 8),
@@ -43,8 +47,8 @@ static const KEntry kBlock[] = {
     FB_BLKH(true, 99, 1024, 16, 4, 16, 16, 4),
     FB_BLKH(true, 99, 2048, 16, 2, 16, 16, 8),
     FB_BLKH(true, 99, 4096, 16, 1, 16, 16, 16),
-    FB_BLKH(true, 99, 8192, 16, 1, 8, 8, 8, 16),
-    FB_BLKH(true, 99, 16384, 16, 1, 16, 16, 16, 4),
+    FB_BLKH(true, 107, 8192, 16, 1, 8, 8, 8, 16),
+    FB_BLKH(true, 99, 16384, 16, 1, 16, 4, 16, 16),
     FB_BLKH(true, 64, 3, 3, 64, 3),
     FB_BLKH(true, 64, 5, 5, 64, 5),
     FB_BLKH(true, 64, 6, 6, 64, 6),
@@ -80,8 +84,10 @@ static const KEntry kBlock[] = {
     FB_BLK(false, 35, 1024, 8, 2, 8, 8, 4, 4),
     FB_BLK(true, 35, 2048, 16, 2, 16, 16, 8),
     FB_BLK(true, 35, 4096, 16, 1, 16, 16, 16),
-    FB_BLK(true, 35, 8192, 16, 1, 8, 8, 8, 16),
-    FB_BLK(true, 35, 16384, 16, 1, 16, 16, 16, 4),
+    FB_BLK(true, 43, 8192, 16, 1, 8, 8, 8, 16),
+    FB_BLK(false, 35, 8192, 16, 1, 8, 8, 8, 16),
+    FB_BLK(true, 35, 16384, 16, 1, 16, 4, 16, 16),
+    FB_BLK(false, 35, 16384, 16, 1, 16, 16, 16, 4),
     // mixed-radix lengths (radix 3 and 5 butterflies and their products)
     FB_BLK(true, 0, 3, 3, 64, 3),
     FB_BLK(false, 35, 3, 3, 64, 3),
@@ -135,7 +141,6 @@ static const KEntry kBlock[] = {
     FB_BLK(false, 3, 8192, 32, 1, 32, 16, 16),
     FB_BLK(false, 35, 8192, 32, 1, 32, 16, 16),
     FB_BLK(false, 0, 8192, 16, 1, 8, 8, 8, 16),
-    FB_BLK(false, 43, 8192, 16, 1, 8, 8, 8, 16),
     FB_BLK(false, 3, 16384, 16, 1, 16, 16, 16, 4),
     FB_BLK(false, 7, 16384, 16, 1, 16, 16, 16, 4),
     // alternative schedules (radix search)

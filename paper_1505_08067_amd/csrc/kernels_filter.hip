@@ -25,9 +25,12 @@ static const KEntry kFilter[] = {
     FB_FLT(true, 35, 1024, 16, 4, 16, 4, 16),
     FB_FLT(false, 547, 1024, 16, 4, 16, 4, 16),
     FB_FLT(false, 547, 512, 16, 8, 16, 16, 2),
-    FB_FLT(false, 35, 8192, 16, 1, 16, 8, 4, 16),
-    FB_FLT(true, 35, 8192, 16, 1, 16, 2, 16, 16),
+    FB_FLT(true, 35, 8192, 16, 1, 16, 8, 4, 16),
+    FB_FLT(false, 35, 8192, 16, 1, 16, 2, 16, 16),
     FB_FLT(false, 43, 8192, 16, 1, 16, 2, 16, 16),
+    FB_FLT(false, 35, 8192, 32, 1, 16, 32, 16),
+    FB_FLT(false, 35, 8192, 32, 1, 32, 8, 32),
+    FB_FLT(false, 35, 16384, 32, 1, 32, 16, 32),
     FB_FLT(true, 35, 2048, 16, 2, 16, 8, 16),
     FB_FLT(true, 35, 16384, 16, 1, 16, 4, 16, 16),
     FB_FLT(false, 3, 8192, 16, 1, 8, 8, 8, 16),
