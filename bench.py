@@ -58,13 +58,15 @@ def parse():
 
 
 def kernel_source_hash() -> str:
-    """sha256 over the kernel sources and the C header (what the traffic figures depend on)."""
+    """sha256 over the device code of the transform kernels (the kernel
+    templates, their argument layout and the kernel catalogues): what the
+    measured traffic figures depend on."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1505_08067_amd", "csrc", "*.hip")) +
-                   glob.glob(os.path.join(ROOT, "paper_1505_08067_amd", "csrc", "*.hpp")) +
-                   [os.path.join(ROOT, "include", "fftblock.h")])
+    csrc = os.path.join(ROOT, "paper_1505_08067_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "kernels_*.hip")) +
+                   [os.path.join(csrc, f) for f in ("fft_device.hpp", "fft_kernel.hpp", "internal.hpp")])
     for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:
@@ -104,7 +106,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU layout (batch sharding and an "
+        print("bench.py: runs on one GPU only; the multi-GPU layout (batch sharding and an "
               "all-to-all corner turn) is a design note, not implemented. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 

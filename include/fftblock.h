@@ -298,8 +298,9 @@ fft_status_t fft_device_query(int device, fft_device_info_t* info);
  * k < 1 or nothing fits.  Pure arithmetic, no device needed. */
 size_t fft_block_max(size_t lds_bytes, int k);
 
-/* Largest length the single-block path handles in this build (the block
- * limit the planner uses: analytic, then confirmed by the runtime sweep). */
+/* Largest length the single-block path handles (the block limit the
+ * planner uses: analytic, then confirmed by the runtime sweep; the
+ * environment variable FFTBLOCK_BLOCK_MAX may lower it). */
 size_t fft_block_limit(void);
 
 /* ---------------------------------------------------------------------------
@@ -361,8 +362,8 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* report);
 /* Wisdom: the kernel (four-step: kernel pair) chosen per length.
  * fft_plan_create uses it when no explicit options are given.  The file
  * format is one "length<TAB>kernel[<TAB>pass-2 kernel]" line per entry
- * (a space may separate length and kernel); entries naming kernels this build
- * does not have are skipped
+ * (a space may separate length and kernel); entries naming kernels the
+ * library does not contain are skipped
  * (INVALID_ARG is returned after loading the rest).  The environment variable
  * FFTBLOCK_WISDOM names a file loaded before the first plan is created. */
 fft_status_t fft_wisdom_set(size_t n, int kernel_index);
