@@ -267,3 +267,21 @@ def test_execute_pass_timed_matches_and_stamps():
                 say(f"  {ms * 1e3:.1f} us")
                 assert 0.0 < ms < 1000.0
             assert np.array_equal(y0.cpu().numpy().view(np.uint32), y1.cpu().numpy().view(np.uint32))
+
+
+@pytest.mark.parametrize("n", [3, 1000, 4096, 16384, 1 << 20])
+def test_zero_input_gives_exact_zero(n):
+    # degenerate case of the error metric: a zero transform must come out exactly zero
+    say(f"case: zero input N={n}")
+    x = np.zeros((2, n), np.complex64)
+    for sign in (FWD, BWD):
+        y = gpu_fft(x, sign)
+        assert np.all(y == 0), sign
+    if n == 4096:
+        with fb.Plan(n, 2, FWD, fb.make_opts(storage=fb.STORAGE_F16)) as p:
+            z = p.execute(torch.zeros(2 * n, dtype=torch.complex32, device="cuda"))
+            assert torch.count_nonzero(torch.view_as_real(z)).item() == 0
+        rep = to_dev(inputs.sar_replica())
+        with fb.RangeCompressor(n, 2, rep) as rc:
+            z = rc.execute(to_dev(x))
+            assert torch.count_nonzero(torch.view_as_real(z)).item() == 0
