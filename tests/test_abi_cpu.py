@@ -206,3 +206,41 @@ def test_filter_planning_without_device():
     assert lib.fft_filter_create(8192, 1, ctypes.c_void_p(0x10004), 10, None, ctypes.byref(h)) == 1
     assert lib.fft_filter_create(8192, 1, ctypes.c_void_p(0x10000), 10, None, None) == 1
     assert h.value is None
+
+
+def test_every_handle_entry_point_rejects_null_and_unknown_handles():
+    lib = fb.load()
+    vp = ctypes.c_void_p
+    bogus = vp(0xdead0)
+    u64 = ctypes.c_uint64()
+    for h in (None, bogus):
+        assert lib.fft_execute_ex(h, 1, vp(16), vp(16), None, None) == 5
+        assert lib.fft_execute_pass(h, 1, vp(16), vp(16), None) == 5
+        assert lib.fft_execute_pass_timed(h, 1, vp(16), vp(16), None, vp(8), vp(8)) == 5
+        assert lib.fft_plan_twiddles(h, None, 0, ctypes.byref(ctypes.c_size_t())) == 5
+        assert lib.fft_ragged_execute(h, vp(16), vp(16), None, 0) == 5
+        assert lib.fft_ragged_describe(h, None, None) == 5
+        assert lib.fft_ragged_destroy(h) == 5
+        assert lib.fft_sched_submit(h, 1, 8, 1, -1, 16, 1, 0.0) == 5
+        assert lib.fft_sched_destroy(h) == 5
+        assert lib.fft_server_submit(h, 8, 1, -1, vp(16), ctypes.byref(u64)) == 5
+        assert lib.fft_server_wait(h, 1, 0.0, None, None) == 5
+        assert lib.fft_server_release(h, 1) == 5
+        assert lib.fft_server_drain(h, 0.0) == 5
+        assert lib.fft_server_destroy(h) == 5
+        assert lib.fft_server_clock(h) == -1.0
+    # events: null arguments are rejected before any HIP call
+    assert lib.fft_event_create(None) == 1
+    assert lib.fft_event_destroy(None) == 1
+    assert lib.fft_event_elapsed(None, None, None) == 1
+
+
+def test_scheduler_host_only_lifecycle():
+    # the scheduler makes no HIP call: it runs here without a device
+    from paper_1505_08067_amd import serving as sv
+    with sv.Scheduler(hbm_budget=1 << 20) as s:
+        s.submit(1, 1024, 2, fb.FORWARD, 32768, True, 0.0)
+        L = s.next(0.0)
+        assert L["requests"] == [1] and L["batch"] == 2
+        s.complete(L["id"], 0.5)
+        assert s.request(1)["state"] == fb.REQ_DONE and s.stats()["completed"] == 1
