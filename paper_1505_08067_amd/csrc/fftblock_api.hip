@@ -5,10 +5,11 @@
 // Planner (paper, Approach): the largest transform one compute unit holds is
 // derived from the local-memory size -- on gfx950 the LDS, 160 KB per CU --
 // as pow2floor(LDS / (8 B * (1 + 1/16) * k)) for k resident workgroups; the
-// runtime sweep then confirms which single-block lengths actually win
-// ("a mix of analytic approach and runtime validation").  Lengths up to the
-// limit run as one block per transform; longer power-of-two lengths run the
-// four-step split N = N1 * N2 with N1 >= N2, both powers of two.
+// runtime sweep then confirms which single-block lengths actually win (the
+// paper pairs the analytic bound with a measurement in the same way).
+// Lengths up to the limit run as one block per transform; longer
+// power-of-two lengths run the four-step split N = N1 * N2 (powers of two,
+// the split chosen by measurement, see plan_choose).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
