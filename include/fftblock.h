@@ -192,7 +192,10 @@ typedef struct {
 #define FFT_STORAGE_C64 0   /* interleaved FP32 (re, im), 8 bytes per value */
 #define FFT_STORAGE_F16 1   /* interleaved IEEE FP16 (re, im), 4 bytes per value; arithmetic stays FP32
                                (values are widened on load and rounded to nearest even on store);
-                               the four-step workspace stays FP32 */
+                               the four-step workspace stays FP32.  The transform is unnormalised,
+                               so an output can reach n * max|x|: outputs beyond 65504 in magnitude
+                               become +-inf (uniform [-1, 1] data stays far below that: its spectrum
+                               has rms sqrt(2n/3)) */
 
 typedef struct {
     size_t block_limit;  /* longest single-block length; 0 = fft_block_limit() */
