@@ -60,3 +60,28 @@ def test_poisson_trace_rate_and_ranges():
     assert n.min() >= 256 and n.max() <= 2 ** 22
     assert b.min() >= 1 and b.max() <= 512
     assert set(np.unique(sign).tolist()) == {-1, 1}
+
+
+def test_sar_replica_is_the_chirp_the_echoes_are_made_of():
+    # a single noiseless target at delay d: the row equals the replica shifted by d,
+    # up to its unit-modulus phase
+    ref = inputs.sar_replica()
+    assert ref.dtype == np.complex64 and ref.size == 625
+    assert np.allclose(np.abs(ref), 1.0, atol=1e-6)
+    x = inputs.sar(5, pulses=2, ranges=2048, targets=1, snr_db=200.0)
+    d = int(inputs.sar_delays(5, ranges=2048, targets=1)[0])
+    for row in x:
+        seg = row[d:d + ref.size].astype(np.complex128)
+        ratio = seg / ref.astype(np.complex128)
+        assert np.allclose(ratio, ratio[0], atol=1e-5) and abs(abs(ratio[0]) - 1) < 1e-5
+        assert np.max(np.abs(np.delete(row, np.s_[d:d + ref.size]))) < 1e-6
+
+
+def test_poisson_trace_batch_is_log_uniform():
+    # batch = floor(exp(U[0, ln 513))): P(b <= 22) = ln 23 / ln 513, about one half
+    t, n, b, sign = inputs.poisson_trace(9, 2000.0, 20.0)
+    frac = np.mean(b <= 22)
+    assert abs(frac - np.log(23) / np.log(513)) < 0.02
+    assert abs(np.mean(sign == -1) - 0.5) < 0.02
+    k = np.log2(n).astype(int)
+    assert set(np.unique(k)) == set(range(8, 23))
