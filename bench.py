@@ -215,13 +215,16 @@ def main():
         e["launches_per_step"] += 1
         e["total_ms"] += avg_ms
         e["durations_ms"].append(avg_ms)
+    kinfo = {k["name"]: k for k in fb.kernels()}
     breakdown = {}
     for kname, e in kernels.items():
         avg = e["total_ms"] / e["launches_per_step"]
         gbps = e["bytes_per_launch"] / (avg * 1e-3) / 1e9
+        occ = fb.kernel_occupancy(kname)
         breakdown[kname] = {"avg_us": round(avg * 1e3, 2), "launches_per_step": e["launches_per_step"],
                             "bytes_per_launch": int(e["bytes_per_launch"]), "GBps": round(gbps, 1),
-                            "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4)}
+                            "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4),
+                            "workgroups_per_cu": occ, "waves_per_simd": occ * kinfo[kname]["threads"] / 64 / 4}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     dom_avg_ms = kernels[dom]["total_ms"] / kernels[dom]["launches_per_step"]
     achieved = kernels[dom]["bytes_per_launch"] / (dom_avg_ms * 1e-3) / 1e9
@@ -236,6 +239,12 @@ def main():
         if args.no_serving:
             which.discard("serving")
         extras = run_extras(torch, fb, inputs, stream, which)
+    cp = extras.get("copy_probe")
+    if isinstance(cp, dict) and cp.get("GBps_read_plus_write"):
+        # the same kernels against what a plain copy reaches on this device
+        for row in breakdown.values():
+            row["frac_copy_peak"] = round(row["GBps"] / cp["GBps_read_plus_write"], 4)
+        roofline["frac_copy_peak"] = round(achieved / cp["GBps_read_plus_write"], 4)
     if args.calibrate:
         src = torch.empty((1 << 28) // 8, dtype=torch.complex64, device="cuda")
         dst = torch.empty_like(src)

@@ -246,6 +246,19 @@ typedef struct {
 int fft_kernel_count(void);
 fft_status_t fft_kernel_info(int index, fft_kernel_info_t* info);
 
+/*
+ * fft_kernel_occupancy -- workgroups of catalogue kernel `index` that one
+ * compute unit of the current device keeps resident at once, as the HIP
+ * runtime's occupancy calculator gives it from the kernel's registers, its
+ * LDS and the wave slots (four SIMDs, 64-wide waves).  A report about the
+ * implementation, not an operation of the paper: it tells how many
+ * workgroups overlap their LDS exchanges with other workgroups' loads.
+ *   workgroups_per_cu  HOST pointer, written on success.
+ * INVALID_ARG for a null pointer or an index outside [0, fft_kernel_count());
+ * DEVICE if there is no device or the runtime reports zero.
+ */
+fft_status_t fft_kernel_occupancy(int index, int* workgroups_per_cu);
+
 /* Fill `desc` for a plan.  INVALID_PLAN / INVALID_ARG on null arguments. */
 fft_status_t fft_plan_describe(fft_plan_t plan, fft_plan_desc_t* desc);
 

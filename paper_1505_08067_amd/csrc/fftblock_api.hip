@@ -365,6 +365,18 @@ fft_status_t fft_kernel_info(int index, fft_kernel_info_t* info)
     return FFT_SUCCESS;
 }
 
+fft_status_t fft_kernel_occupancy(int index, int* workgroups_per_cu)
+{
+    if (workgroups_per_cu == nullptr) return FFT_ERR_INVALID_ARG;
+    int c = 0;
+    const KEntry* t = kernel_table(&c);
+    if (index < 0 || index >= c) return FFT_ERR_INVALID_ARG;
+    const int occ = t[index].occupancy ? t[index].occupancy() : 0;
+    if (occ <= 0) return FFT_ERR_DEVICE;
+    *workgroups_per_cu = occ;
+    return FFT_SUCCESS;
+}
+
 // Pure host planning: path, kernels, four-step split and table layout.
 // Makes no HIP call, so it is usable (and testable) without a device.
 static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft_plan_opts_t* opts,

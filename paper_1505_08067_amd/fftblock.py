@@ -37,8 +37,8 @@ EXPORTS = (
     "fft_plan_create", "fft_execute", "fft_execute_pass", "fft_transpose", "fft_plan_destroy", "fft_status_string",
     "fft_plan_describe", "fft_plan_query", "fft_device_query", "fft_block_max", "fft_block_limit",
     "fft_copy", "fft_plan_opts_init", "fft_plan_create_ex", "fft_plan_query_ex", "fft_kernel_count",
-    "fft_kernel_info", "fft_schedule_search", "fft_stage_benchmark", "fft_autotune", "fft_wisdom_set",
-    "fft_wisdom_get", "fft_wisdom_clear", "fft_wisdom_save", "fft_wisdom_load",
+    "fft_kernel_info", "fft_kernel_occupancy", "fft_schedule_search", "fft_stage_benchmark", "fft_autotune",
+    "fft_wisdom_set", "fft_wisdom_get", "fft_wisdom_clear", "fft_wisdom_save", "fft_wisdom_load",
     "fft_ragged_create", "fft_ragged_execute", "fft_ragged_describe", "fft_ragged_destroy",
     "fft_plan_twiddles", "fft_ragged_create_ex", "fft_filter_create", "fft_filter_query", "fft_execute_ex",
     "fft_sched_opts_init", "fft_sched_create", "fft_sched_destroy", "fft_sched_submit", "fft_sched_next",
@@ -217,6 +217,7 @@ def load():
     lib.fft_kernel_count.argtypes = []
     lib.fft_kernel_count.restype = i
     lib.fft_kernel_info.argtypes = [i, ctypes.POINTER(KernelInfo)]
+    lib.fft_kernel_occupancy.argtypes = [i, ctypes.POINTER(i)]
     dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
     lib.fft_schedule_search.argtypes = [i, ip, i, dp, ip, ip, dp]
     lib.fft_stage_benchmark.argtypes = [sz, i, i, i, dp]
@@ -266,7 +267,7 @@ def load():
         getattr(lib, name).restype = ctypes.c_int
     for name in ("fft_plan_create", "fft_execute", "fft_execute_pass", "fft_transpose", "fft_plan_destroy",
                  "fft_plan_describe", "fft_plan_query", "fft_device_query", "fft_copy",
-                 "fft_plan_create_ex", "fft_plan_query_ex", "fft_kernel_info"):
+                 "fft_plan_create_ex", "fft_plan_query_ex", "fft_kernel_info", "fft_kernel_occupancy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -339,6 +340,20 @@ def kernels() -> list:
                     "radix": list(k.radix[: k.n_radix]), "threads": k.threads, "lds_bytes": k.lds_bytes,
                     "is_default": bool(k.is_default), "name": k.name.decode()})
     return out
+
+
+def kernel_occupancy(name: str) -> int:
+    """Workgroups per compute unit of the named catalogue kernel on the current
+    device (``fft_kernel_occupancy``)."""
+    lib = load()
+    for idx in range(lib.fft_kernel_count()):
+        k = KernelInfo()
+        _check(lib.fft_kernel_info(idx, ctypes.byref(k)), "fft_kernel_info")
+        if k.name.decode() == name:
+            occ = ctypes.c_int()
+            _check(lib.fft_kernel_occupancy(idx, ctypes.byref(occ)), "fft_kernel_occupancy")
+            return occ.value
+    raise FFTError(f"no kernel named {name}")
 
 
 def plan_query(n: int, batch: int, direction: int = FORWARD, opts: "PlanOpts | None" = None) -> dict:

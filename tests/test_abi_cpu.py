@@ -136,6 +136,11 @@ def test_null_and_unknown_handles():
     assert lib.fft_plan_describe(None, None) == 5
     assert lib.fft_plan_query(8, 1, -1, None) == 1
     assert lib.fft_device_query(0, None) == 1
+    occ = ctypes.c_int(-7)
+    assert lib.fft_kernel_occupancy(0, None) == 1
+    assert lib.fft_kernel_occupancy(-1, ctypes.byref(occ)) == 1
+    assert lib.fft_kernel_occupancy(lib.fft_kernel_count(), ctypes.byref(occ)) == 1
+    assert occ.value == -7
 
 
 def test_transpose_and_copy_argument_errors_without_device():

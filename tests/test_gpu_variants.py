@@ -147,3 +147,17 @@ def test_fourstep_forced_on_block_sizes(n, sign):
     say(f"forced four-step N={n} = {d['n1']}x{d['n2']}")
     ref = oracle.fft(x.astype(np.complex128), sign)
     metrics.check(y, ref, n)
+
+
+def test_kernel_occupancy_fits_the_compute_unit():
+    # every catalogue kernel can be resident, and the reported count respects the
+    # compute unit's LDS and thread limits
+    info = fb.device_query()
+    props = torch.cuda.get_device_properties(0)
+    max_threads = getattr(props, "max_threads_per_multi_processor", 2048)
+    for k in fb.kernels():
+        occ = fb.kernel_occupancy(k["name"])
+        say(f"{k['name']} occupancy {occ}")
+        assert occ >= 1, k["name"]
+        assert occ * k["lds_bytes"] <= info["lds_per_cu"], k["name"]
+        assert occ * k["threads"] <= max_threads, k["name"]
