@@ -47,7 +47,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle time for the CPU baseline")
     p.add_argument("--no-extras", action="store_true", help="skip copy probe and SAR chain timing")
-    p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.md"),
+    p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "hbm_traffic_n4096x4096_n2p20x16.md"),
                    help="rocprofv3 traffic summary (measured HBM bytes per launch per kernel)")
     p.add_argument("--no-serving", action="store_true", help="skip the serving stream (profiling runs)")
     p.add_argument("--extras", default=",".join(("copy", "sar", "fp16", "ragged", "serving")),

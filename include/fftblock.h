@@ -322,7 +322,8 @@ size_t fft_block_limit(void);
 /* ---------------------------------------------------------------------------
  * Bandwidth probe (the analogue of the paper's memory benchmark, Approach,
  * bottom-level analysis): copy `bytes` (multiple of 16, 16-byte aligned
- * pointers, no overlap) from `in` to `out` with 16-byte vector accesses.
+ * pointers, no overlap) from `in` to `out` with 16-byte streaming
+ * (non-temporal) vector loads and stores, the access form of the transforms.
  * ------------------------------------------------------------------------- */
 fft_status_t fft_copy(const void* in, void* out, size_t bytes, void* stream);
 

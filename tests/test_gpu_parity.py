@@ -186,12 +186,21 @@ def test_transpose_bit_exact(shape):
     assert np.array_equal(tt.cpu().numpy().view(np.uint32), x.view(np.uint32))
 
 
-def test_copy_probe():
-    a = torch.from_numpy(inputs.uniform(15, 1, 1 << 20)).to("cuda")
-    b = torch.empty_like(a)
+@pytest.mark.parametrize("values", [1 << 20, 2 * 1037, 2, (1 << 25) + 6])
+def test_copy_probe(values):
+    # whole rounds, a ragged last round, one 16-byte element, and three
+    # elements past one round of the capped grid (16384 x 1024 x 16 bytes)
+    say(f"copy {values} complex64 values")
+    g = torch.Generator(device="cuda").manual_seed(15)
+    a = torch.randn(values, dtype=torch.complex64, device="cuda", generator=g)
+    b = torch.full_like(a, complex(7.0, -7.0))
+    guard = torch.full((2 * values + 64,), complex(3.0, 3.0), dtype=torch.complex64, device="cuda")
+    fb.copy_(guard[32:32 + values], a)
     fb.copy_(b, a)
     torch.cuda.synchronize()
     assert torch.equal(a.view(torch.float32), b.view(torch.float32))
+    assert torch.equal(guard[32:32 + values].view(torch.float32), a.view(torch.float32))
+    assert bool((guard[:32] == complex(3.0, 3.0)).all()) and bool((guard[32 + values:] == complex(3.0, 3.0)).all())
 
 
 def test_device_query_and_block_limit():
