@@ -559,6 +559,8 @@ typedef struct {
     int auto_release;    /* nonzero: outputs are dropped at completion (load generation) */
 } fft_server_opts_t;
 
+/* A server's calls may come from any host threads; fft_server_destroy must
+ * not overlap another call on the same server. */
 typedef struct fft_server_s* fft_server_t;
 
 void fft_server_opts_init(fft_server_opts_t* opts);
@@ -569,8 +571,14 @@ fft_status_t fft_server_create(const fft_server_opts_t* opts, fft_server_t* out)
  * (plans and twiddle tables stay resident for the server's lifetime). */
 fft_status_t fft_server_prepare(fft_server_t s, size_t n, int direction);
 /* Queue a request; `in` is a DEVICE pointer to batch * n complex64 values that
- * must stay valid and unchanged until the request completes.  The output is
- * allocated from the server's arena.  Non-blocking. */
+ * must stay valid and unchanged until the request completes.  The output (and,
+ * for four-step lengths, the workspace) is allocated from the server's arena
+ * when the request is issued; outputs stay there until fft_server_release (or
+ * completion, with auto_release), and a full arena holds later launches back
+ * until room is freed.  Non-blocking.  OUT_OF_MEMORY at once for a request
+ * whose output (and workspace) can never fit the arena; INVALID_ARG for a null
+ * or misaligned pointer, zero sizes or a bad direction; UNSUPPORTED_SIZE for a
+ * length the planner has no kernels for. */
 fft_status_t fft_server_submit(fft_server_t s, size_t n, size_t batch, int direction, const void* in,
                                uint64_t* ticket);
 /* Block until the request completes (TIMEOUT after timeout_s seconds);

@@ -815,6 +815,10 @@ fft_status_t fft_server_submit(fft_server_t s, size_t n, size_t batch, int direc
     if (st != FFT_SUCCESS) return st;
     const bool four = d.path == FFT_PATH_FOURSTEP;
     const size_t bytes = n * batch * sizeof(float2) * (four ? 3 : 2);  // in + out (+ workspace)
+    // arena space it takes when issued (output, and workspace, in 256-byte
+    // units): a request that can never fit would hold the queue's head forever
+    const size_t part = (n * batch * sizeof(float2) + 255) & ~(size_t)255;
+    if (part * (four ? 2 : 1) > s->opts.arena_bytes) return FFT_ERR_OUT_OF_MEMORY;
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->error != FFT_SUCCESS) return s->error;
     const uint64_t id = s->next_id++;

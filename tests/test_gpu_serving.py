@@ -150,3 +150,31 @@ def test_server_edge_lengths():
             srv.release(tk)
         with pytest.raises(fb.FFTError):
             srv.release(tickets[0])                    # already released
+
+
+def test_server_arena_backpressure_and_oversize():
+    # 1 MiB arena: a request whose output can never fit is refused at submit;
+    # unreleased outputs hold a later launch back until one is released
+    n, b = 4096, 12                        # 384 KiB of output per request
+    xs = [torch.from_numpy(inputs.uniform(4100 + i, b, n)).to("cuda") for i in range(3)]
+    big = torch.from_numpy(inputs.uniform(4199, 4, 1 << 16)).to("cuda")
+    say("case: server arena 1 MiB, three 384 KiB outputs and one 2 MiB output")
+    with sv.Server(arena_bytes=1 << 20, hbm_budget=1 << 30, n_streams=2) as srv:
+        with pytest.raises(fb.FFTError) as ei:
+            srv.submit(big, 1 << 16, 4)
+        assert ei.value.status == 3
+        ta, tb = srv.submit(xs[0], n, b), srv.submit(xs[1], n, b)
+        ya, _ = srv.result(ta)
+        yb, _ = srv.result(tb)
+        tc = srv.submit(xs[2], n, b)
+        with pytest.raises(fb.FFTError) as ei:
+            srv.wait(tc, timeout=0.5)          # 768 KiB held, 256 KiB free
+        assert ei.value.status == 6
+        srv.release(ta)
+        yc, info = srv.result(tc)
+        assert info["state"] == fb.REQ_DONE
+        for x, y in ((xs[0], ya), (xs[1], yb), (xs[2], yc)):
+            ref = oracle.fft(x.cpu().numpy().astype(np.complex128))
+            metrics.check(y.cpu().numpy(), ref, n)
+        srv.release(tb)
+        srv.release(tc)
