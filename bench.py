@@ -50,8 +50,8 @@ def parse():
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "hbm_traffic_n4096x4096_n2p20x16.md"),
                    help="rocprofv3 traffic summary (measured HBM bytes per launch per kernel)")
     p.add_argument("--no-serving", action="store_true", help="skip the serving stream (profiling runs)")
-    p.add_argument("--extras", default=",".join(("copy", "sar", "fp16", "ragged", "serving")),
-                   help="comma list of extras to run: copy, sar, fp16, ragged, serving")
+    p.add_argument("--extras", default=",".join(("copy", "small", "sar", "fp16", "ragged", "serving")),
+                   help="comma list of extras to run: copy, small, sar, fp16, ragged, serving")
     p.add_argument("--calibrate", action="store_true",
                    help="also run the copy kernel on 256 MiB three times (counter calibration)")
     return p.parse_args()
@@ -221,7 +221,9 @@ def main():
         avg = e["total_ms"] / e["launches_per_step"]
         gbps = e["bytes_per_launch"] / (avg * 1e-3) / 1e9
         occ = fb.kernel_occupancy(kname)
-        breakdown[kname] = {"avg_us": round(avg * 1e3, 2), "launches_per_step": e["launches_per_step"],
+        durs = sorted(d for li, (k2, _, _, _) in enumerate(launches) if k2 == kname for d in per[li])
+        breakdown[kname] = {"avg_us": round(avg * 1e3, 2), "median_us": round(durs[len(durs) // 2] * 1e3, 2),
+                            "launches_per_step": e["launches_per_step"],
                             "bytes_per_launch": int(e["bytes_per_launch"]), "GBps": round(gbps, 1),
                             "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4),
                             "workgroups_per_cu": occ, "waves_per_simd": occ * kinfo[kname]["threads"] / 64 / 4}
@@ -292,13 +294,14 @@ def main():
         p.close()
 
 
-EXTRAS = ("copy", "sar", "fp16", "ragged", "serving")
+EXTRAS = ("copy", "small", "sar", "fp16", "ragged", "serving")
 
 
 def run_extras(torch, fb, inputs, stream, which=EXTRAS):
     out = {}
     todo = [("copy_probe", "copy", lambda: run_copy(torch, fb, stream)),
             ("fourstep_1024x1024", "copy", lambda: run_split(torch, fb, inputs, stream)),
+            ("small_batches", "small", lambda: run_small(torch, fb, inputs, stream)),
             ("sar", "sar", lambda: run_sar(torch, fb, inputs, stream)),
             ("fp16_storage", "fp16", lambda: run_fp16(torch, fb, inputs, stream)),
             ("ragged", "ragged", lambda: run_ragged(torch, fb, inputs, stream)),
@@ -449,6 +452,39 @@ def run_sar(torch, fb, inputs, stream):
     del x, t1, t2, t3
     log("SAR", json.dumps(sar))
     return out
+
+
+def run_small(torch, fb, inputs, stream):
+    """Batches too small to be HBM-bound: N=1024 x 64 forward (launch-bound),
+    three more small batches, and the paper's own workload N=1024 x 1024
+    (16 MiB in + out, resident in the Infinity Cache).  Per-call time is 50
+    back-to-back launches between two events (it includes the gaps between
+    launches); where the planner picks the one-wave form of a kernel, the
+    full-width form is timed beside it.  Kernel durations of the same launches
+    come from a kernel trace (dispatch-stamped events have a floor of about
+    4 us, above these kernels)."""
+    res = {}
+    sh = stream.cuda_stream
+    ks = {k["name"]: k for k in fb.kernels()}
+    cases = (("n1024x64_launch_bound", 1024, 64, 0), ("n512x64", 512, 64, 0), ("n256x256", 256, 256, 0),
+             ("n3072x64", 3072, 64, 0), ("n1024x1024_cache_resident", 1024, 1024, 1))
+    for name, n, batch, seed in cases:
+        x = torch.from_numpy(inputs.uniform(seed, batch, n)).to("cuda")
+        y = torch.empty_like(x)
+        row = {}
+        wide = ks[fb.plan_query(n, 1 << 20)["kernel_name"]]
+        forms = [("planner", None)]
+        if fb.plan_query(n, batch)["kernel_name"] != wide["name"]:
+            forms.append(("full_width", fb.make_opts(radix=wide["radix"], flags=wide["flags"], c=wide["c"])))
+        for form, opts in forms:
+            with fb.Plan(n, batch, fb.FORWARD, opts) as p:
+                t = _timed(torch, stream, lambda: p.execute_ptr(x.data_ptr(), y.data_ptr(), sh), reps=50)
+                row[form] = {"kernel": p.describe()["kernel_name"], "per_call_us": round(t * 1e6, 2),
+                             "GFLOPs_per_call": round(flops(n, batch) / t / 1e9, 1)}
+        res[name] = row
+        del x, y
+    log("small batches", json.dumps(res))
+    return res
 
 
 def _timed(torch, stream, fn, reps=10):

@@ -71,10 +71,17 @@ typedef enum {
  * fft_plan_create -- plan `batch` transforms of length `n` in `direction`
  * on the calling thread's current HIP device.
  *
- *   n          transform length; powers of two from 1 to 2^22 (the single
+ *   n          transform length: powers of two from 1 to 2^22 (the single
  *              block path covers n <= the LDS block limit, longer lengths
- *              use the four-step path).  Other lengths: UNSUPPORTED_SIZE.
- *   batch      number of transforms per execute (>= 1).
+ *              use the four-step path), and the compiled mixed-radix lengths
+ *              3, 5, 6, 10, 12, 15, 20, 60, 100, 1000, 3072, 6000 and 15360
+ *              (single block).  Other lengths: UNSUPPORTED_SIZE.
+ *   batch      number of transforms per execute (>= 1).  On the block path
+ *              the default kernel's width follows it: a batch that would
+ *              give the full-width kernel fewer than 128 workgroups runs
+ *              the one-wave form of the same schedule and variant (fewer
+ *              transforms per workgroup, more compute units busy); the
+ *              same rule applies to the batch of each fft_execute_ex call.
  *   direction  FFT_FORWARD or FFT_BACKWARD.
  *   plan_out   receives the plan handle.
  *
@@ -202,10 +209,12 @@ typedef struct {
     int n_radix;         /* schedule of the single block (four-step: of pass 1): 0 = default, else radix[0..n_radix) */
     int radix[8];
     int flags;           /* variant of the block kernel / pass 1; -1 = default */
-    int c;               /* four-step pass-1 columns per workgroup; 0 = default */
+    int c;               /* transforms per workgroup of the block kernel, or four-step pass-1
+                            columns per workgroup; 0 = default */
     int flags2;          /* variant of pass 2; -1 = default */
     int c2;              /* pass-2 rows per workgroup (workspace block width); 0 = default */
-    size_t n1;           /* four-step split n = n1 * n2 (a power of two); 0 = default 2^ceil(log2(n)/2) */
+    size_t n1;           /* four-step split n = n1 * n2 (a power of two); 0 = the planner's split
+                            (rows n2 up to 2048, columns n1 at least 256) */
     int storage;         /* FFT_STORAGE_C64 (default) or FFT_STORAGE_F16 */
     int device_twiddles; /* nonzero: evaluate the twiddle tables in FP64 on the GPU
                             (default: FP64 on the host); both round once to FP32 */

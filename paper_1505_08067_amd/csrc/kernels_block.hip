@@ -14,6 +14,12 @@ namespace fb {
     make_entry<N, E, C, Sched<__VA_ARGS__>, PolBlock, FL>(DEF, "block_fft<" #N ",[" #__VA_ARGS__ \
                                                                 "],v" #FL ">")
 
+// the same, with the workgroup width in the name (narrow variants of a
+// schedule that also exists at full width)
+#define FB_BLKC(DEF, FL, N, E, C, ...)                                                                  \
+    make_entry<N, E, C, Sched<__VA_ARGS__>, PolBlock, FL>(DEF, "block_fft<" #N ",C" #C ",[" #__VA_ARGS__ \
+                                                                "],v" #FL ">")
+
 #define FB_BLKH(DEF, FL, N, E, C, ...)                                                               \
     make_entry<N, E, C, Sched<__VA_ARGS__>, PolBlockH, FL>(DEF, "block_fft_f16<" #N ",[" #__VA_ARGS__ \
                                                                  "],v" #FL ">")
@@ -155,6 +161,20 @@ static const KEntry kBlock[] = {
     FB_BLK(false, 0, 8192, 32, 1, 16, 16, 32),
     FB_BLK(false, 0, 16384, 32, 1, 32, 32, 16),
     FB_BLK(false, 35, 16384, 32, 1, 32, 32, 16),
+    // small batches: one wavefront per workgroup (fewer transforms per
+    // workgroup, same schedule and variant), so a batch too small to fill the
+    // device spreads over more compute units; listed last so that a search by
+    // schedule and variant alone finds the full-width kernel first
+    FB_BLKC(false, 0, 16, 16, 64, 16),
+    FB_BLKC(false, 0, 32, 16, 32, 16, 2),
+    FB_BLKC(false, 0, 64, 16, 16, 16, 4),
+    FB_BLKC(false, 0, 128, 16, 8, 16, 8),
+    FB_BLKC(false, 35, 256, 16, 4, 16, 16),
+    FB_BLKC(false, 35, 512, 8, 1, 8, 8, 8),
+    FB_BLKC(false, 35, 1024, 16, 1, 16, 16, 4),
+    FB_BLKC(false, 35, 2048, 16, 1, 16, 16, 8),
+    FB_BLKC(false, 0, 1000, 10, 1, 10, 10, 10),
+    FB_BLKC(false, 35, 3072, 24, 1, 6, 8, 8, 8),
 };
 
 const KEntry* block_entries(int* count)

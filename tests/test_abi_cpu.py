@@ -249,3 +249,33 @@ def test_scheduler_host_only_lifecycle():
         assert L["requests"] == [1] and L["batch"] == 2
         s.complete(L["id"], 0.5)
         assert s.request(1)["state"] == fb.REQ_DONE and s.stats()["completed"] == 1
+
+
+def test_small_batches_take_the_one_wave_form():
+    # fewer than 128 workgroups of the full-width kernel: the narrowest compiled
+    # form of the same schedule and variant; otherwise the full-width default
+    ks = {k["name"]: k for k in fb.kernels()}
+    for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 1000, 3072):
+        wide = fb.plan_query(n, 1 << 16)
+        kw = ks[wide["kernel_name"]]
+        assert kw["is_default"], n
+        small_batch = 127 * kw["c"]                    # 127 workgroups
+        full_batch = 127 * kw["c"] + 1                 # 128 workgroups
+        narrow = fb.plan_query(n, small_batch)
+        kn = ks[narrow["kernel_name"]]
+        assert kn["c"] < kw["c"] and kn["radix"] == kw["radix"] and kn["flags"] == kw["flags"], n
+        assert kn["threads"] < kw["threads"]
+        assert narrow["transforms_per_block"] == kn["c"]
+        assert fb.plan_query(n, full_batch)["kernel_name"] == kw["name"], n
+    # lengths without a narrower form, FP16 storage and explicit options keep the default
+    assert fb.plan_query(4096, 1)["kernel_name"] == fb.plan_query(4096, 4096)["kernel_name"]
+    assert fb.plan_query(1024, 1, opts=fb.make_opts(storage=fb.STORAGE_F16))["transforms_per_block"] == 4
+    assert fb.plan_query(1024, 1, opts=fb.make_opts(radix=[16, 16, 4], flags=35))["transforms_per_block"] == 4
+    # wisdom names one kernel for every batch
+    fb.wisdom_clear()
+    alt = ks[fb.plan_query(1024, 1 << 16)["kernel_name"]]
+    fb.wisdom_set(1024, alt["name"])
+    try:
+        assert fb.plan_query(1024, 8)["kernel_name"] == alt["name"]
+    finally:
+        fb.wisdom_clear()
