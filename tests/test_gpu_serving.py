@@ -20,7 +20,10 @@ def say(*a):
 
 
 def test_execute_ex_batch_and_workspace():
-    for n, plan_batch, batch in ((4096, 1, 7), (1000, 2, 5), (1 << 20, 1, 3), (1 << 16, 4, 2)):
+    # (1024, 4096, 3) and (1024, 2, 4096): the call's batch, not the plan's,
+    # picks the block kernel's width (one-wave form below 128 workgroups)
+    for n, plan_batch, batch in ((4096, 1, 7), (1000, 2, 5), (1 << 20, 1, 3), (1 << 16, 4, 2), (1024, 4096, 3),
+                                 (1024, 2, 4096)):
         say(f"case: execute_ex n={n} plan batch {plan_batch} call batch {batch}")
         x = inputs.uniform(n + 11, batch, n)
         xd = torch.from_numpy(x).to("cuda")
