@@ -571,6 +571,8 @@ def run_serving(torch, fb, inputs):
             "coalesced_requests": st["coalesced_requests"], "backfilled_requests": st["backfilled_requests"],
             "p50_ms": round(st["latency_p50"] * 1e3, 3), "p99_ms": round(st["latency_p99"] * 1e3, 3),
             "mean_ms": round(st["latency_mean"] * 1e3, 3), "max_ms": round(st["latency_max"] * 1e3, 3),
+            "queue_p50_ms": round(st["queue_p50"] * 1e3, 3), "queue_p99_ms": round(st["queue_p99"] * 1e3, 3),
+            "device_p50_ms": round(st["device_p50"] * 1e3, 3), "device_p99_ms": round(st["device_p99"] * 1e3, 3),
             "peak_inflight_GiB": round(st["peak_inflight_bytes"] / 2 ** 30, 2),
             "wall_s": round(st["wall"], 3), "GFLOPs": round(fl / st["wall"] / 1e9, 1),
             "points_per_s": round(pts / st["wall"], 1)}

@@ -542,6 +542,9 @@ typedef struct {
     double points;                /* transform points completed (n * batch summed) */
     double t_last_done;
     double latency_p50, latency_p99, latency_mean, latency_max;   /* seconds, nearest rank */
+    double queue_p50, queue_p99;    /* seconds from arrival to launch (admission and stream wait) */
+    double device_p50, device_p99;  /* seconds from launch to completion (on the device, with
+                                       whatever shares it) */
 } fft_sched_stats_t;
 
 typedef struct fft_sched_s* fft_sched_t;

@@ -201,6 +201,8 @@ public:
             r.state = FFT_REQ_DONE;
             r.t_done = now;
             lat_.push_back(now - r.t_arrive);
+            wait_.push_back(r.t_launch - r.t_arrive);
+            run_.push_back(now - r.t_launch);
             points_ += (double)r.n * (double)r.batch;
             ++completed_;
             if (done) done->push_back(id);
@@ -254,20 +256,26 @@ public:
         s->points = points_;
         s->t_last_done = t_last_;
         if (!lat_.empty()) {
-            std::vector<double> v = lat_;
-            std::sort(v.begin(), v.end());
             // nearest rank: the smallest value with at least p of the samples at or below it
-            auto pct = [&](double p) {
+            auto pct = [](const std::vector<double>& v, double p) {
                 size_t k = (size_t)std::ceil(p * (double)v.size());
                 if (k < 1) k = 1;
                 return v[k - 1];
             };
+            std::vector<double> v = lat_, w = wait_, r = run_;
+            std::sort(v.begin(), v.end());
+            std::sort(w.begin(), w.end());
+            std::sort(r.begin(), r.end());
             double sum = 0.0;
             for (double x : v) sum += x;
-            s->latency_p50 = pct(0.50);
-            s->latency_p99 = pct(0.99);
+            s->latency_p50 = pct(v, 0.50);
+            s->latency_p99 = pct(v, 0.99);
             s->latency_mean = sum / (double)v.size();
             s->latency_max = v.back();
+            s->queue_p50 = pct(w, 0.50);
+            s->queue_p99 = pct(w, 0.99);
+            s->device_p50 = pct(r, 0.50);
+            s->device_p99 = pct(r, 0.99);
         }
     }
 
@@ -283,7 +291,7 @@ private:
     size_t submitted_ = 0, completed_ = 0, rejected_ = 0, launches_ = 0, coalesced_ = 0;
     long long next_launch_ = 0;
     double points_ = 0.0, t_last_ = 0.0;
-    std::vector<double> lat_;
+    std::vector<double> lat_, wait_, run_;  // arrival->done, arrival->launch, launch->done
 };
 
 bool opts_ok(const fft_sched_opts_t& o)

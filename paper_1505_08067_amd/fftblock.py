@@ -159,7 +159,8 @@ class SchedStats(ctypes.Structure):
         ("inflight_bytes", ctypes.c_size_t),
         ("peak_inflight_bytes", ctypes.c_size_t), ("points", ctypes.c_double), ("t_last_done", ctypes.c_double),
         ("latency_p50", ctypes.c_double), ("latency_p99", ctypes.c_double), ("latency_mean", ctypes.c_double),
-        ("latency_max", ctypes.c_double),
+        ("latency_max", ctypes.c_double), ("queue_p50", ctypes.c_double), ("queue_p99", ctypes.c_double),
+        ("device_p50", ctypes.c_double), ("device_p99", ctypes.c_double),
     ]
 
 

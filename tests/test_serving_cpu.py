@@ -42,6 +42,9 @@ def test_fifo_admission_under_budget_without_bypass():
         assert st["completed"] == 3 and st["inflight_bytes"] == 0
         lat = sorted([1.0, 2.0 - 0.1, 1.5 - 0.2])
         assert st["latency_p50"] == pytest.approx(lat[1]) and st["latency_max"] == pytest.approx(lat[2])
+        # queue: launch - arrival (0.3, 0.9, 0.8); device: completion - launch (0.7, 1.0, 0.5)
+        assert st["queue_p50"] == pytest.approx(0.8) and st["queue_p99"] == pytest.approx(0.9)
+        assert st["device_p50"] == pytest.approx(0.7) and st["device_p99"] == pytest.approx(1.0)
         assert s.request(2)["t_launch"] == pytest.approx(1.0) and s.request(2)["state"] == fb.REQ_DONE
 
 
@@ -165,6 +168,12 @@ def test_simulated_cfg5_trace_accounting():
         lat = np.array([s.request(i)["t_done"] - trace[i]["t"] for i in range(len(trace))])
         k = lambda p: np.sort(lat)[int(np.ceil(p * lat.size)) - 1]   # nearest rank
         assert st["latency_p50"] == pytest.approx(k(0.5)) and st["latency_p99"] == pytest.approx(k(0.99))
+        q = np.array([s.request(i)["t_launch"] - trace[i]["t"] for i in range(len(trace))])
+        d = np.array([s.request(i)["t_done"] - s.request(i)["t_launch"] for i in range(len(trace))])
+        kq = lambda p: np.sort(q)[int(np.ceil(p * q.size)) - 1]
+        kd = lambda p: np.sort(d)[int(np.ceil(p * d.size)) - 1]
+        assert st["queue_p50"] == pytest.approx(kq(0.5)) and st["queue_p99"] == pytest.approx(kq(0.99))
+        assert st["device_p50"] == pytest.approx(kd(0.5)) and st["device_p99"] == pytest.approx(kd(0.99))
         assert st["points"] == pytest.approx(sum(r["n"] * r["batch"] for r in trace))
     # the plain path (one stream, one launch at a time, no batching) is never faster at p99
     with sv.Scheduler(hbm_budget=budget, n_streams=1, max_inflight=1, max_coalesce=1, backfill_bytes=0) as s:
