@@ -508,6 +508,11 @@ typedef struct {
     size_t backfill_bytes;  /* while the head request waits for room, later requests of at most this
                                many bytes may pass it, at most this many bytes of them in flight
                                (default 1 GiB; 0 = strict FIFO) */
+    int small_streams;      /* streams [0, small_streams) take only launches led by a request of at
+                               most small_bytes, so short requests never queue on a stream behind a
+                               long transform (they use any stream when these are full); default 1,
+                               0 = none, capped at n_streams - 1 */
+    size_t small_bytes;     /* default 64 MiB */
 } fft_sched_opts_t;
 
 typedef struct {

@@ -11,7 +11,11 @@
 //     time, so the head is delayed by little and never starved
 //     (backfill_bytes = 0: strict FIFO);
 //   * the launch goes to the stream with the fewest outstanding bytes among
-//     those with fewer than max_inflight launches outstanding;
+//     those with fewer than max_inflight launches outstanding; the first
+//     small_streams streams take only launches led by requests of at most
+//     small_bytes (a lane for short requests, which would otherwise wait on a
+//     stream behind a long transform), and such a launch uses any stream
+//     when the lane is full;
 //   * continuous batching: queued requests of the same (n, direction) that
 //     the library can run as one list launch join the head's launch, in
 //     arrival order, up to max_coalesce requests / max_transforms transforms
@@ -97,10 +101,6 @@ public:
             queue_.pop_front();
         }
         if (queue_.empty()) return false;
-        int s = -1;
-        for (int i = 0; i < o_.n_streams; ++i)
-            if (out_[(size_t)i] < o_.max_inflight && (s < 0 || outb_[(size_t)i] < outb_[(size_t)s])) s = i;
-        if (s < 0) return false;
         // the head, or -- while the head waits for room -- the first small
         // request that fits (backfill, bounded so the head is not starved)
         auto pick = queue_.begin();
@@ -115,6 +115,8 @@ public:
             backfill = true;
         }
         SReq& head = reqs_[*pick];
+        const int s = pick_stream(head.bytes);
+        if (s < 0) return false;
         L->id = next_launch_++;
         L->stream = s;
         L->n = head.n;
@@ -159,6 +161,26 @@ public:
         if (L->reqs.size() > 1) coalesced_ += L->reqs.size();
         running_[L->id] = *L;
         return true;
+    }
+
+    // Stream for a launch led by a request of `bytes`: the fewest outstanding
+    // bytes among streams below max_inflight.  Streams [0, lane) take only
+    // small launches (at most small_bytes), so short requests do not queue on
+    // a stream behind a long transform; a small launch falls back to any
+    // stream when the lane is full.  -1: none free.
+    int pick_stream(size_t bytes) const
+    {
+        const int lane = std::min(o_.small_streams, o_.n_streams - 1);
+        const bool small = lane > 0 && bytes <= o_.small_bytes;
+        auto best = [&](int lo, int hi) {
+            int s = -1;
+            for (int i = lo; i < hi; ++i)
+                if (out_[(size_t)i] < o_.max_inflight && (s < 0 || outb_[(size_t)i] < outb_[(size_t)s])) s = i;
+            return s;
+        };
+        if (!small) return best(lane, o_.n_streams);
+        const int s = best(0, lane);
+        return s >= 0 ? s : best(0, o_.n_streams);
     }
 
     // Undo a next() whose launch could not be issued: the requests go back to
@@ -297,7 +319,8 @@ private:
 bool opts_ok(const fft_sched_opts_t& o)
 {
     return o.hbm_budget > 0 && o.n_streams >= 1 && o.n_streams <= 16 && o.max_inflight >= 1 &&
-           o.max_coalesce >= 1 && o.max_coalesce <= FFT_LAUNCH_MAX_REQUESTS && o.max_transforms >= 1;
+           o.max_coalesce >= 1 && o.max_coalesce <= FFT_LAUNCH_MAX_REQUESTS && o.max_transforms >= 1 &&
+           o.small_streams >= 0;
 }
 
 }  // namespace
@@ -355,6 +378,8 @@ void fft_sched_opts_init(fft_sched_opts_t* o)
     o->max_coalesce = 32;
     o->max_transforms = 16384;
     o->backfill_bytes = (size_t)1 << 30;
+    o->small_streams = 1;
+    o->small_bytes = (size_t)64 << 20;
 }
 
 fft_status_t fft_sched_create(const fft_sched_opts_t* opts, fft_sched_t* out)

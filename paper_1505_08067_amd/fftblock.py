@@ -127,6 +127,7 @@ class SchedOpts(ctypes.Structure):
     _fields_ = [
         ("hbm_budget", ctypes.c_size_t), ("n_streams", ctypes.c_int), ("max_inflight", ctypes.c_int),
         ("max_coalesce", ctypes.c_int), ("max_transforms", ctypes.c_size_t), ("backfill_bytes", ctypes.c_size_t),
+        ("small_streams", ctypes.c_int), ("small_bytes", ctypes.c_size_t),
     ]
 
 

@@ -19,12 +19,13 @@ from . import fftblock as fb
 
 
 def sched_opts(hbm_budget=64 << 30, n_streams=4, max_inflight=2, max_coalesce=32, max_transforms=16384,
-               backfill_bytes=1 << 30):
+               backfill_bytes=1 << 30, small_streams=1, small_bytes=64 << 20):
     o = fb.SchedOpts()
     fb.load().fft_sched_opts_init(ctypes.byref(o))
     o.hbm_budget, o.n_streams, o.max_inflight = int(hbm_budget), int(n_streams), int(max_inflight)
     o.max_coalesce, o.max_transforms = int(max_coalesce), int(max_transforms)
     o.backfill_bytes = int(backfill_bytes)
+    o.small_streams, o.small_bytes = int(small_streams), int(small_bytes)
     return o
 
 

@@ -88,7 +88,7 @@ def test_oversized_request_is_rejected_and_others_proceed():
 
 
 def test_stream_choice_and_inflight_cap():
-    with sv.Scheduler(hbm_budget=1 << 30, n_streams=2, max_inflight=1, max_coalesce=1) as s:
+    with sv.Scheduler(hbm_budget=1 << 30, n_streams=2, max_inflight=1, max_coalesce=1, small_streams=0) as s:
         for i, nb in enumerate((500, 100, 100)):
             s.submit(i, 64 << i, 1, F, nb, False, 0.0)
         a, b = s.next(0.0), s.next(0.0)
@@ -97,12 +97,45 @@ def test_stream_choice_and_inflight_cap():
         s.complete(a["id"], 1.0)
         c = s.next(1.0)
         assert c["stream"] == 0 and c["requests"] == [2]
-    with sv.Scheduler(hbm_budget=1 << 30, n_streams=2, max_inflight=2, max_coalesce=1) as s:
+    with sv.Scheduler(hbm_budget=1 << 30, n_streams=2, max_inflight=2, max_coalesce=1, small_streams=0) as s:
         for i, nb in enumerate((500, 100, 100)):
             s.submit(i, 64 << i, 1, F, nb, False, 0.0)
         got = [s.next(0.0) for _ in range(3)]
         # least outstanding bytes: 0 -> s0 (500), 1 -> s1 (100), 2 -> s1 (200 < 500)
         assert [g["stream"] for g in got] == [0, 1, 1]
+
+
+def test_small_request_lane():
+    # stream 0 takes only launches led by requests of at most small_bytes;
+    # larger ones use streams 1..n-1; a small launch falls back to any stream
+    # when the lane is full
+    kw = dict(hbm_budget=1 << 30, max_inflight=1, max_coalesce=1, small_streams=1, small_bytes=100)
+    with sv.Scheduler(n_streams=3, **kw) as s:
+        for i, nb in enumerate((500, 50, 600, 60, 70)):
+            s.submit(i, 64 << i, 1, F, nb, False, 0.0)
+        a, b, c = s.next(0.0), s.next(0.0), s.next(0.0)
+        assert (a["requests"], a["stream"]) == ([0], 1)
+        assert (b["requests"], b["stream"]) == ([1], 0)
+        assert (c["requests"], c["stream"]) == ([2], 2)
+        assert s.next(0.0) is None                    # every stream at its cap
+        s.complete(b["id"], 1.0)
+        d = s.next(1.0)
+        assert (d["requests"], d["stream"]) == ([3], 0)
+        s.complete(a["id"], 1.0)
+        e = s.next(1.0)
+        assert (e["requests"], e["stream"]) == ([4], 1)   # lane full: any stream
+    # a large head never takes the lane
+    with sv.Scheduler(n_streams=2, **kw) as s:
+        s.submit(0, 64, 1, F, 500, False, 0.0)
+        s.submit(1, 128, 1, F, 500, False, 0.0)
+        assert s.next(0.0)["stream"] == 1
+        assert s.next(0.0) is None
+    # one stream: no lane
+    with sv.Scheduler(n_streams=1, **kw) as s:
+        s.submit(0, 64, 1, F, 500, False, 0.0)
+        assert s.next(0.0)["stream"] == 0
+    with pytest.raises(fb.FFTError):
+        sv.Scheduler(small_streams=-1)
 
 
 def test_continuous_batching_groups_same_length_and_direction():
