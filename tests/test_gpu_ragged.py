@@ -144,3 +144,30 @@ def test_ragged_fp16_storage():
             alone = torch.view_as_real(p.execute(xh[at:at + n * c].clone())).cpu().numpy()
         assert np.array_equal(alone.view(np.int16), g16[at:at + n * c].view(np.int16)), n
         at += n * c
+
+
+def test_full_ragged_mix_sampled_against_oracle():
+    # the full mix the bench times (15 lengths, about 2^28 points, one graph
+    # launch): the first and the last transform of every length against the oracle
+    sizes = inputs.ragged_sizes(3)
+    classes = [(int(n), int((sizes == n).sum())) for n in inputs.RAGGED_POW2 + inputs.RAGGED_MIXED]
+    total = sum(n * c for n, c in classes)
+    say(f"case: full ragged mix, {len(classes)} lengths, {total} points")
+    x = torch.empty(total, dtype=torch.complex64, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    x.real.uniform_(-1.0, 1.0, generator=gen)
+    x.imag.uniform_(-1.0, 1.0, generator=gen)
+    with fb.Ragged(classes, fb.FORWARD) as r:
+        y = r.execute(x)
+        torch.cuda.synchronize()
+    at = 0
+    for n, c in classes:
+        for b in (0, c - 1):
+            lo = at + b * n
+            xs = x[lo:lo + n].cpu().numpy().astype(np.complex128)[None, :]
+            ys = y[lo:lo + n].cpu().numpy()[None, :]
+            mx, _, tol = metrics.check(ys, oracle.fft(xs, -1), n)
+            say(f"  N={n} transform {b} of {c}: rel L2 {mx:.2e} (tol {tol:.1e})")
+        at += n * c
+    assert at == total
