@@ -181,3 +181,56 @@ def test_server_arena_backpressure_and_oversize():
             metrics.check(y.cpu().numpy(), ref, n)
         srv.release(tb)
         srv.release(tc)
+
+
+def test_served_stream_slice_sampled_against_oracle():
+    # 0.1 s of the full serving stream (N = 2^8 ... 2^22, batch 1 ... 512, both
+    # directions, 64 GiB budget, the default pooled server): the first
+    # transform of every request against the oracle.  Outputs are read back
+    # and released as requests complete, so the arena never fills.
+    import collections
+    import ctypes
+    t, nn, bb, sg = inputs.poisson_trace(4, 2000.0, 0.1, 8, 22, 512)
+    trace = [{"t": float(t[i]), "n": int(nn[i]), "batch": int(bb[i]), "direction": int(sg[i])}
+             for i in range(t.size)]
+    say(f"case: served stream slice, {len(trace)} requests")
+    pool_points = (1 << 22) * 512
+    pool = torch.empty(pool_points, dtype=torch.complex64, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4)
+    pool.real.uniform_(-1.0, 1.0, generator=gen)
+    pool.imag.uniform_(-1.0, 1.0, generator=gen)
+    offs = sv.trace_offsets(5, trace, pool_points)
+    lib = fb.load()
+    got, pending = {}, collections.deque()
+    with sv.Server(hbm_budget=64 << 30) as srv:
+        def collect(block):
+            while pending:
+                i, tk = pending[0]
+                out, info = ctypes.c_void_p(), fb.RequestInfo()
+                st = lib.fft_server_wait(srv._h, tk, 60.0 if block else 0.0, ctypes.byref(out), ctypes.byref(info))
+                if st == 6 and not block:
+                    return
+                fb._check(st, "fft_server_wait")
+                n = trace[i]["n"]
+                y = torch.empty(n, dtype=torch.complex64, device="cuda")
+                fb._check(lib.fft_copy(out, ctypes.c_void_p(y.data_ptr()), n * 8, None), "fft_copy")
+                torch.cuda.synchronize()
+                got[i] = y.cpu().numpy()
+                srv.release(tk)
+                pending.popleft()
+
+        # the arrival loop of serving.replay, without its final drain: the
+        # outputs still held must be read and released first
+        t0 = srv.clock()
+        for i, r in enumerate(trace):
+            while srv.clock() < t0 + r["t"]:
+                pass
+            pending.append((i, srv.submit_ptr(pool.data_ptr() + 8 * offs[i], r["n"], r["batch"], r["direction"])))
+            collect(False)
+        collect(True)
+    assert len(got) == len(trace)
+    for i, r in enumerate(trace):
+        n = r["n"]
+        x = pool[offs[i]:offs[i] + n].cpu().numpy().astype(np.complex128)[None, :]
+        metrics.check(got[i][None, :], oracle.fft(x, r["direction"]), n)
