@@ -311,10 +311,10 @@ def run_extras(torch, fb, inputs, stream, which=EXTRAS):
             continue
         try:
             res = fn()
-        except fb.FFTError as e:
+        except (fb.FFTError, RuntimeError, ValueError) as e:
             # a failed extra is reported, not fatal to the headline line
-            res = {"error": str(e)}
-            log(f"{key} failed: {e}")
+            res = {"error": f"{type(e).__name__}: {e}"}
+            log(f"{key} failed: {type(e).__name__}: {e}")
             torch.cuda.synchronize()
         if key == "sar" and "error" not in res:
             out.update(res)
