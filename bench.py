@@ -259,7 +259,13 @@ def main():
     # ------------------------------------------------------- CPU baseline
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(items, fl_step, args.cpu_seconds)
+        # the GPU's outputs of the same inputs, compared with the oracle's
+        outs = {}
+        for name, n, batch, sign in items:
+            xin = bufs[(n, batch)][0][0]
+            outs[name] = plans[name].execute(xin).cpu().numpy().reshape(batch, n)
+        cpu = cpu_baseline(items, fl_step, args.cpu_seconds, outs)
+        del outs
 
     rec = {
         "metric": METRIC,
@@ -644,31 +650,42 @@ def run_ragged(torch, fb, inputs, stream):
     return res
 
 
-def cpu_baseline(items, fl_step, target_s):
-    """The FP64 oracle (radix-2 recursion, all host threads) on the same step, repeated ~target_s."""
+def cpu_baseline(items, fl_step, target_s, gpu_outs=None):
+    """The FP64 oracle (radix-2 recursion, all host threads) on the same step,
+    repeated ~target_s.  The first repetition's results are also compared with
+    the GPU's outputs of the same inputs (relative L2 per transform)."""
     import numpy as np
 
     import oracle
+    from oracle import metrics
     from paper_1505_08067_amd import inputs
 
     data = {}
     for _, n, batch, _ in items:
         if (n, batch) not in data:
             data[(n, batch)] = inputs.uniform(1, batch, n).astype(np.complex128)
-    reps, t_total = 0, 0.0
+    reps, t_total, err = 0, 0.0, {}
     while t_total < target_s or reps == 0:
         t0 = time.perf_counter()
-        for _, n, batch, sign in items:
-            oracle.fft_radix2(data[(n, batch)], sign)
+        res = [oracle.fft_radix2(data[(n, batch)], sign) for _, n, batch, sign in items]
         t_total += time.perf_counter() - t0
+        if reps == 0 and gpu_outs:
+            for (name, n, _, _), ref in zip(items, res):
+                e = metrics.rel_l2_per_transform(gpu_outs[name], ref)
+                err[name] = {"max_rel_l2": float(f"{np.max(e):.3e}"), "median_rel_l2": float(f"{np.median(e):.3e}"),
+                             "tolerance": float(f"{metrics.tolerance(n):.3e}")}
+        del res
         reps += 1
         if reps >= 50:
             break
     value = fl_step * reps / t_total / 1e9
     log(f"cpu baseline: {reps} steps in {t_total:.2f} s")
-    return {"value": round(value, 3), "unit": "GFLOP/s", "cores": oracle.nthreads(), "kind": "oracle",
-            "sample": f"{reps} full step(s) of the same workload (4096x4096 fwd+inv, 2^20x16 fwd+inv) "
-                      f"through the FP64 radix-2 oracle, {t_total:.1f} s"}
+    out = {"value": round(value, 3), "unit": "GFLOP/s", "cores": oracle.nthreads(), "kind": "oracle",
+           "sample": f"{reps} full step(s) of the same workload (4096x4096 fwd+inv, 2^20x16 fwd+inv) "
+                     f"through the FP64 radix-2 oracle, {t_total:.1f} s"}
+    if err:
+        out["gpu_error_vs_oracle"] = err
+    return out
 
 
 if __name__ == "__main__":
