@@ -286,6 +286,18 @@ def _stream_handle(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _record(stream, *tensors) -> None:
+    """Work queued on a stream other than the current one: the caching
+    allocator must not hand these tensors' blocks out again before that
+    stream has used them."""
+    if stream is None:
+        return
+    import torch
+    for t in tensors:
+        if stream != torch.cuda.current_stream(t.device):
+            t.record_stream(stream)
+
+
 def _check_tensor(x, name: str, storage: int = 0):
     import torch
     if not isinstance(x, torch.Tensor):
@@ -409,6 +421,7 @@ class Plan:
         st = _stream_handle(stream)
         _check(load().fft_execute(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), st),
                "fft_execute")
+        _record(stream, x, out)
         return out
 
     def execute_ptr(self, in_ptr: int, out_ptr: int, stream_handle: int = 0) -> None:
@@ -526,6 +539,7 @@ def transpose(x, out=None, stream=None):
     _check_tensor(out, "out")
     _check(load().fft_transpose(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                 rows, cols, batch, _stream_handle(stream)), "fft_transpose")
+    _record(stream, x, out)
     return out
 
 
@@ -536,6 +550,7 @@ def copy_(dst, src, stream=None):
         raise ValueError("size mismatch")
     _check(load().fft_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
                            _stream_handle(stream)), "fft_copy")
+    _record(stream, src, dst)
     return dst
 
 
@@ -679,6 +694,7 @@ class Ragged:
         _check_tensor(out, "out", self.storage)
         _check(load().fft_ragged_execute(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                          _stream_handle(stream), 0 if graph else 1), "fft_ragged_execute")
+        _record(stream, x, out)
         return out
 
     def describe(self) -> dict:

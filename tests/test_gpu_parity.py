@@ -294,3 +294,25 @@ def test_zero_input_gives_exact_zero(n):
         with fb.RangeCompressor(n, 2, rep) as rc:
             z = rc.execute(to_dev(x))
             assert torch.count_nonzero(torch.view_as_real(z)).item() == 0
+
+
+@pytest.mark.parametrize("n", [4096, 1 << 20])
+def test_execute_on_a_side_stream(n):
+    # work queued on a stream other than the current one gives the same
+    # result, and the output allocated for it stays valid until that stream
+    # has run (the binding records the stream on the tensors)
+    batch = 8 if n == 4096 else 2
+    say(f"case: side stream N={n} batch={batch}")
+    x = torch.from_numpy(inputs.uniform(60, batch, n)).to("cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with fb.Plan(n, batch) as p:
+        ref = p.execute(x)
+        ys = [p.execute(x, stream=side) for _ in range(3)]
+        ys.append(fb.transpose(x.view(batch, n // 64, 64), stream=side))
+        side.synchronize()
+        torch.cuda.synchronize()
+    for y in ys[:3]:
+        assert torch.equal(torch.view_as_real(y), torch.view_as_real(ref))
+    tref = x.view(batch, n // 64, 64).transpose(1, 2).contiguous()
+    assert torch.equal(torch.view_as_real(ys[3]), torch.view_as_real(tref))
