@@ -305,9 +305,10 @@ def test_execute_on_a_side_stream(n):
     say(f"case: side stream N={n} batch={batch}")
     x = torch.from_numpy(inputs.uniform(60, batch, n)).to("cuda")
     side = torch.cuda.Stream()
-    side.wait_stream(torch.cuda.current_stream())
     with fb.Plan(n, batch) as p:
         ref = p.execute(x)
+        # one plan, one workspace: the side stream starts after the current one
+        side.wait_stream(torch.cuda.current_stream())
         ys = [p.execute(x, stream=side) for _ in range(3)]
         ys.append(fb.transpose(x.view(batch, n // 64, 64), stream=side))
         side.synchronize()
