@@ -473,18 +473,23 @@ fft_status_t fft_ragged_describe(fft_ragged_t r, size_t* total_points, size_t* g
 fft_status_t fft_ragged_destroy(fft_ragged_t r);
 
 /* ---------------------------------------------------------------------------
- * Serving: a request scheduler and a GPU server built on it.
+ * Serving: a request scheduler and a GPU server built on it.  Not an
+ * operation of the paper: its top-level analysis runs one batch of
+ * same-size FFTs (one FFT per processing element, read / compute / write);
+ * serving extends that to requests of any size arriving over time.
  *
  * Requests (n, batch, direction) arrive over time.  The scheduler admits them
  * in arrival order while the bytes of the requests in flight (input, output
  * and four-step workspace) stay within an HBM budget; a request larger than
  * the budget is rejected, one that does not fit yet waits at the head of the
- * queue, and while it waits only small requests (backfill_bytes) may pass it.  Each launch goes to the stream with the fewest outstanding bytes
- * among those with fewer than max_inflight launches outstanding.  Continuous
- * batching: queued requests of the same (n, direction) on the single-block
- * path join the head request's launch (one list launch), in arrival order,
- * up to max_coalesce requests and max_transforms transforms.  Latency =
- * completion time - arrival time.
+ * queue, and while it waits only small requests (backfill_bytes) may pass it.
+ * Each launch goes to the stream with the fewest outstanding bytes among
+ * those with fewer than max_inflight launches outstanding; the first
+ * small_streams streams are kept for launches led by short requests.
+ * Continuous batching: queued requests of the same (n, direction) on the
+ * single-block path join the head request's launch (one list launch), in
+ * arrival order, up to max_coalesce requests and max_transforms transforms.
+ * Latency = completion time - arrival time.
  *
  * The scheduler alone (fft_sched_*) is a host-only state machine: it makes
  * no HIP call and takes every time as an argument (seconds, any monotonic
