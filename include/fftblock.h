@@ -434,7 +434,9 @@ fft_status_t fft_filter_query(size_t n, size_t batch, size_t replica_len, const 
                               fft_plan_desc_t* desc);
 
 /* ---------------------------------------------------------------------------
- * Ragged batches: transforms of several lengths in one submission.
+ * Ragged batches: transforms of several lengths in one submission (the
+ * paper's top-level analysis submits one batch of one size; here the lengths
+ * of a mix each get the schedule the autotuner measured best for them).
  * ------------------------------------------------------------------------- */
 typedef struct fft_ragged_s* fft_ragged_t;
 
