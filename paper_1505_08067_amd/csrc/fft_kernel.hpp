@@ -34,7 +34,18 @@
 
 namespace fb {
 
-enum : int { kSwz = 8, kStaged = 16, kTwPow = 32, kXcd = 128, kStageStride = 256, kWaveSync = 512 };
+enum : int { kSwz = 8, kStaged = 16, kTwPow = 32, kXcd = 128, kStageStride = 256, kWaveSync = 512, kHalfX = 1024 };
+
+// Half exchanges (kHalfX): two-stage schedules [R, 2R] with E = 2R values per
+// thread.  Stage 0's two butterflies per thread write exactly the two halves
+// of the slots that stage 1 reads, so the exchange (and the staged store of
+// pass 1) can run in two rounds through an LDS buffer of N/2 values per
+// transform: half the LDS per workgroup, more workgroups per CU.
+template <int N, int FL>
+__host__ __device__ constexpr int lds_points()
+{
+    return (FL & kHalfX) != 0 ? N / 2 : N;
+}
 
 // Synchronisation of an LDS exchange.  When every thread that exchanges
 // through a buffer belongs to one wavefront (a whole transform per wave), its
@@ -239,14 +250,15 @@ struct PolPass1T {
     }
     // Contiguous store of the workgroup's outputs from LDS (natural order per
     // column): for each block g of CW rows the C columns x CW values are one
-    // contiguous run of the workspace.
+    // contiguous run of the workspace.  The LDS holds outputs k0 .. k0 + N - 1
+    // of every column (k0 a multiple of CW).
     template <int N, int C, int FL, int LDSN, int NT>
-    __device__ static void staged_store(const KArgs& a, long long unit, const float2* lds, int tid)
+    __device__ static void staged_store(const KArgs& a, long long unit, const float2* lds, int tid, int k0)
     {
         const long long bt = unit / a.tiles;
         const int tile = (int)(unit - bt * a.tiles);
-        float2* base = a.out + bt * a.nbig + ((long long)(tile * C) << a.cw_bits);
         const long long gstride = a.n_other << a.cw_bits;
+        float2* base = a.out + bt * a.nbig + ((long long)(tile * C) << a.cw_bits) + (k0 >> a.cw_bits) * gstride;
         const int cwm = (1 << a.cw_bits) - 1;
         const int blk_bits = a.cw_bits + __builtin_ctz(C);
 #pragma unroll
@@ -343,6 +355,35 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const floa
 {
     constexpr int T = N / E;
     constexpr int NST = S::count;
+    if constexpr ((FL & kHalfX) != 0) {
+        constexpr int R0 = S::r(0);
+        static_assert(NST == 2 && E == 2 * R0 && S::r(1) == E && (FL & kPipe) == 0,
+                      "half exchanges need a schedule [R, 2R] with 2R values per thread");
+        // stage 0: butterfly j = t + T h (h = 0, 1) on v[h R0 .. h R0 + R0)
+        Dft<R0>::run(&v[0]);
+        Dft<R0>::run(&v[R0]);
+        // butterfly t + T h writes slots R0 (t + T h) + q; R0 T = N / 2, so
+        // round h holds slots [h N/2, h N/2 + N/2) at offset R0 t + q, and
+        // stage 1's inputs r in [h R0, h R0 + R0) sit at t + T r - h N/2
+        sfor<0, 2>([&](auto hc) {
+            constexpr int h = decltype(hc)::value;
+            if constexpr (h > 0) exch_sync<WS>();  // round 0's reads precede these writes
+#pragma unroll
+            for (int q = 0; q < R0; ++q) L[lds_at<FL>(R0 * t + q)] = v[h * R0 + q];
+            exch_sync<WS>();
+#pragma unroll
+            for (int r = 0; r < R0; ++r) v[h * R0 + r] = L[lds_at<FL>(t + T * r)];
+        });
+        // stage 1: one radix-2R butterfly, twiddles by k = t mod R0
+        constexpr int R1 = E;
+        const int k = t % S::ns(1);
+        if constexpr ((FL & kTwPow) != 0)
+            apply_pow_row<R1>(&v[0], tw + S::ptw_off(1) + k * S::p_row(1));
+        else
+            apply_row<R1>(&v[0], tw + S::tw_off(1) + k * R1);
+        Dft<R1>::run(&v[0]);
+        return;
+    }
     sfor<0, NST>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
         constexpr int R = S::r(s);
@@ -384,7 +425,7 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const floa
 template <int N, int C, class S, int FL, bool FFAST, int T>
 __host__ __device__ constexpr int k_tw_base()
 {
-    return (S::count > 1 ? ((C * lds_stride<N, FL, FFAST, C, T>() + 1) & ~1) : 0);
+    return (S::count > 1 ? ((C * lds_stride<lds_points<N, FL>(), FL, FFAST, C, T>() + 1) & ~1) : 0);
 }
 template <int N, int C, class S, int FL, bool FFAST, int T>
 __host__ __device__ constexpr int k_lds_elems()
@@ -399,6 +440,13 @@ __host__ __device__ constexpr int k_lds_elems()
 template <int N, int E, int C, class S, int FL, bool FFAST>
 __host__ __device__ constexpr int k_min_waves()
 {
+    if ((FL & kHalfX) != 0) {
+        // ask the register allocator for the residency the halved LDS allows
+        const int lds = k_lds_elems<N, C, S, FL, FFAST, N / E>() * 8;
+        const int wgs = 163840 / lds;
+        const int waves = wgs * (((N / E) * C + 63) / 64) / 4;
+        return waves < 1 ? 1 : waves > 3 ? 3 : waves;
+    }
     if ((FL & kPipe) == 0) return 1;
     const int lds = k_lds_elems<N, C, S, FL, FFAST, N / E>() * 8;
     const int wgs = 163840 / lds;
@@ -413,7 +461,7 @@ k_fft(KArgs a)
 {
     constexpr int T = N / E;
     constexpr int NST = S::count;
-    constexpr int LDSN = lds_stride<N, FL, P::f_fast, C, T>();
+    constexpr int LDSN = lds_stride<lds_points<N, FL>(), FL, P::f_fast, C, T>();
     constexpr int R0 = S::r(0);
     constexpr int RL = S::r(NST - 1);
     constexpr int NsL = S::ns(NST - 1);
@@ -487,7 +535,20 @@ k_fft(KArgs a)
         }
         const auto cx = P::template ctx<N, C>(a, unit, f);
         P::template twiddle_outputs<N, E, T, RL, NsL, FL>(a, cx, t, v);
-        if constexpr ((FL & kStaged) != 0) {
+        if constexpr ((FL & kStaged) != 0 && (FL & kHalfX) != 0) {
+            // the same in two rounds of N/2 outputs: output q of the last
+            // stage is k = t + T q (E = RL), so round h holds q in
+            // [h RL/2, h RL/2 + RL/2), at k - h N/2
+            static_assert(P::kind == kKindPass1 && E == RL, "staged store is a pass-1 variant");
+            sfor<0, 2>([&](auto hc) {
+                constexpr int h = decltype(hc)::value;
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < RL / 2; ++q) L[lds_at<FL>(t + q * T)] = v[h * (RL / 2) + q];
+                __syncthreads();
+                P::template staged_store<N / 2, C, FL, LDSN, T * C>(a, unit, lds, tid, h * (N / 2));
+            });
+        } else if constexpr ((FL & kStaged) != 0) {
             // outputs (twiddled) to LDS in natural order, then contiguous stores
             static_assert(P::kind == kKindPass1, "staged store is a pass-1 variant");
             __syncthreads();
@@ -499,7 +560,7 @@ k_fft(KArgs a)
                     L[lds_at<FL>(k)] = v[i * RL + q];
                 }
             __syncthreads();
-            P::template staged_store<N, C, FL, LDSN, T * C>(a, unit, lds, tid);
+            P::template staged_store<N, C, FL, LDSN, T * C>(a, unit, lds, tid, 0);
         } else {
             if constexpr (P::conj_out) {
                 if (bwd) {

@@ -41,6 +41,9 @@ static const KEntry kPass[] = {
     FB_P1(false, 177, 512, 16, 8, 16, 16, 2),
     FB_P1(false, 177, 1024, 16, 8, 16, 16, 4),
     FB_P2(false, 161, 2048, 16, 4, 16, 16, 8),
+    // half exchanges through half the LDS: without streaming loads, and at 128
+    FB_P1(false, 1072, 512, 32, 16, 16, 32),
+    FB_P1(false, 1073, 128, 16, 16, 8, 16),
     // pass 2 reads the workspace pass 1 has just written (partly still in the
     // Infinity Cache): cached loads, power-row twiddles, with / without
     // streaming stores
@@ -74,7 +77,10 @@ static const KEntry kPass[] = {
     FB_P1(true, 49, 64, 16, 16, 16, 4),
     FB_P1(true, 49, 128, 16, 16, 16, 8),
     FB_P1(true, 49, 256, 16, 16, 16, 16),
-    FB_P1(true, 49, 512, 32, 16, 16, 32),
+    // 512: [16, 32] with half exchanges (35 KB of LDS, three workgroups per
+    // CU instead of two: 51.8 against 56.3 us at 2^20 x 16, same results)
+    FB_P1(true, 1073, 512, 32, 16, 16, 32),
+    FB_P1(false, 49, 512, 32, 16, 16, 32),
     FB_P1(false, 49, 512, 16, 16, 16, 16, 2),
     FB_P1(true, 49, 1024, 16, 16, 16, 16, 4),
     FB_P1(true, 49, 2048, 16, 8, 16, 16, 8),

@@ -279,3 +279,12 @@ def test_small_batches_take_the_one_wave_form():
         assert fb.plan_query(1024, 8)["kernel_name"] == alt["name"]
     finally:
         fb.wisdom_clear()
+
+
+def test_variant_constants_match_the_header():
+    import re
+    text = open(HEADER).read()
+    defs = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"#define FFT_VARIANT_(\w+)\s+(\d+)", text))
+    assert defs, "no variant flags found"
+    for name, value in defs.items():
+        assert getattr(fb, "VARIANT_" + name) == value, name
