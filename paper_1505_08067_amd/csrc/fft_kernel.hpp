@@ -34,13 +34,17 @@
 
 namespace fb {
 
-enum : int { kSwz = 8, kStaged = 16, kTwPow = 32, kXcd = 128, kStageStride = 256, kWaveSync = 512, kHalfX = 1024 };
+enum : int {
+    kSwz = 8, kStaged = 16, kTwPow = 32, kXcd = 128, kStageStride = 256, kWaveSync = 512, kHalfX = 1024,
+    kFitRegs = 2048  // with kHalfX: registers fitted to every workgroup the halved LDS allows
+};
 
-// Half exchanges (kHalfX): two-stage schedules [R, 2R] with E = 2R values per
-// thread.  Stage 0's two butterflies per thread write exactly the two halves
-// of the slots that stage 1 reads, so the exchange (and the staged store of
-// pass 1) can run in two rounds through an LDS buffer of N/2 values per
-// transform: half the LDS per workgroup, more workgroups per CU.
+// Half exchanges (kHalfX): when every stage but the last runs an even number
+// of butterflies per thread, the butterflies of one half write exactly the
+// slots that hold one half of every input of the next stage, so each
+// exchange (and the staged store of pass 1) runs in two rounds through an
+// LDS buffer of N/2 values per transform: half the LDS per workgroup, more
+// workgroups per CU.
 template <int N, int FL>
 __host__ __device__ constexpr int lds_points()
 {
@@ -355,44 +359,18 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const floa
 {
     constexpr int T = N / E;
     constexpr int NST = S::count;
-    if constexpr ((FL & kHalfX) != 0) {
-        constexpr int R0 = S::r(0);
-        static_assert(NST == 2 && E == 2 * R0 && S::r(1) == E && (FL & kPipe) == 0,
-                      "half exchanges need a schedule [R, 2R] with 2R values per thread");
-        // stage 0: butterfly j = t + T h (h = 0, 1) on v[h R0 .. h R0 + R0)
-        Dft<R0>::run(&v[0]);
-        Dft<R0>::run(&v[R0]);
-        // butterfly t + T h writes slots R0 (t + T h) + q; R0 T = N / 2, so
-        // round h holds slots [h N/2, h N/2 + N/2) at offset R0 t + q, and
-        // stage 1's inputs r in [h R0, h R0 + R0) sit at t + T r - h N/2
-        sfor<0, 2>([&](auto hc) {
-            constexpr int h = decltype(hc)::value;
-            if constexpr (h > 0) exch_sync<WS>();  // round 0's reads precede these writes
-#pragma unroll
-            for (int q = 0; q < R0; ++q) L[lds_at<FL>(R0 * t + q)] = v[h * R0 + q];
-            exch_sync<WS>();
-#pragma unroll
-            for (int r = 0; r < R0; ++r) v[h * R0 + r] = L[lds_at<FL>(t + T * r)];
-        });
-        // stage 1: one radix-2R butterfly, twiddles by k = t mod R0
-        constexpr int R1 = E;
-        const int k = t % S::ns(1);
-        if constexpr ((FL & kTwPow) != 0)
-            apply_pow_row<R1>(&v[0], tw + S::ptw_off(1) + k * S::p_row(1));
-        else
-            apply_row<R1>(&v[0], tw + S::tw_off(1) + k * R1);
-        Dft<R1>::run(&v[0]);
-        return;
-    }
+
     sfor<0, NST>([&](auto sc) {
         constexpr int s = decltype(sc)::value;
         constexpr int R = S::r(s);
         constexpr int Ns = S::ns(s);
         if constexpr (s > 0) {
+            if constexpr ((FL & kHalfX) == 0) {
 #pragma unroll
-            for (int i = 0; i < E / R; ++i)
+                for (int i = 0; i < E / R; ++i)
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[i * R + r] = L[lds_at<FL>(t + i * T + r * (N / R))];
+                    for (int r = 0; r < R; ++r) v[i * R + r] = L[lds_at<FL>(t + i * T + r * (N / R))];
+            }  // half exchanges read this stage's inputs during the exchange itself
 #pragma unroll
             for (int i = 0; i < E / R; ++i) {
                 const int k = (t + i * T) % Ns;
@@ -406,7 +384,7 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const floa
         }
 #pragma unroll
         for (int i = 0; i < E / R; ++i) Dft<R>::run(&v[i * R]);
-        if constexpr (s < NST - 1) {
+        if constexpr (s < NST - 1 && (FL & kHalfX) == 0) {
             if constexpr (s > 0) exch_sync<WS>();
 #pragma unroll
             for (int i = 0; i < E / R; ++i) {
@@ -416,6 +394,37 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const floa
                 for (int q = 0; q < R; ++q) L[lds_at<FL>(base + q * Ns)] = v[i * R + q];
             }
             exch_sync<WS>();
+        } else if constexpr (s < NST - 1) {
+            // Half exchange through N/2 slots.  Butterfly i of this stage
+            // (j = t + i T) writes slots Ns (R (j / Ns) + q) + j mod Ns, which
+            // lie in the upper half exactly when j >= N / 2R, i.e. i >= E / 2R;
+            // the next stage's input r of its butterfly i2 sits at slot
+            // t + i2 T + r N / R2, in the upper half exactly when r >= R2 / 2.
+            // Round h writes butterflies [h E/2R, (h+1) E/2R) and reads the
+            // inputs r in [h R2/2, (h+1) R2/2) of every butterfly.
+            constexpr int R2 = S::r(s + 1);
+            static_assert(E % (2 * R) == 0 && R2 % 2 == 0 && (FL & kPipe) == 0,
+                          "half exchanges need an even number of butterflies per thread");
+            float2 w[E];
+            sfor<0, 2>([&](auto hc) {
+                constexpr int h = decltype(hc)::value;
+                if constexpr (h > 0 || s > 0) exch_sync<WS>();  // earlier reads precede these writes
+#pragma unroll
+                for (int i = h * (E / (2 * R)); i < (h + 1) * (E / (2 * R)); ++i) {
+                    const int j = t + i * T;
+                    const int base = (j / Ns) * Ns * R + (j % Ns) - h * (N / 2);
+#pragma unroll
+                    for (int q = 0; q < R; ++q) L[lds_at<FL>(base + q * Ns)] = v[i * R + q];
+                }
+                exch_sync<WS>();
+#pragma unroll
+                for (int i2 = 0; i2 < E / R2; ++i2)
+#pragma unroll
+                    for (int r = h * (R2 / 2); r < (h + 1) * (R2 / 2); ++r)
+                        w[i2 * R2 + r] = L[lds_at<FL>(t + i2 * T + r * (N / R2) - h * (N / 2))];
+            });
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = w[e];
         }
     });
 }
@@ -445,7 +454,8 @@ __host__ __device__ constexpr int k_min_waves()
         const int lds = k_lds_elems<N, C, S, FL, FFAST, N / E>() * 8;
         const int wgs = 163840 / lds;
         const int waves = wgs * (((N / E) * C + 63) / 64) / 4;
-        return waves < 1 ? 1 : waves > 3 ? 3 : waves;
+        const int cap = (FL & kFitRegs) != 0 ? 8 : 3;
+        return waves < 1 ? 1 : waves > cap ? cap : waves;
     }
     if ((FL & kPipe) == 0) return 1;
     const int lds = k_lds_elems<N, C, S, FL, FFAST, N / E>() * 8;
@@ -501,6 +511,7 @@ k_fft(KArgs a)
     };
     auto finish = [&](float2(&v)[E], long long unit) {
         run_stages<N, E, S, FL, WS>(v, L, a.tw, Ltw, t);
+        static_assert(P::kind != kKindFilter || (FL & kHalfX) == 0, "the filter's round trip needs N slots");
         if constexpr (P::kind == kKindFilter) {
             // Z = X conj(H) is transformed back as conj(F(conj Z)), and
             // conj Z = conj(X) H: X[k] sits at v[i RL + q], k = t + i T + q NsL.
@@ -536,15 +547,18 @@ k_fft(KArgs a)
         const auto cx = P::template ctx<N, C>(a, unit, f);
         P::template twiddle_outputs<N, E, T, RL, NsL, FL>(a, cx, t, v);
         if constexpr ((FL & kStaged) != 0 && (FL & kHalfX) != 0) {
-            // the same in two rounds of N/2 outputs: output q of the last
-            // stage is k = t + T q (E = RL), so round h holds q in
-            // [h RL/2, h RL/2 + RL/2), at k - h N/2
-            static_assert(P::kind == kKindPass1 && E == RL, "staged store is a pass-1 variant");
+            // the same in two rounds of N/2 outputs: output (i, q) of the last
+            // stage is k = t + i T + q NsL, in the upper half exactly when
+            // q >= RL / 2; round h stores those at k - h N/2
+            static_assert(P::kind == kKindPass1 && RL % 2 == 0, "staged store is a pass-1 variant");
             sfor<0, 2>([&](auto hc) {
                 constexpr int h = decltype(hc)::value;
                 __syncthreads();
 #pragma unroll
-                for (int q = 0; q < RL / 2; ++q) L[lds_at<FL>(t + q * T)] = v[h * (RL / 2) + q];
+                for (int i = 0; i < E / RL; ++i)
+#pragma unroll
+                    for (int q = h * (RL / 2); q < (h + 1) * (RL / 2); ++q)
+                        L[lds_at<FL>(t + i * T + q * NsL - h * (N / 2))] = v[i * RL + q];
                 __syncthreads();
                 P::template staged_store<N / 2, C, FL, LDSN, T * C>(a, unit, lds, tid, h * (N / 2));
             });

@@ -41,9 +41,13 @@ static const KEntry kPass[] = {
     FB_P1(false, 177, 512, 16, 8, 16, 16, 2),
     FB_P1(false, 177, 1024, 16, 8, 16, 16, 4),
     FB_P2(false, 161, 2048, 16, 4, 16, 16, 8),
-    // half exchanges through half the LDS: without streaming loads, and at 128
+    // half exchanges through half the LDS: without streaming loads, and at
+    // 128; pass 2 at 2048 with 32 values per thread and registers fitted to
+    // two workgroups per CU (a few spilled): 52.4 against 53.0 us, within
+    // the run-to-run spread, so not the default
     FB_P1(false, 1072, 512, 32, 16, 16, 32),
     FB_P1(false, 1073, 128, 16, 16, 8, 16),
+    FB_P2(false, 3106, 2048, 32, 8, 16, 16, 8),
     // pass 2 reads the workspace pass 1 has just written (partly still in the
     // Infinity Cache): cached loads, power-row twiddles, with / without
     // streaming stores
@@ -82,7 +86,10 @@ static const KEntry kPass[] = {
     FB_P1(true, 1073, 512, 32, 16, 16, 32),
     FB_P1(false, 49, 512, 32, 16, 16, 32),
     FB_P1(false, 49, 512, 16, 16, 16, 16, 2),
-    FB_P1(true, 49, 1024, 16, 16, 16, 16, 4),
+    // 1024: 32 values per thread with half exchanges (65.9 against 69.6 us
+    // at 2^20 x 16, one workgroup per CU either way)
+    FB_P1(true, 1073, 1024, 32, 16, 16, 16, 4),
+    FB_P1(false, 49, 1024, 16, 16, 16, 16, 4),
     FB_P1(true, 49, 2048, 16, 8, 16, 16, 8),
     // pass 2: cached loads of the workspace pass 1 has just written (partly
     // still in the Infinity Cache), streaming stores of the result
