@@ -36,6 +36,8 @@ static const KEntry kBlock[] = {
     FB_BLK(false, 35, 8192, 32, 1, 16, 32, 16),
     FB_BLK(false, 35, 8192, 32, 1, 32, 8, 32),
     FB_BLK(false, 35, 16384, 32, 1, 32, 16, 32),
+    // half exchanges at 4096 (eight workgroups per CU instead of four): no gain
+    FB_BLK(false, 1059, 4096, 32, 1, 16, 16, 16),
     // eight values per thread: twice the waves per workgroup at the same LDS
     FB_BLK(false, 35, 8192, 8, 1, 8, 8, 8, 8, 2),
     FB_BLK(false, 35, 2048, 8, 2, 8, 8, 4, 8),
@@ -90,9 +92,15 @@ static const KEntry kBlock[] = {
     FB_BLK(false, 35, 1024, 8, 2, 8, 8, 4, 4),
     FB_BLK(true, 35, 2048, 16, 2, 16, 16, 8),
     FB_BLK(true, 35, 4096, 16, 1, 16, 16, 16),
-    FB_BLK(true, 43, 8192, 16, 1, 8, 8, 8, 16),
+    // 8192 and 16384: 32 values per thread with half exchanges, so the LDS
+    // of a workgroup halves (8192: four workgroups per CU instead of two,
+    // 97 against 102 us for 2^25 points; 16384: two instead of one, 107
+    // against 118 us)
+    FB_BLK(true, 1059, 8192, 32, 1, 8, 8, 8, 16),
+    FB_BLK(false, 43, 8192, 16, 1, 8, 8, 8, 16),
     FB_BLK(false, 35, 8192, 16, 1, 8, 8, 8, 16),
-    FB_BLK(true, 35, 16384, 16, 1, 16, 4, 16, 16),
+    FB_BLK(true, 1059, 16384, 32, 1, 16, 4, 16, 16),
+    FB_BLK(false, 35, 16384, 16, 1, 16, 4, 16, 16),
     FB_BLK(false, 35, 16384, 16, 1, 16, 16, 16, 4),
     // mixed-radix lengths (radix 3 and 5 butterflies and their products)
     FB_BLK(true, 0, 3, 3, 64, 3),

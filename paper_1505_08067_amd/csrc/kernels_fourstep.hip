@@ -86,10 +86,10 @@ static const KEntry kPass[] = {
     FB_P1(true, 1073, 512, 32, 16, 16, 32),
     FB_P1(false, 49, 512, 32, 16, 16, 32),
     FB_P1(false, 49, 512, 16, 16, 16, 16, 2),
-    // 1024: 32 values per thread with half exchanges (65.9 against 69.6 us
-    // at 2^20 x 16, one workgroup per CU either way)
-    FB_P1(true, 1073, 1024, 32, 16, 16, 16, 4),
-    FB_P1(false, 49, 1024, 16, 16, 16, 16, 4),
+    FB_P1(true, 49, 1024, 16, 16, 16, 16, 4),
+    // 32 values per thread with half exchanges: faster at 2^20 (1024 x 1024:
+    // 65.9 against 69.6 us), slower at 2^21 (1024 x 2048: 71 against 67 us)
+    FB_P1(false, 1073, 1024, 32, 16, 16, 16, 4),
     FB_P1(true, 49, 2048, 16, 8, 16, 16, 8),
     // pass 2: cached loads of the workspace pass 1 has just written (partly
     // still in the Infinity Cache), streaming stores of the result

@@ -21,8 +21,8 @@ static const KEntry kList[] = {
     FB_LST(35, 1024, 16, 4, 16, 16, 4),
     FB_LST(35, 2048, 16, 2, 16, 16, 8),
     FB_LST(35, 4096, 16, 1, 16, 16, 16),
-    FB_LST(43, 8192, 16, 1, 8, 8, 8, 16),
-    FB_LST(35, 16384, 16, 1, 16, 4, 16, 16),
+    FB_LST(1059, 8192, 32, 1, 8, 8, 8, 16),
+    FB_LST(1059, 16384, 32, 1, 16, 4, 16, 16),
     FB_LST(0, 3, 3, 64, 3),
     FB_LST(0, 5, 5, 64, 5),
     FB_LST(0, 6, 6, 64, 6),
