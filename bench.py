@@ -612,8 +612,8 @@ def run_ragged(torch, fb, inputs, stream):
     y = torch.empty_like(x)
     sh = stream.cuda_stream
 
-    def timed(fn, reps=10):
-        for _ in range(2):
+    def timed(fn, reps=10, warm=2):
+        for _ in range(warm):
             fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -634,8 +634,9 @@ def run_ragged(torch, fb, inputs, stream):
         t_plain += t
         at += n * c
     with fb.Ragged(classes, fb.FORWARD) as r:
-        t_graph = timed(lambda: r.execute(x, out=y))
-        t_seq = timed(lambda: r.execute(x, out=y, graph=False))
+        # the first launches of a freshly captured graph run slower: warm it up
+        t_graph = timed(lambda: r.execute(x, out=y), reps=20, warm=10)
+        t_seq = timed(lambda: r.execute(x, out=y, graph=False), reps=20, warm=10)
         nodes = r.describe()["graph_nodes"]
     fl = sum(5.0 * n * math.log2(n) * c for n, c in classes)
     res = {
