@@ -194,8 +194,11 @@ typedef struct {
 #define FFT_VARIANT_XCD_ORDER 128     /* work units ordered so neighbours share an XCD (and its L2) */
 #define FFT_VARIANT_STAGE_STRIDE 256  /* four-step pass 1: LDS stride residue for the staged store */
 #define FFT_VARIANT_WAVE_SYNC 512     /* one transform per wavefront: exchanges without workgroup barriers */
-#define FFT_VARIANT_HALF_EXCHANGE 1024 /* schedules [R, 2R] with 2R values per thread: exchanges (and the
-                                          pass-1 staged store) in two rounds through half the LDS */
+#define FFT_VARIANT_HALF_EXCHANGE 1024 /* every stage but the last runs an even number of butterflies
+                                          per thread: exchanges (and the pass-1 staged store) in two
+                                          rounds through half the LDS */
+#define FFT_VARIANT_FIT_REGISTERS 2048 /* with HALF_EXCHANGE: registers fitted to every workgroup the
+                                          halved LDS allows, spilling if need be */
 
 /* Storage of the transform data (fft_plan_opts_t.storage). */
 #define FFT_STORAGE_C64 0   /* interleaved FP32 (re, im), 8 bytes per value */
