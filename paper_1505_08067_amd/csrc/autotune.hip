@@ -415,7 +415,7 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
         for (int r = 0; r < t[i].nr; ++r) o.radix[r] = t[i].radix[r];
         o.flags = t[i].flags;
         o.c = t[i].c;
-        o.block_limit = 16384;
+        o.block_limit = kMaxBlockLen;
         fft_plan_t p = nullptr;
         fft_status_t st = fft_plan_create_ex(n, batch, FFT_FORWARD, &o, &p);
         if (st != FFT_SUCCESS) continue;

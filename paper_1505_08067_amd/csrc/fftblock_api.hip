@@ -271,13 +271,21 @@ size_t env_size(const char* name, size_t dflt)
 }
 
 constexpr size_t kMaxN = size_t(1) << 22;
-constexpr size_t kDefaultBlockLimit = 16384;
+// Longest single block: with half exchanges 32768 points fit the LDS of one
+// workgroup (16384 exchange slots).
+constexpr size_t kDefaultBlockLimit = kMaxBlockLen;
+// Blocks longer than this take a whole compute unit's LDS per transform, so a
+// batch below kLongBlockMinBatch leaves most of the device idle; the default
+// plan then takes the four-step path, which spreads each transform over many
+// workgroups.  An explicit block limit in the options overrides this.
+constexpr size_t kLongBlock = 16384;
+constexpr size_t kLongBlockMinBatch = 64;
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 size_t sanitize_limit(size_t lim)
 {
-    if (!is_pow2(lim) || lim < 1024 || lim > kDefaultBlockLimit) return kDefaultBlockLimit;
+    if (!is_pow2(lim) || lim < 1024 || lim > kMaxBlockLen) return kDefaultBlockLimit;
     return lim;
 }
 
@@ -418,7 +426,7 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
     if (n == 0 || batch == 0) return FFT_ERR_INVALID_ARG;
     if (direction != FFT_FORWARD && direction != FFT_BACKWARD) return FFT_ERR_INVALID_ARG;
     if (n > kMaxN) return FFT_ERR_UNSUPPORTED_SIZE;
-    if (!is_pow2(n) && (n > kDefaultBlockLimit || !kernel_default(kKindBlock, (int)n, 0, 0)))
+    if (!is_pow2(n) && (n > kLongBlock || !kernel_default(kKindBlock, (int)n, 0, 0)))
         return FFT_ERR_UNSUPPORTED_SIZE;  // other lengths: the compiled mixed-radix blocks only
     if (batch > ((size_t)1 << 40) / n) return FFT_ERR_INVALID_ARG;
     fft_plan_opts_t o;
@@ -438,7 +446,7 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
     p->segs.clear();
     if (n == 1) {
         p->path = FFT_PATH_BLOCK;
-    } else if (n <= limit || !is_pow2(n)) {
+    } else if ((n <= limit && (n <= kLongBlock || batch >= kLongBlockMinBatch || o.block_limit)) || !is_pow2(n)) {
         p->path = FFT_PATH_BLOCK;
         if (o.n_radix == 0 && o.flags < 0 && o.c <= 0) {
             p->k1 = sto ? nullptr : wisdom_kernel(n);
@@ -715,7 +723,7 @@ static fft_status_t filter_choose(size_t n, size_t batch, size_t replica_len, co
     fft_plan_opts_init(&o);
     if (opts) o = *opts;
     if (o.storage != 0 || o.n_radix < 0 || o.n_radix > 8) return FFT_ERR_INVALID_ARG;
-    if (n > (size_t)kDefaultBlockLimit) return FFT_ERR_UNSUPPORTED_SIZE;
+    if (n > kLongBlock) return FFT_ERR_UNSUPPORTED_SIZE;
     p->n = n;
     p->batch = batch;
     p->direction = FFT_FORWARD;

@@ -10,6 +10,9 @@ struct fft_plan_s;
 
 namespace fb {
 
+// Longest length one workgroup transforms from LDS (the block path's limit).
+constexpr size_t kMaxBlockLen = 32768;
+
 // Arguments shared by every transform kernel (one struct so all launchers
 // have the same signature).
 struct KArgs {

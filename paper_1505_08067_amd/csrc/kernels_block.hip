@@ -38,6 +38,9 @@ static const KEntry kBlock[] = {
     FB_BLK(false, 35, 16384, 32, 1, 32, 16, 32),
     // half exchanges at 4096 (eight workgroups per CU instead of four): no gain
     FB_BLK(false, 1059, 4096, 32, 1, 16, 16, 16),
+    // other 32768 schedules (half exchanges)
+    FB_BLK(false, 1059, 32768, 32, 1, 16, 16, 8, 16),
+    FB_BLK(false, 1059, 32768, 32, 1, 8, 16, 16, 16),
     // eight values per thread: twice the waves per workgroup at the same LDS
     FB_BLK(false, 35, 8192, 8, 1, 8, 8, 8, 8, 2),
     FB_BLK(false, 35, 2048, 8, 2, 8, 8, 4, 8),
@@ -61,6 +64,7 @@ static const KEntry kBlock[] = {
     FB_BLKH(false, 107, 8192, 16, 1, 8, 8, 8, 16),
     FB_BLKH(true, 1123, 16384, 32, 1, 16, 4, 16, 16),
     FB_BLKH(false, 99, 16384, 16, 1, 16, 4, 16, 16),
+    FB_BLKH(true, 1123, 32768, 32, 1, 16, 8, 16, 16),
     FB_BLKH(true, 64, 3, 3, 64, 3),
     FB_BLKH(true, 64, 5, 5, 64, 5),
     FB_BLKH(true, 64, 6, 6, 64, 6),
@@ -106,6 +110,10 @@ static const KEntry kBlock[] = {
     FB_BLK(true, 1059, 16384, 32, 1, 16, 4, 16, 16),
     FB_BLK(false, 35, 16384, 16, 1, 16, 4, 16, 16),
     FB_BLK(false, 35, 16384, 16, 1, 16, 16, 16, 4),
+    // 32768 in one workgroup: half exchanges need 16384 LDS slots (128 KiB),
+    // one workgroup per CU; 141 against 179 us (four-step 256 x 128) for
+    // 2^25 points
+    FB_BLK(true, 1059, 32768, 32, 1, 16, 8, 16, 16),
     // mixed-radix lengths (radix 3 and 5 butterflies and their products)
     FB_BLK(true, 0, 3, 3, 64, 3),
     FB_BLK(false, 35, 3, 3, 64, 3),

@@ -844,7 +844,12 @@ fft_status_t fft_server_submit(fft_server_t s, size_t n, size_t batch, int direc
     if (!ticket || !in || ((uintptr_t)in & 7u) || n == 0 || batch == 0) return FFT_ERR_INVALID_ARG;
     if (direction != FFT_FORWARD && direction != FFT_BACKWARD) return FFT_ERR_INVALID_ARG;
     fft_plan_desc_t d;
-    fft_status_t st = fft_plan_query(n, batch, direction, &d);
+    fft_status_t st = fft_plan_query(n, batch, direction, &d);   // validates the batch
+    if (st != FFT_SUCCESS) return st;
+    // the path of the server's own plan for n (created at batch 1, as in
+    // get_plan): a length whose default plan depends on the batch is served
+    // the way a single request would be
+    st = fft_plan_query(n, 1, direction, &d);
     if (st != FFT_SUCCESS) return st;
     const bool four = d.path == FFT_PATH_FOURSTEP;
     const size_t bytes = n * batch * sizeof(float2) * (four ? 3 : 2);  // in + out (+ workspace)

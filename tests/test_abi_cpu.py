@@ -77,11 +77,13 @@ def test_block_max_other_sizes():
 
 def test_plan_query_block_and_fourstep():
     limit = fb.block_limit()
-    assert limit == 16384
+    assert limit == 32768
     for L in range(1, 23):
         n = 1 << L
         d = fb.plan_query(n, 3)
-        if n <= limit:
+        # 32768 fills one compute unit per transform: three transforms go
+        # four-step, 64 or more take the single block
+        if n <= 16384:
             assert d["path"] == fb.PATH_BLOCK and d["kernels_per_execute"] == 1
             assert math.prod(d["radix"]) == n
             assert d["workspace_bytes"] == 0
@@ -94,6 +96,15 @@ def test_plan_query_block_and_fourstep():
             assert math.prod(d["radix"]) == d["n1"] and math.prod(d["radix2"]) == d["n2"]
             assert d["workspace_bytes"] == 8 * n * 3
             assert d["lds_bytes"] <= 160 * 1024
+    for batch, path in ((63, fb.PATH_FOURSTEP), (64, fb.PATH_BLOCK), (1024, fb.PATH_BLOCK)):
+        d = fb.plan_query(limit, batch)
+        assert d["path"] == path, batch
+        if path == fb.PATH_BLOCK:
+            assert math.prod(d["radix"]) == limit and d["workspace_bytes"] == 0
+            assert d["lds_bytes"] <= 160 * 1024 and d["threads_per_block"] == limit // 32
+    # an explicit block limit keeps the single block at any batch
+    assert fb.plan_query(limit, 1, opts=fb.make_opts(block_limit=limit))["path"] == fb.PATH_BLOCK
+    assert fb.plan_query(limit, 1024, opts=fb.make_opts(block_limit=16384))["path"] == fb.PATH_FOURSTEP
     d = fb.plan_query(1 << 20, 16)
     assert (d["n1"], d["n2"]) == (512, 2048)
     d = fb.plan_query(1 << 20, 16, opts=fb.make_opts(n1=1024))
@@ -163,6 +174,8 @@ def test_fp16_storage_planning_without_device():
         d = fb.plan_query(n, 3, opts=fb.make_opts(storage=fb.STORAGE_F16))
         assert d["storage"] == 1 and "_f16" in d["kernel_name"], n
         assert d["flags"] & fb.VARIANT_FP16_STORAGE
+    d = fb.plan_query(32768, 64, opts=fb.make_opts(storage=fb.STORAGE_F16))
+    assert d["path"] == fb.PATH_BLOCK and "_f16" in d["kernel_name"]
     for L in (15, 20, 22):
         d = fb.plan_query(1 << L, 1, opts=fb.make_opts(storage=fb.STORAGE_F16))
         assert d["path"] == fb.PATH_FOURSTEP

@@ -210,7 +210,8 @@ def test_device_query_and_block_limit():
     assert info["warp_size"] == 64
     assert info["lds_per_cu"] == 160 * 1024
     assert info["block_max"] == [16384, 8192, 4096]
-    assert fb.block_limit() <= info["block_max"][0]
+    # half exchanges hold half the points in LDS: twice the analytic limit
+    assert fb.block_limit() <= 2 * info["block_max"][0]
 
 
 def test_errors_on_device():

@@ -137,8 +137,10 @@ def test_replay_short_poisson_stream_pooled_and_plain():
 
 def test_server_edge_lengths():
     # n = 1 (a copy), a mixed-radix length through its list kernel, the
-    # longest four-step length with its workspace from the arena
-    cases = [(1, 5, -1), (6000, 3, 1), (1 << 22, 2, -1), (3, 7, 1)]
+    # longest four-step length with its workspace from the arena, and 32768
+    # at a batch whose own plan would be a single block (served as the
+    # server's batch-1 plan: four-step, workspace included)
+    cases = [(1, 5, -1), (6000, 3, 1), (1 << 22, 2, -1), (3, 7, 1), (1 << 15, 80, 1)]
     data = [torch.from_numpy(inputs.uniform(3000 + i, b, n)).to("cuda") for i, (n, b, _) in enumerate(cases)]
     with sv.Server(hbm_budget=1 << 30) as srv:
         tickets = [srv.submit(data[i], n, b, d) for i, (n, b, d) in enumerate(cases)]

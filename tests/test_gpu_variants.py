@@ -48,7 +48,8 @@ def test_block_variant(k):
         batch = max(batch, (1 << 24) // n + 3)   # more units than resident workgroups
     fp16 = bool(k["flags"] & fb.VARIANT_FP16_STORAGE)
     opts = fb.make_opts(radix=k["radix"], flags=k["flags"], c=k["c"],
-                        storage=fb.STORAGE_F16 if fp16 else fb.STORAGE_C64)
+                        storage=fb.STORAGE_F16 if fp16 else fb.STORAGE_C64,
+                        block_limit=n if n > 16384 else 0)   # at any batch
     x = inputs.uniform(300 + n, batch, n)
     for sign in (fb.FORWARD, fb.BACKWARD):
         say(f"{k['name']} batch={batch} sign={sign}")
