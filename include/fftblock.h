@@ -63,7 +63,7 @@ typedef enum {
 #define FFT_BACKWARD (+1)
 
 /* Execution path chosen by the planner. */
-#define FFT_PATH_BLOCK 1      /* one LDS-resident block per transform (N <= block limit) */
+#define FFT_PATH_BLOCK 1      /* one LDS-resident block per transform (N <= block limit 32768) */
 #define FFT_PATH_FOURSTEP 2   /* two block passes, N = N1 * N2 */
 #define FFT_PATH_FILTER 3     /* range compression: forward, filter, backward in one block */
 
@@ -75,7 +75,10 @@ typedef enum {
  *              block path covers n <= the LDS block limit, longer lengths
  *              use the four-step path), and the compiled mixed-radix lengths
  *              3, 5, 6, 10, 12, 15, 20, 60, 100, 1000, 3072, 6000 and 15360
- *              (single block).  Other lengths: UNSUPPORTED_SIZE.
+ *              (single block).  Other lengths: UNSUPPORTED_SIZE.  n = 32768
+ *              takes a whole compute unit's LDS per transform: below 64
+ *              transforms it goes four-step unless the options give a block
+ *              limit.
  *   batch      number of transforms per execute (>= 1).  On the block path
  *              the default kernel's width follows it: a batch that would
  *              give the full-width kernel fewer than 128 workgroups runs
@@ -210,7 +213,9 @@ typedef struct {
                                has rms sqrt(2n/3)) */
 
 typedef struct {
-    size_t block_limit;  /* longest single-block length; 0 = fft_block_limit() */
+    size_t block_limit;  /* longest single-block length (power of two, 1024..32768); 0 =
+                            fft_block_limit() with the small-batch rule for 32768 (see
+                            fft_plan_create); nonzero: the single block at every batch */
     int n_radix;         /* schedule of the single block (four-step: of pass 1): 0 = default, else radix[0..n_radix) */
     int radix[8];
     int flags;           /* variant of the block kernel / pass 1; -1 = default */
@@ -328,9 +333,12 @@ fft_status_t fft_device_query(int device, fft_device_info_t* info);
  * k < 1 or nothing fits.  Pure arithmetic, no device needed. */
 size_t fft_block_max(size_t lds_bytes, int k);
 
-/* Largest length the single-block path handles (the block limit the
- * planner uses: analytic, then confirmed by the runtime sweep; the
- * environment variable FFTBLOCK_BLOCK_MAX may lower it). */
+/* Largest length the single-block path handles: 32768, twice the analytic
+ * limit for one workgroup per CU, since the half-exchange kernels stage only
+ * half the points in LDS at a time; the runtime sweep confirms each step
+ * (block faster than four-step at 2048..32768 for large batches).  The
+ * environment variable FFTBLOCK_BLOCK_MAX (power of two, 1024..32768) may
+ * lower it. */
 size_t fft_block_limit(void);
 
 /* ---------------------------------------------------------------------------
