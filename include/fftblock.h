@@ -202,6 +202,8 @@ typedef struct {
                                           rounds through half the LDS */
 #define FFT_VARIANT_FIT_REGISTERS 2048 /* with HALF_EXCHANGE: registers fitted to every workgroup the
                                           halved LDS allows, spilling if need be */
+#define FFT_VARIANT_LOOP 4096         /* persistent workgroups (as many as are resident) looping over
+                                         the units in launch order, without prefetch */
 
 /* Storage of the transform data (fft_plan_opts_t.storage). */
 #define FFT_STORAGE_C64 0   /* interleaved FP32 (re, im), 8 bytes per value */

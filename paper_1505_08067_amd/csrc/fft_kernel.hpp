@@ -36,7 +36,8 @@ namespace fb {
 
 enum : int {
     kSwz = 8, kStaged = 16, kTwPow = 32, kXcd = 128, kStageStride = 256, kWaveSync = 512, kHalfX = 1024,
-    kFitRegs = 2048  // with kHalfX: registers fitted to every workgroup the halved LDS allows
+    kFitRegs = 2048,  // with kHalfX: registers fitted to every workgroup the halved LDS allows
+    kLoop = 4096      // persistent workgroups looping over units, without prefetch
 };
 
 // Half exchanges (kHalfX): when every stage but the last runs an even number
@@ -482,8 +483,8 @@ k_fft(KArgs a)
     __shared__ __attribute__((aligned(16))) float2 lds[k_lds_elems<N, C, S, FL, P::f_fast, T>()];
 
     const int tid = threadIdx.x;
-    const int f = P::f_fast ? tid % C : tid / T;
-    const int t = P::f_fast ? tid / C : tid % T;
+    int f = P::f_fast ? tid % C : tid / T;
+    int t = P::f_fast ? tid / C : tid % T;
     float2* L = lds + (NST > 1 ? f * LDSN : 0);
     float2* Ltw = lds + TWB;
 
@@ -591,7 +592,28 @@ k_fft(KArgs a)
         }
     };
 
-    if constexpr ((FL & kPipe) == 0) {
+    if constexpr ((FL & kLoop) != 0) {
+        static_assert((FL & kPipe) == 0 && (FL & kXcd) == 0, "the loop form takes units in launch order");
+        // One workgroup per resident slot walks units b, b + G, ...: the next
+        // unit's loads issue as soon as this unit's stores are issued, with no
+        // workgroup exit and dispatch in between.
+        const long long units = P::units(a, C);
+        for (long long u = blockIdx.x; u < units; u += gridDim.x) {
+            // the thread's indices are re-derived in every iteration (the
+            // empty asm hides that they repeat), so the many per-thread LDS
+            // and global offsets are not hoisted out of the loop and kept
+            // live across it, which would spill
+            int tl = tid;
+            asm volatile("" : "+v"(tl));
+            f = P::f_fast ? tl % C : tl / T;
+            t = P::f_fast ? tl / C : tl % T;
+            L = lds + (NST > 1 ? f * LDSN : 0);
+            float2 v[E];
+            load(v, u);
+            finish(v, u);
+            __syncthreads();  // the next unit's first LDS writes follow every thread's last LDS reads
+        }
+    } else if constexpr ((FL & kPipe) == 0) {
         float2 v[E];
         long long unit = blockIdx.x;
         if constexpr ((FL & kXcd) != 0) unit = xcd_unit(unit, gridDim.x);

@@ -615,7 +615,7 @@ fft_status_t fft_plan_query(size_t n, size_t batch, int direction, fft_plan_desc
 static long long grid_for(const KEntry* k, const KArgs& a, int cus)
 {
     const long long units = kernel_units(*k, a);
-    if ((k->flags & FFT_VARIANT_PERSISTENT) == 0) return units;
+    if ((k->flags & (FFT_VARIANT_PERSISTENT | FFT_VARIANT_LOOP)) == 0) return units;
     const int occ = k->occupancy ? k->occupancy() : 0;
     const long long cap = (long long)(occ > 0 ? occ : 1) * (cus > 0 ? cus : 1);
     return units < cap ? units : cap;

@@ -41,6 +41,8 @@ static const KEntry kBlock[] = {
     // other 32768 schedules (half exchanges)
     FB_BLK(false, 1059, 32768, 32, 1, 16, 16, 8, 16),
     FB_BLK(false, 1059, 32768, 32, 1, 8, 16, 16, 16),
+    // persistent workgroups looping over units (no prefetch)
+    FB_BLK(false, 4131, 4096, 16, 1, 16, 16, 16),
     // eight values per thread: twice the waves per workgroup at the same LDS
     FB_BLK(false, 35, 8192, 8, 1, 8, 8, 8, 8, 2),
     FB_BLK(false, 35, 2048, 8, 2, 8, 8, 4, 8),

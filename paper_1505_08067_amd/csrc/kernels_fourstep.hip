@@ -48,6 +48,8 @@ static const KEntry kPass[] = {
     FB_P1(false, 1072, 512, 32, 16, 16, 32),
     FB_P1(false, 1073, 128, 16, 16, 8, 16),
     FB_P2(false, 3106, 2048, 32, 8, 16, 16, 8),
+    // persistent workgroups looping over units (no prefetch, no spills)
+    FB_P2(false, 4130, 2048, 16, 8, 16, 16, 8),
     // pass 2 reads the workspace pass 1 has just written (partly still in the
     // Infinity Cache): cached loads, power-row twiddles, with / without
     // streaming stores

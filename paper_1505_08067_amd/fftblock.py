@@ -60,6 +60,7 @@ VARIANT_STAGE_STRIDE = 256
 VARIANT_WAVE_SYNC = 512
 VARIANT_HALF_EXCHANGE = 1024
 VARIANT_FIT_REGISTERS = 2048
+VARIANT_LOOP = 4096
 STORAGE_C64 = 0
 STORAGE_F16 = 1
 KERNEL_KINDS = {0: "block", 1: "pass1", 2: "pass2", 3: "filter", 4: "list"}

@@ -42,7 +42,7 @@ def _block_variants():
 @pytest.mark.parametrize("k", _block_variants())
 def test_block_variant(k):
     n = k["n"]
-    persistent = bool(k["flags"] & fb.VARIANT_PERSISTENT)
+    persistent = bool(k["flags"] & (fb.VARIANT_PERSISTENT | fb.VARIANT_LOOP))
     batch = 2 * k["c"] + 1
     if persistent:
         batch = max(batch, (1 << 24) // n + 3)   # more units than resident workgroups
@@ -114,6 +114,8 @@ def _pass_combos():
 def test_fourstep_variant_pairs(n1, k1, k2):
     n2 = k2["n"]
     n, batch = n1 * n2, 2
+    if (k1["flags"] | k2["flags"]) & fb.VARIANT_LOOP:
+        batch = max(batch, (1 << 23) // n)   # more units than resident workgroups
     half = bool(k1["flags"] & fb.VARIANT_FP16_STORAGE)
     # lengths a single block would take are forced onto the four-step path
     limit = 0 if n > fb.block_limit() else max(1024, n // 2)
