@@ -71,6 +71,21 @@ def test_block_sizes_against_oracle(n, sign):
     check(y, ref, n, label=f"N={n}")
 
 
+@pytest.mark.parametrize("batch", [63, 64])
+def test_32768_default_path_by_batch(batch):
+    # one workgroup per 32768-point transform fills the device only from 64
+    # transforms on; below that the default plan is four-step
+    n = 1 << 15
+    d = fb.plan_query(n, batch)
+    assert d["path"] == (fb.PATH_BLOCK if batch >= 64 else fb.PATH_FOURSTEP)
+    say(f"case: N={n} batch={batch} default path {d['path']} {d['kernel_name']}")
+    x = inputs.uniform(150 + batch, batch, n)
+    for sign in (FWD, BWD):
+        y = gpu_fft(x, sign)
+        ref = oracle.fft(x.astype(np.complex128), sign)
+        check(y, ref, n, label=f"N={n} batch={batch} sign={sign}")
+
+
 def test_n1_is_copy():
     x = inputs.uniform(5, 7, 1)
     for sign in (FWD, BWD):
