@@ -75,10 +75,12 @@ typedef enum {
  *              block path covers n <= the LDS block limit, longer lengths
  *              use the four-step path), and the compiled mixed-radix lengths
  *              3, 5, 6, 10, 12, 15, 20, 60, 100, 1000, 3072, 6000 and 15360
- *              (single block).  Other lengths: UNSUPPORTED_SIZE.  n = 32768
- *              takes a whole compute unit's LDS per transform: below 64
- *              transforms it goes four-step unless the options give a block
- *              limit.
+ *              (single block).  Other lengths: UNSUPPORTED_SIZE.  Long
+ *              blocks hold a large share of a compute unit's LDS per
+ *              transform, so small batches of them go four-step: the block
+ *              path needs at least 16 transforms at n = 8192, 48 at 16384
+ *              and 64 at 32768, unless fft_plan_create_ex's options give a
+ *              block limit or name a block kernel (radix, flags or c).
  *   batch      number of transforms per execute (>= 1).  On the block path
  *              the default kernel's width follows it: a batch that would
  *              give the full-width kernel fewer than 128 workgroups runs
@@ -216,8 +218,8 @@ typedef struct {
 
 typedef struct {
     size_t block_limit;  /* longest single-block length (power of two, 1024..32768); 0 =
-                            fft_block_limit() with the small-batch rule for 32768 (see
-                            fft_plan_create); nonzero: the single block at every batch */
+                            fft_block_limit() with the small-batch rule of fft_plan_create;
+                            nonzero: the single block at every batch up to this length */
     int n_radix;         /* schedule of the single block (four-step: of pass 1): 0 = default, else radix[0..n_radix) */
     int radix[8];
     int flags;           /* variant of the block kernel / pass 1; -1 = default */

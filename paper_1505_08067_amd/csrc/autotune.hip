@@ -378,6 +378,9 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
                 if (sp > 0 && !t[j].is_default) continue;
                 fft_plan_opts_t o;
                 fft_plan_opts_init(&o);
+                // a length the single block could take (a small batch put it
+                // on this path) stays four-step under explicit kernel options
+                if (n <= kMaxBlockLen) o.block_limit = std::max<size_t>(1024, n / 2);
                 o.n1 = n1;
                 o.n_radix = t[i].nr;
                 for (int r = 0; r < t[i].nr; ++r) o.radix[r] = t[i].radix[r];

@@ -274,12 +274,22 @@ constexpr size_t kMaxN = size_t(1) << 22;
 // Longest single block: with half exchanges 32768 points fit the LDS of one
 // workgroup (16384 exchange slots).
 constexpr size_t kDefaultBlockLimit = kMaxBlockLen;
-// Blocks longer than this take a whole compute unit's LDS per transform, so a
-// batch below kLongBlockMinBatch leaves most of the device idle; the default
-// plan then takes the four-step path, which spreads each transform over many
-// workgroups.  An explicit block limit in the options overrides this.
+// Longest length with a compiled list form, filter and mixed-radix blocks.
 constexpr size_t kLongBlock = 16384;
-constexpr size_t kLongBlockMinBatch = 64;
+
+// Smallest batch at which the default plan of a power-of-two length takes the
+// single block.  From 8192 on a transform holds a large share of a compute
+// unit's LDS (half of it at 16384, all of it at 32768), so a small batch
+// occupies few compute units, while the four-step path spreads every
+// transform over many workgroups.  Measured crossovers (microseconds per
+// execute, block against four-step): 8192 x 4: 9.0 / 7.8, x 16: 8.3 / 8.4;
+// 16384 x 1: 11.2 / 7.6, x 32: 12.2 / 10.6, x 64: 12.7 / 13.9; 32768 x 1:
+// 19.4 / 8.1, x 48: 22.1 / 18.0, x 96: 23.8 / 26.5.  Options that name a
+// block kernel or a block limit keep the block at any batch.
+size_t block_min_batch(size_t n)
+{
+    return n >= 32768 ? 64 : n >= 16384 ? 48 : n >= 8192 ? 16 : 1;
+}
 
 size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -446,7 +456,8 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
     p->segs.clear();
     if (n == 1) {
         p->path = FFT_PATH_BLOCK;
-    } else if ((n <= limit && (n <= kLongBlock || batch >= kLongBlockMinBatch || o.block_limit)) || !is_pow2(n)) {
+    } else if (!is_pow2(n) ||
+               (n <= limit && (batch >= block_min_batch(n) || o.block_limit || o.n_radix || o.flags >= 0 || o.c > 0))) {
         p->path = FFT_PATH_BLOCK;
         if (o.n_radix == 0 && o.flags < 0 && o.c <= 0) {
             p->k1 = sto ? nullptr : wisdom_kernel(n);

@@ -547,6 +547,16 @@ fft_status_t st_of(hipError_t e)
     return e == hipSuccess ? FFT_SUCCESS : e == hipErrorOutOfMemory ? FFT_ERR_OUT_OF_MEMORY : FFT_ERR_DEVICE;
 }
 
+// Options of the server's plans: single blocks up to 16384 at every batch
+// (their list forms coalesce same-length requests), four-step above.
+fft_plan_opts_t server_plan_opts()
+{
+    fft_plan_opts_t o;
+    fft_plan_opts_init(&o);
+    o.block_limit = std::min<size_t>(fft_block_limit(), 16384);
+    return o;
+}
+
 // Plan for (n, direction), created on first use (batch 1: the tables; the
 // per-request batch and workspace are given at execute).
 fft_status_t get_plan(fft_server_s* s, size_t n, int dir, fft_plan_t* p)
@@ -558,7 +568,8 @@ fft_status_t get_plan(fft_server_s* s, size_t n, int dir, fft_plan_t* p)
         return FFT_SUCCESS;
     }
     fft_plan_t q = nullptr;
-    const fft_status_t st = fft_plan_create(n, 1, dir, &q);
+    const fft_plan_opts_t o = server_plan_opts();
+    const fft_status_t st = fft_plan_create_ex(n, 1, dir, &o, &q);
     if (st != FFT_SUCCESS) return st;
     s->plans[key] = q;
     *p = q;
@@ -846,10 +857,9 @@ fft_status_t fft_server_submit(fft_server_t s, size_t n, size_t batch, int direc
     fft_plan_desc_t d;
     fft_status_t st = fft_plan_query(n, batch, direction, &d);   // validates the batch
     if (st != FFT_SUCCESS) return st;
-    // the path of the server's own plan for n (created at batch 1, as in
-    // get_plan): a length whose default plan depends on the batch is served
-    // the way a single request would be
-    st = fft_plan_query(n, 1, direction, &d);
+    // the path of the server's own plan for n (as get_plan creates it)
+    const fft_plan_opts_t so = server_plan_opts();
+    st = fft_plan_query_ex(n, 1, direction, &so, &d);
     if (st != FFT_SUCCESS) return st;
     const bool four = d.path == FFT_PATH_FOURSTEP;
     const size_t bytes = n * batch * sizeof(float2) * (four ? 3 : 2);  // in + out (+ workspace)

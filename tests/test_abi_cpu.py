@@ -80,10 +80,10 @@ def test_plan_query_block_and_fourstep():
     assert limit == 32768
     for L in range(1, 23):
         n = 1 << L
-        d = fb.plan_query(n, 3)
-        # 32768 fills one compute unit per transform: three transforms go
-        # four-step, 64 or more take the single block
-        if n <= 16384:
+        d = fb.plan_query(n, 64)
+        # from 8192 on a transform fills a large share of a compute unit, so
+        # small batches go four-step (checked below); 64 take the block
+        if n <= limit:
             assert d["path"] == fb.PATH_BLOCK and d["kernels_per_execute"] == 1
             assert math.prod(d["radix"]) == n
             assert d["workspace_bytes"] == 0
@@ -94,16 +94,25 @@ def test_plan_query_block_and_fourstep():
             # rows (pass 2) up to 2048, columns (pass 1) at least 256
             assert d["n2"] == min(2048, n // 256) and d["n1"] == n // d["n2"]
             assert math.prod(d["radix"]) == d["n1"] and math.prod(d["radix2"]) == d["n2"]
-            assert d["workspace_bytes"] == 8 * n * 3
+            assert d["workspace_bytes"] == 8 * n * 64
             assert d["lds_bytes"] <= 160 * 1024
-    for batch, path in ((63, fb.PATH_FOURSTEP), (64, fb.PATH_BLOCK), (1024, fb.PATH_BLOCK)):
-        d = fb.plan_query(limit, batch)
-        assert d["path"] == path, batch
-        if path == fb.PATH_BLOCK:
-            assert math.prod(d["radix"]) == limit and d["workspace_bytes"] == 0
-            assert d["lds_bytes"] <= 160 * 1024 and d["threads_per_block"] == limit // 32
-    # an explicit block limit keeps the single block at any batch
+    for n, first in ((2048, 1), (4096, 1), (8192, 16), (16384, 48), (32768, 64)):
+        for batch in (1, first - 1, first, 1024):
+            if batch < 1:
+                continue
+            d = fb.plan_query(n, batch)
+            assert d["path"] == (fb.PATH_BLOCK if batch >= first else fb.PATH_FOURSTEP), (n, batch)
+            if d["path"] == fb.PATH_BLOCK:
+                assert math.prod(d["radix"]) == n and d["workspace_bytes"] == 0
+                assert d["lds_bytes"] <= 160 * 1024
+            else:
+                assert d["n1"] * d["n2"] == n and d["workspace_bytes"] == 8 * n * batch
+    assert fb.plan_query(limit, 64)["threads_per_block"] == limit // 32
+    # an explicit block limit, or options naming a block kernel, keep the
+    # single block at any batch
     assert fb.plan_query(limit, 1, opts=fb.make_opts(block_limit=limit))["path"] == fb.PATH_BLOCK
+    assert fb.plan_query(16384, 1, opts=fb.make_opts(flags=1059))["path"] == fb.PATH_BLOCK
+    assert fb.plan_query(8192, 1, opts=fb.make_opts(c=1))["path"] == fb.PATH_BLOCK
     assert fb.plan_query(limit, 1024, opts=fb.make_opts(block_limit=16384))["path"] == fb.PATH_FOURSTEP
     d = fb.plan_query(1 << 20, 16)
     assert (d["n1"], d["n2"]) == (512, 2048)

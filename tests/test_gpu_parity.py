@@ -29,11 +29,11 @@ def to_dev(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex64)).to("cuda")
 
 
-def gpu_fft(x, sign, inplace=False):
+def gpu_fft(x, sign, inplace=False, opts=None):
     x = np.ascontiguousarray(x, dtype=np.complex64)
     n = x.shape[-1]
     batch = x.size // n
-    with fb.Plan(n, batch, sign) as plan:
+    with fb.Plan(n, batch, sign, opts) as plan:
         d = to_dev(x)
         y = plan.execute(d, out=d if inplace else None)
         torch.cuda.synchronize()
@@ -61,23 +61,27 @@ BLOCK_SIZES = [2 ** k for k in range(1, 15)]
 @pytest.mark.parametrize("n", BLOCK_SIZES)
 @pytest.mark.parametrize("sign", [FWD, BWD])
 def test_block_sizes_against_oracle(n, sign):
-    d = fb.plan_query(n, 1, sign)
+    # small batches of 8192 and longer default to four-step: name the limit
+    opts = fb.make_opts(block_limit=n) if n >= 8192 else None
+    d = fb.plan_query(n, 1, sign, opts)
+    assert d["path"] == fb.PATH_BLOCK
     fpb = max(1, d["transforms_per_block"])
     batch = 2 * fpb + 1 if n < 16384 else 3   # a partly filled last workgroup
     say(f"case: block N={n} batch={batch} sign={sign} kernel={d['kernel_name']}")
     x = inputs.uniform(100 + n, batch, n)
-    y = gpu_fft(x, sign)
+    y = gpu_fft(x, sign, opts=opts)
     ref = oracle.fft(x.astype(np.complex128), sign)
     check(y, ref, n, label=f"N={n}")
 
 
-@pytest.mark.parametrize("batch", [63, 64])
-def test_32768_default_path_by_batch(batch):
-    # one workgroup per 32768-point transform fills the device only from 64
-    # transforms on; below that the default plan is four-step
-    n = 1 << 15
+@pytest.mark.parametrize("n,batch", [(8192, 15), (8192, 16), (16384, 47), (16384, 48), (32768, 63), (32768, 64)])
+def test_long_block_default_path_by_batch(n, batch):
+    # a long block fills the device only from a minimum batch on (one
+    # 32768-point transform takes a whole compute unit); below it the
+    # default plan is four-step
+    first = {8192: 16, 16384: 48, 32768: 64}[n]
     d = fb.plan_query(n, batch)
-    assert d["path"] == (fb.PATH_BLOCK if batch >= 64 else fb.PATH_FOURSTEP)
+    assert d["path"] == (fb.PATH_BLOCK if batch >= first else fb.PATH_FOURSTEP)
     say(f"case: N={n} batch={batch} default path {d['path']} {d['kernel_name']}")
     x = inputs.uniform(150 + batch, batch, n)
     for sign in (FWD, BWD):
