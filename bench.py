@@ -462,30 +462,38 @@ def run_sar(torch, fb, inputs, stream):
 
 def run_small(torch, fb, inputs, stream):
     """Batches too small to be HBM-bound: N=1024 x 64 forward (launch-bound),
-    three more small batches, and the paper's own workload N=1024 x 1024
+    five more small batches, and the paper's own workload N=1024 x 1024
     (16 MiB in + out, resident in the Infinity Cache).  Per-call time is 50
     back-to-back launches between two events (it includes the gaps between
-    launches); where the planner picks the one-wave form of a kernel, the
-    full-width form is timed beside it.  Kernel durations of the same launches
+    launches); where the planner picks the one-wave form of a kernel, or the
+    four-step path for a long length, the full-width single block is timed
+    beside it.  Kernel durations of the same launches
     come from a kernel trace (dispatch-stamped events have a floor of about
     4 us, above these kernels)."""
     res = {}
     sh = stream.cuda_stream
     ks = {k["name"]: k for k in fb.kernels()}
     cases = (("n1024x64_launch_bound", 1024, 64, 0), ("n512x64", 512, 64, 0), ("n256x256", 256, 256, 0),
-             ("n3072x64", 3072, 64, 0), ("n1024x1024_cache_resident", 1024, 1024, 1))
+             ("n3072x64", 3072, 64, 0), ("n16384x1", 16384, 1, 2), ("n32768x16", 32768, 16, 3),
+             ("n1024x1024_cache_resident", 1024, 1024, 1))
     for name, n, batch, seed in cases:
         x = torch.from_numpy(inputs.uniform(seed, batch, n)).to("cuda")
         y = torch.empty_like(x)
         row = {}
-        wide = ks[fb.plan_query(n, 1 << 20)["kernel_name"]]
+        wide = ks[fb.plan_query(n, 1 << 14)["kernel_name"]]
         forms = [("planner", None)]
-        if fb.plan_query(n, batch)["kernel_name"] != wide["name"]:
-            forms.append(("full_width", fb.make_opts(radix=wide["radix"], flags=wide["flags"], c=wide["c"])))
+        planned = fb.plan_query(n, batch)
+        if planned["kernel_name"] != wide["name"]:
+            # the one-wave form, or for long lengths the four-step path: the
+            # full-width single block beside it
+            alt = "single_block" if planned["path"] == fb.PATH_FOURSTEP else "full_width"
+            forms.append((alt, fb.make_opts(radix=wide["radix"], flags=wide["flags"], c=wide["c"])))
         for form, opts in forms:
             with fb.Plan(n, batch, fb.FORWARD, opts) as p:
                 t = _timed(torch, stream, lambda: p.execute_ptr(x.data_ptr(), y.data_ptr(), sh), reps=50)
-                row[form] = {"kernel": p.describe()["kernel_name"], "per_call_us": round(t * 1e6, 2),
+                d = p.describe()
+                kname = d["kernel_name"] + ("+" + d["kernel_name2"] if d["path"] == fb.PATH_FOURSTEP else "")
+                row[form] = {"kernel": kname, "per_call_us": round(t * 1e6, 2),
                              "GFLOPs_per_call": round(flops(n, batch) / t / 1e9, 1)}
         res[name] = row
         del x, y
