@@ -171,12 +171,14 @@ def test_batch_isolation_with_poisoned_neighbours(n):
     check(y[0::2], oracle.fft(good.astype(np.complex128), FWD), n, label="clean slots")
 
 
-@pytest.mark.parametrize("n", [512, 4096, 1 << 20])
-def test_in_place_equals_out_of_place(n):
+@pytest.mark.parametrize("n,limit", [(512, 0), (4096, 0), (16384, 0), (32768, 32768), (1 << 20, 0)])
+def test_in_place_equals_out_of_place(n, limit):
+    # 16384 x 3 runs four-step (small batch), 32768 x 3 the single block
     batch = 3
+    opts = fb.make_opts(block_limit=limit) if limit else None
     x = inputs.uniform(12, batch, n)
-    a = gpu_fft(x, FWD)
-    b = gpu_fft(x, FWD, inplace=True)
+    a = gpu_fft(x, FWD, opts=opts)
+    b = gpu_fft(x, FWD, inplace=True, opts=opts)
     assert np.array_equal(a, b)
 
 
