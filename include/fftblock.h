@@ -79,8 +79,9 @@ typedef enum {
  *              blocks hold a large share of a compute unit's LDS per
  *              transform, so small batches of them go four-step: the block
  *              path needs at least 16 transforms at n = 8192, 48 at 16384
- *              and 64 at 32768, unless fft_plan_create_ex's options give a
- *              block limit or name a block kernel (radix, flags or c).
+ *              and 64 at 32768 (FP16 storage: 32 at 16384, 48 at 32768),
+ *              unless fft_plan_create_ex's options give a block limit or
+ *              name a block kernel (radix, flags or c).
  *   batch      number of transforms per execute (>= 1).  On the block path
  *              the default kernel's width follows it: a batch that would
  *              give the full-width kernel fewer than 128 workgroups runs

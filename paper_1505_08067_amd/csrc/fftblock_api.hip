@@ -284,10 +284,15 @@ constexpr size_t kLongBlock = 16384;
 // transform over many workgroups.  Measured crossovers (microseconds per
 // execute, block against four-step): 8192 x 4: 9.0 / 7.8, x 16: 8.3 / 8.4;
 // 16384 x 1: 11.2 / 7.6, x 32: 12.2 / 10.6, x 64: 12.7 / 13.9; 32768 x 1:
-// 19.4 / 8.1, x 48: 22.1 / 18.0, x 96: 23.8 / 26.5.  Options that name a
-// block kernel or a block limit keep the block at any batch.
-size_t block_min_batch(size_t n)
+// 19.4 / 8.1, x 48: 22.1 / 18.0, x 96: 23.8 / 26.5.  FP16 storage halves
+// the block's bytes but not the four-step workspace's, which moves the
+// crossovers down: 8192 x 1: 7.4 / 8.3; 16384 x 24: 10.7 / 10.6, x 32:
+// 10.6 / 11.2; 32768 x 32: 17.7 / 14.1, x 48: 18.0 / 18.1.  Options that name
+// a block kernel or a block limit keep the block at any batch.
+size_t block_min_batch(size_t n, int storage)
 {
+    if (storage)
+        return n >= 32768 ? 48 : n >= 16384 ? 32 : 1;
     return n >= 32768 ? 64 : n >= 16384 ? 48 : n >= 8192 ? 16 : 1;
 }
 
@@ -457,7 +462,7 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
     if (n == 1) {
         p->path = FFT_PATH_BLOCK;
     } else if (!is_pow2(n) ||
-               (n <= limit && (batch >= block_min_batch(n) || o.block_limit || o.n_radix || o.flags >= 0 || o.c > 0))) {
+               (n <= limit && (batch >= block_min_batch(n, sto) || o.block_limit || o.n_radix || o.flags >= 0 || o.c > 0))) {
         p->path = FFT_PATH_BLOCK;
         if (o.n_radix == 0 && o.flags < 0 && o.c <= 0) {
             p->k1 = sto ? nullptr : wisdom_kernel(n);

@@ -107,6 +107,12 @@ def test_plan_query_block_and_fourstep():
                 assert d["lds_bytes"] <= 160 * 1024
             else:
                 assert d["n1"] * d["n2"] == n and d["workspace_bytes"] == 8 * n * batch
+    f16 = fb.make_opts(storage=fb.STORAGE_F16)
+    for n, first in ((8192, 1), (16384, 32), (32768, 48)):
+        for batch in (first - 1, first):
+            if batch >= 1:
+                d = fb.plan_query(n, batch, opts=f16)
+                assert d["path"] == (fb.PATH_BLOCK if batch >= first else fb.PATH_FOURSTEP), (n, batch)
     assert fb.plan_query(limit, 64)["threads_per_block"] == limit // 32
     # an explicit block limit, or options naming a block kernel, keep the
     # single block at any batch
