@@ -31,6 +31,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "batched c64 FFT GFLOP/s (5Nlog2N) + % HBM peak; serving p50/p99 latency"
+STAMP = 10   # one timed step in STAMP carries per-dispatch duration stamps
 HBM_PEAK_GBPS = 8000.0
 
 
@@ -42,7 +43,7 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=50)
-    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=50, help="untimed steps (the clocks settle within ~20 ms)")
     p.add_argument("--rotate", type=int, default=4, help="(in,out) buffer sets per shape")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle time for the CPU baseline")
@@ -172,34 +173,42 @@ def main():
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} steps done")
 
-    # timed region: K steps of ordinary launches between two events
+    # timed region: K steps between two events on the launch stream.  Every
+    # STAMP-th step dispatches each kernel with two events the device stamps
+    # at the kernel's own start and end, so the per-kernel durations are
+    # sampled from the timed launches themselves; a stamped dispatch adds
+    # several microseconds of gap before the next one, so only a sample of
+    # the steps carries stamps
     K = args.steps
+    stamped = [s for s in range(K) if s % STAMP == STAMP - 1] or [K - 1]
+    evs = {s: [(fb.Event(), fb.Event()) for _ in range(len(launches))] for s in stamped}
     t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     t_start.record(stream)
     for s in range(K):
-        run_step(s)
+        run_step(s, evs.get(s))
     t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log(f"timed {K} steps in {wall:.3f} s wall")
-    total_ms = t_start.elapsed_time(t_end)
-    ms_per_step = total_ms / K
+    ms_per_step = t_start.elapsed_time(t_end) / K
 
-    # the same K steps again with every dispatch stamped (start and end of the
-    # kernel itself), for the per-kernel durations
-    evs = [[(fb.Event(), fb.Event()) for _ in range(len(launches))] for _ in range(K)]
+    # cross-check: the same K steps with ordinary launches (no stamps)
     torch.cuda.synchronize()
+    t_start.record(stream)
     for s in range(K):
-        run_step(s, evs[s])
+        run_step(s)
+    t_end.record(stream)
     torch.cuda.synchronize()
+    ms_per_step_plain = t_start.elapsed_time(t_end) / K
+    log(f"step {ms_per_step * 1e3:.1f} us stamped, {ms_per_step_plain * 1e3:.1f} us with ordinary launches")
     per = {}
-    for s in range(K):
+    for s in stamped:
         for li, (kname, name, pass_, key) in enumerate(launches):
             e0, e1 = evs[s][li]
             per.setdefault(li, []).append(e0.elapsed_ms(e1))
-    for row in evs:
+    for row in evs.values():
         for e0, e1 in row:
             e0.close()
             e1.close()
@@ -289,6 +298,7 @@ def main():
             "hbm_bytes_per_step": int(sum(16.0 * n * b for _, _, _, (n, b) in launches)),
             "device": info["arch"],
             "kernel_source_hash": kernel_source_hash(),
+            "ms_per_step_unstamped_launches": round(ms_per_step_plain, 5),
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
