@@ -214,6 +214,13 @@ struct PolPass1T {
     {
         return c.src + (long long)n * a.n_other;
     }
+    // the same for n = t + nc with nc the same in every lane: one per-thread
+    // base, then a stride the scalar unit forms (no 64-bit multiply per load)
+    template <int C>
+    __device__ static const TI* in_at_split(const KArgs& a, const Ctx& c, int t, int nc)
+    {
+        return c.src + (long long)t * a.n_other + (long long)nc * a.n_other;
+    }
     // x * exp(-2 pi i col k / N)
     __device__ static float2 twiddled(const KArgs& a, const Ctx& c, int k, float2 x)
     {
@@ -266,6 +273,7 @@ struct PolPass1T {
         float2* base = a.out + bt * a.nbig + ((long long)(tile * C) << a.cw_bits) + (k0 >> a.cw_bits) * gstride;
         const int cwm = (1 << a.cw_bits) - 1;
         const int blk_bits = a.cw_bits + __builtin_ctz(C);
+        const unsigned gs24 = (unsigned)gstride;
 #pragma unroll
         for (int m = 0; m < N * C / NT; ++m) {
             const int e = tid + m * NT;
@@ -273,7 +281,9 @@ struct PolPass1T {
             const int w = e & ((1 << blk_bits) - 1);
             const int ff = w >> a.cw_bits;
             const int k = (g << a.cw_bits) + (w & cwm);
-            gstore<FL>(base + g * gstride + w, lds[ff * LDSN + lds_at<FL>(k)]);
+            // the offset within one transform is below N <= 2^22, so a
+            // 24-bit multiply in 32 bits forms it (no 64-bit multiply)
+            gstore<FL>(base + (long long)(int)(__umul24(g, gs24) + w), lds[ff * LDSN + lds_at<FL>(k)]);
         }
     }
     __host__ __device__ static long long units(const KArgs& a, int) { return a.batch * a.tiles; }
@@ -317,10 +327,35 @@ struct PolPass2T {
     {
         gstore<FL>(c.dst + (long long)k * a.n_other, x);
     }
+    // the same for k = t + kc with kc the same in every lane (see in_at_split)
+    template <int FL>
+    __device__ static void store_split(const KArgs& a, const Ctx& c, int t, int kc, float2 x)
+    {
+        gstore<FL>(c.dst + (long long)t * a.n_other + (long long)kc * a.n_other, x);
+    }
     __host__ __device__ static long long units(const KArgs& a, int) { return a.batch * a.tiles; }
 };
 using PolPass2 = PolPass2T<float2>;
 using PolPass2H = PolPass2T<h2_t>;
+
+// Address of element t + c (t per lane, c the same in every lane) through the
+// policy's split form where it has one, else its plain one.
+template <class P, int C, class Ctx>
+__device__ __forceinline__ auto in_at_split(const KArgs& a, const Ctx& cx, int t, int c)
+{
+    if constexpr (requires { P::template in_at_split<C>(a, cx, t, c); })
+        return P::template in_at_split<C>(a, cx, t, c);
+    else
+        return P::template in_at<C>(a, cx, t + c);
+}
+template <class P, int FL, class Ctx>
+__device__ __forceinline__ void store_split(const KArgs& a, const Ctx& cx, int t, int c, float2 x)
+{
+    if constexpr (requires { P::template store_split<FL>(a, cx, t, c, x); })
+        P::template store_split<FL>(a, cx, t, c, x);
+    else
+        P::template store<FL>(a, cx, t + c, x);
+}
 
 // --------------------------------------------------------------- the stages
 // v holds the stage-0 inputs x[t + i*T + r*N/R0] on entry and the outputs
@@ -498,7 +533,7 @@ k_fft(KArgs a)
             for (int i = 0; i < E / R0; ++i)
 #pragma unroll
                 for (int r = 0; r < R0; ++r)
-                    v[i * R0 + r] = gload<FL>(P::template in_at<C>(a, cx, t + i * T + r * (N / R0)));
+                    v[i * R0 + r] = gload<FL>(in_at_split<P, C>(a, cx, t, i * T + r * (N / R0)));
         } else {
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = make_float2(0.f, 0.f);
@@ -587,7 +622,7 @@ k_fft(KArgs a)
 #pragma unroll
                 for (int i = 0; i < E / RL; ++i)
 #pragma unroll
-                    for (int q = 0; q < RL; ++q) P::template store<FL>(a, cx, t + i * T + q * NsL, v[i * RL + q]);
+                    for (int q = 0; q < RL; ++q) store_split<P, FL>(a, cx, t, i * T + q * NsL, v[i * RL + q]);
             }
         }
     };
