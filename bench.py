@@ -31,7 +31,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "batched c64 FFT GFLOP/s (5Nlog2N) + % HBM peak; serving p50/p99 latency"
-STAMP = 10   # one timed step in STAMP carries per-dispatch duration stamps
 HBM_PEAK_GBPS = 8000.0
 
 
@@ -162,7 +161,7 @@ def main():
         k = s % args.rotate
         for li, (_, name, pass_, key) in enumerate(launches):
             xin, xout = bufs[key][k]
-            if evs is None:
+            if evs is None or li not in evs:
                 plans[name].execute_pass_ptr(pass_, xin.data_ptr(), xout.data_ptr(), sh)
             else:
                 # the device stamps the pair at this dispatch's own start and end
@@ -173,15 +172,19 @@ def main():
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} steps done")
 
-    # timed region: K steps between two events on the launch stream.  Every
-    # STAMP-th step dispatches each kernel with two events the device stamps
-    # at the kernel's own start and end, so the per-kernel durations are
-    # sampled from the timed launches themselves; a stamped dispatch adds
-    # several microseconds of gap before the next one, so only a sample of
-    # the steps carries stamps
+    # timed region: K steps between two events on the launch stream.  In
+    # every step one launch, in turn, is dispatched with two events the device
+    # stamps at the kernel's own start and end, so the per-kernel durations
+    # are sampled from the timed launches themselves.  A stamped dispatch
+    # leaves a gap of several microseconds before the next one, and a kernel
+    # that starts after such a gap finds the previous kernel's stores drained
+    # and runs faster than back to back; stamping one launch per step keeps
+    # each stamped kernel's predecessor an ordinary launch.
     K = args.steps
-    stamped = [s for s in range(K) if s % STAMP == STAMP - 1] or [K - 1]
-    evs = {s: [(fb.Event(), fb.Event()) for _ in range(len(launches))] for s in stamped}
+    nl = len(launches)
+    evs = {s: {s % nl: (fb.Event(), fb.Event())} for s in range(K)}
+    for li in range(K, nl):  # fewer steps than launches: the last step stamps the rest
+        evs[K - 1][li] = (fb.Event(), fb.Event())
     t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -204,12 +207,11 @@ def main():
     ms_per_step_plain = t_start.elapsed_time(t_end) / K
     log(f"step {ms_per_step * 1e3:.1f} us stamped, {ms_per_step_plain * 1e3:.1f} us with ordinary launches")
     per = {}
-    for s in stamped:
-        for li, (kname, name, pass_, key) in enumerate(launches):
-            e0, e1 = evs[s][li]
+    for s in range(K):
+        for li, (e0, e1) in evs[s].items():
             per.setdefault(li, []).append(e0.elapsed_ms(e1))
     for row in evs.values():
-        for e0, e1 in row:
+        for e0, e1 in row.values():
             e0.close()
             e1.close()
     fl_step = sum(flops(n, b) for _, n, b, _ in items)
