@@ -6,7 +6,8 @@ One step = one pass of the hot path over the plain workload:
   * N = 2^20, batch 16, forward and inverse (four-step N1 x N2 as planned:
     column block FFTs + twiddle, then row block FFTs + corner-turn store).
 Inputs are seeded uniform[-1,1] complex64, resident in HBM before timing;
-the step rotates over several (in, out) buffer sets so the footprint exceeds
+every launch of the step (each direction of each shape) has its own (in, out)
+buffer sets, rotated, so no buffer is reused within 1.75 GiB of traffic, beyond
 the 256 MB Infinity Cache (cold-cache timing).
 
 Metric: GFLOP/s counted as 5 N log2 N per transform, over the event-timed
@@ -43,7 +44,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=50, help="untimed steps (the clocks settle within ~20 ms)")
-    p.add_argument("--rotate", type=int, default=4, help="(in,out) buffer sets per shape")
+    p.add_argument("--rotate", type=int, default=2,
+                   help="(in,out) buffer sets per launch of a step (every launch has its own sets)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="target oracle time for the CPU baseline")
     p.add_argument("--no-extras", action="store_true", help="skip copy probe and SAR chain timing")
@@ -132,25 +134,28 @@ def main():
     ]
     plans = {}
     bufs = {}
+    # Every item of the step (each direction of each shape) has its own
+    # `rotate` (in, out) sets, so no launch reads what another launch of the
+    # same step read or wrote: between two uses of one buffer the step moves
+    # at least rotate * 4 * 256 MiB - 256 MiB >= 1.75 GiB, beyond the 256 MB
+    # Infinity Cache and the 32 MB of L2.
+    host_x = {}
     for name, n, batch, sign in items:
         plans[name] = fb.Plan(n, batch, sign)
-        if (n, batch) not in bufs:
-            x = torch.from_numpy(inputs.uniform(1, batch, n)).to("cuda")
-            sets = []
-            for _ in range(args.rotate):
-                sets.append((x.clone(), torch.empty_like(x)))
-            del x
-            bufs[(n, batch)] = sets
+        if (n, batch) not in host_x:
+            host_x[(n, batch)] = torch.from_numpy(inputs.uniform(1, batch, n))
+        x = host_x[(n, batch)].to("cuda")
+        bufs[name] = [(x.clone(), torch.empty_like(x)) for _ in range(args.rotate)]
+        del x
+    del host_x
     torch.cuda.synchronize()
 
-    # launches of one step: (kernel label, plan, pass, shape key)
+    # launches of one step: (kernel label, item, pass, shape)
     launches = []
     for name, n, batch, sign in items:
         d = plans[name].describe()
-        if d["path"] == fb.PATH_BLOCK:
-            launches.append((d["kernel_name"], name, 1, (n, batch)))
-        else:
-            launches.append((d["kernel_name"], name, 1, (n, batch)))
+        launches.append((d["kernel_name"], name, 1, (n, batch)))
+        if d["path"] != fb.PATH_BLOCK:
             launches.append((d["kernel_name2"], name, 2, (n, batch)))
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
@@ -159,8 +164,8 @@ def main():
 
     def run_step(s, evs=None):
         k = s % args.rotate
-        for li, (_, name, pass_, key) in enumerate(launches):
-            xin, xout = bufs[key][k]
+        for li, (_, name, pass_, _) in enumerate(launches):
+            xin, xout = bufs[name][k]
             if evs is None or li not in evs:
                 plans[name].execute_pass_ptr(pass_, xin.data_ptr(), xout.data_ptr(), sh)
             else:
@@ -237,7 +242,17 @@ def main():
                             "launches_per_step": e["launches_per_step"],
                             "bytes_per_launch": int(e["bytes_per_launch"]), "GBps": round(gbps, 1),
                             "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4),
-                            "workgroups_per_cu": occ, "waves_per_simd": occ * kinfo[kname]["threads"] / 64 / 4}
+                            "workgroups_per_cu": occ, "waves_per_simd": occ * kinfo[kname]["threads"] / 64 / 4,
+                            "by_direction": {}}
+    # the same rows split by direction (each launch has its own buffers)
+    for li, (kname, name, pass_, (n, batch)) in enumerate(launches):
+        d = sorted(per[li])
+        avg = sum(d) / len(d)
+        gbps = 16.0 * n * batch / (avg * 1e-3) / 1e9
+        breakdown[kname]["by_direction"][name.rsplit(" ", 1)[1]] = {
+            "launch": name + (f" pass {pass_}" if plans[name].describe()["path"] != fb.PATH_BLOCK else ""),
+            "samples": len(d), "avg_us": round(avg * 1e3, 2), "median_us": round(d[len(d) // 2] * 1e3, 2),
+            "GBps": round(gbps, 1), "frac_hbm_peak": round(gbps / HBM_PEAK_GBPS, 4)}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     dom_avg_ms = kernels[dom]["total_ms"] / kernels[dom]["launches_per_step"]
     achieved = kernels[dom]["bytes_per_launch"] / (dom_avg_ms * 1e-3) / 1e9
@@ -295,7 +310,7 @@ def main():
             "workload": "batched complex64 FFT, N=4096 x batch 4096 forward+inverse (single LDS block) "
                         f"+ N=2^20 x batch 16 forward+inverse (four-step {split})",
             "inputs": "uniform[-1,1] re/im, seed 1",
-            "cold_cache_buffer_sets": args.rotate,
+            "buffer_sets_per_launch": args.rotate,
             "flops_per_step": fl_step,
             "hbm_bytes_per_step": int(sum(16.0 * n * b for _, _, _, (n, b) in launches)),
             "device": info["arch"],

@@ -531,8 +531,10 @@ typedef struct {
     int max_coalesce;    /* requests per launch, 1..FFT_LAUNCH_MAX_REQUESTS (default 32; 1 = off) */
     size_t max_transforms;  /* transforms per coalesced launch (default 16384) */
     size_t backfill_bytes;  /* while the head request waits for room, later requests of at most this
-                               many bytes may pass it, at most this many bytes of them in flight
-                               (default 1 GiB; 0 = strict FIFO) */
+                               many bytes may pass it, at most this many bytes of them in flight and
+                               never more than the budget minus the head's bytes, so the head fits as
+                               soon as the work launched before it completes (default 1 GiB; 0 =
+                               strict FIFO) */
     int small_streams;      /* streams [0, small_streams) take only launches led by a request of at
                                most small_bytes, so short requests never queue on a stream behind a
                                long transform (they use any stream when these are full); default 1,
@@ -613,7 +615,12 @@ fft_status_t fft_server_create(const fft_server_opts_t* opts, fft_server_t* out)
  * (plans and twiddle tables stay resident for the server's lifetime). */
 fft_status_t fft_server_prepare(fft_server_t s, size_t n, int direction);
 /* Queue a request; `in` is a DEVICE pointer to batch * n complex64 values that
- * must stay valid and unchanged until the request completes.  The output (and,
+ * must stay valid and unchanged until the request completes.  `stream` is the
+ * submitter's hipStream_t (NULL = the null stream): the server records an event
+ * there at submission and its launch waits for it, so work queued on `stream`
+ * before the call (the kernel or copy that writes `in`) completes before the
+ * server reads the input; the submitting thread need not synchronise.  The
+ * output (and,
  * for four-step lengths, the workspace) is allocated from the server's arena
  * when the request is issued; outputs stay there until fft_server_release (or
  * completion, with auto_release), and a full arena holds later launches back
@@ -622,7 +629,7 @@ fft_status_t fft_server_prepare(fft_server_t s, size_t n, int direction);
  * or misaligned pointer, zero sizes or a bad direction; UNSUPPORTED_SIZE for a
  * length the planner has no kernels for. */
 fft_status_t fft_server_submit(fft_server_t s, size_t n, size_t batch, int direction, const void* in,
-                               uint64_t* ticket);
+                               void* stream, uint64_t* ticket);
 /* Block until the request completes (TIMEOUT after timeout_s seconds);
  * *out = its output in the arena (valid until fft_server_release), *info its
  * record.  OUT_OF_MEMORY for a rejected request.  Not for auto_release

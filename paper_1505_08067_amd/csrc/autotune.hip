@@ -94,26 +94,6 @@ static StageFn stage_fn(int radix)
     }
 }
 
-// exp(-2 pi i m / n) in FP64, rounded once (same reduction as the planner's)
-static float2 root32(long long m, long long n)
-{
-    m %= n;
-    if (m < 0) m += n;
-    const long long q = (4 * m) / n, rem = 4 * m - q * n;
-    const double hp = 1.57079632679489661923132169163975144;
-    double c, s;
-    if (2 * rem <= n) {
-        c = std::cos(hp * ((double)rem / (double)n));
-        s = std::sin(hp * ((double)rem / (double)n));
-    } else {
-        c = std::sin(hp * ((double)(n - rem) / (double)n));
-        s = std::cos(hp * ((double)(n - rem) / (double)n));
-    }
-    const double cr = q == 0 ? c : q == 1 ? -s : q == 2 ? -c : s;
-    const double sr = q == 0 ? s : q == 1 ? c : q == 2 ? -s : -c;
-    return make_float2((float)cr, (float)-sr);
-}
-
 // ---------------------------------------------------------------- wisdom
 struct Wisdom {
     std::mutex mu;
@@ -265,7 +245,7 @@ fft_status_t fft_stage_benchmark(size_t n, int radix, int start_stage, int reps,
     const int row = (P + 1) & ~1;
     std::vector<float2> pw((size_t)ns * row, make_float2(0.f, 0.f));
     for (int k = 0; k < ns; ++k)
-        for (int i = 0; i < P; ++i) pw[(size_t)k * row + i] = root32((long long)k << i, (long long)ns * radix);
+        for (int i = 0; i < P; ++i) pw[(size_t)k * row + i] = root_f32((long long)k << i, (long long)ns * radix);
     const size_t batch = std::max<size_t>((size_t)1 << 22, n) / n;
     float2 *d = nullptr, *dpw = nullptr;
     hipError_t e = hipMalloc(&d, batch * n * sizeof(float2));

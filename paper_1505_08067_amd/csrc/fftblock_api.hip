@@ -114,35 +114,6 @@ long long kernel_units(const KEntry& k, const KArgs& a)
     return a.batch * a.tiles;
 }
 
-}  // namespace fb
-
-namespace {
-
-std::mutex g_mu;
-std::unordered_set<fft_plan_s*> g_plans;
-
-bool plan_live(fft_plan_s* p)
-{
-    std::lock_guard<std::mutex> lk(g_mu);
-    return p != nullptr && g_plans.count(p) != 0;
-}
-
-fft_status_t from_hip(hipError_t e)
-{
-    if (e == hipSuccess) return FFT_SUCCESS;
-    if (e == hipErrorOutOfMemory) return FFT_ERR_OUT_OF_MEMORY;
-    return FFT_ERR_DEVICE;
-}
-
-bool is_pow2(size_t n) { return n != 0 && (n & (n - 1)) == 0; }
-
-int ilog2(size_t n)
-{
-    int l = 0;
-    while ((size_t(1) << l) < n) ++l;
-    return l;
-}
-
 // exp(-2 pi i m / n) in FP64 by quadrant reduction: the angle handed to
 // cos/sin never exceeds pi/4, and multiples of a quarter turn are exact.
 void root_fwd(long long m, long long n, double* re, double* im)
@@ -178,6 +149,35 @@ float2 root_f32(long long m, long long n)
     double re, im;
     root_fwd(m, n, &re, &im);
     return make_float2((float)re, (float)im);  // one round-to-nearest-even from FP64
+}
+
+}  // namespace fb
+
+namespace {
+
+std::mutex g_mu;
+std::unordered_set<fft_plan_s*> g_plans;
+
+bool plan_live(fft_plan_s* p)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return p != nullptr && g_plans.count(p) != 0;
+}
+
+fft_status_t from_hip(hipError_t e)
+{
+    if (e == hipSuccess) return FFT_SUCCESS;
+    if (e == hipErrorOutOfMemory) return FFT_ERR_OUT_OF_MEMORY;
+    return FFT_ERR_DEVICE;
+}
+
+bool is_pow2(size_t n) { return n != 0 && (n & (n - 1)) == 0; }
+
+int ilog2(size_t n)
+{
+    int l = 0;
+    while ((size_t(1) << l) < n) ++l;
+    return l;
 }
 
 // (m, n) of one table entry, per segment type (see TwSeg in internal.hpp).

@@ -103,6 +103,11 @@ struct TwSeg {
     long long offset, count;
     long long a, b, c, d;
 };
+// exp(-2 pi i m / n) in FP64 on the host (quadrant reduction, quarter turns
+// exact), and the same rounded once to FP32: every host-side twiddle value.
+void root_fwd(long long m, long long n, double* re, double* im);
+float2 root_f32(long long m, long long n);
+
 // Evaluate the segments on the device in FP64 into dst (total entries).
 hipError_t generate_twiddles_device(float2* dst, long long total, const TwSeg* segs, int nseg, hipStream_t st);
 

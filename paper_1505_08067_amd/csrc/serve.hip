@@ -8,7 +8,9 @@
 //     still free waits at the head of the queue;
 //   * while the head waits, later requests of at most backfill_bytes may
 //     pass it, with at most backfill_bytes of such requests in flight at a
-//     time, so the head is delayed by little and never starved
+//     time and never more than the head leaves of the budget: once the work
+//     launched before the head completes, the head fits beside whatever
+//     backfill is in flight, so it is delayed by little and never starved
 //     (backfill_bytes = 0: strict FIFO);
 //   * the launch goes to the stream with the fewest outstanding bytes among
 //     those with fewer than max_inflight launches outstanding; the first
@@ -105,11 +107,14 @@ public:
         // request that fits (backfill, bounded so the head is not starved)
         auto pick = queue_.begin();
         bool backfill = false;
+        // backfill in flight may take at most what the head leaves of the budget
+        size_t bf_cap = o_.backfill_bytes;
         if (inflight_ + reqs_[*pick].bytes > o_.hbm_budget) {
             if (o_.backfill_bytes == 0) return false;
+            bf_cap = std::min(bf_cap, o_.hbm_budget - reqs_[*pick].bytes);
             for (++pick; pick != queue_.end(); ++pick) {
                 const SReq& r = reqs_[*pick];
-                if (r.bytes + backfill_inflight_ <= o_.backfill_bytes && inflight_ + r.bytes <= o_.hbm_budget) break;
+                if (r.bytes + backfill_inflight_ <= bf_cap && inflight_ + r.bytes <= o_.hbm_budget) break;
             }
             if (pick == queue_.end()) return false;
             backfill = true;
@@ -129,7 +134,7 @@ public:
         if (head.coalescible && o_.max_coalesce > 1) {
             for (auto it = backfill ? after : queue_.begin(); it != queue_.end() && (int)L->reqs.size() < o_.max_coalesce;) {
                 const SReq& r = reqs_[*it];
-                const bool room = backfill ? backfill_inflight_ + L->bytes + r.bytes <= o_.backfill_bytes : true;
+                const bool room = backfill ? backfill_inflight_ + L->bytes + r.bytes <= bf_cap : true;
                 if (r.coalescible && r.n == L->n && r.dir == L->dir && L->batch + r.batch <= o_.max_transforms &&
                     room && inflight_ + L->bytes + r.bytes <= o_.hbm_budget) {
                     L->reqs.push_back(r.id);
@@ -492,6 +497,7 @@ private:
 
 struct SrvReq {
     const float2* in = nullptr;
+    hipEvent_t ready = nullptr;  // recorded on the submitter's stream: the input is written
     size_t out_off = 0, out_bytes = 0;
     size_t ws_off = 0, ws_bytes = 0;
     bool has_out = false, has_ws = false;
@@ -523,6 +529,7 @@ struct fft_server_s {
     std::map<std::pair<size_t, int>, fft_plan_t> plans;
     std::deque<InFlight> inflight;
     std::vector<hipEvent_t> event_pool;
+    std::vector<hipEvent_t> ready_pool;  // input-ready events (no timing)
     std::unordered_map<uint64_t, SrvReq> reqs;
     uint64_t next_id = 1;
     std::thread worker;
@@ -594,6 +601,16 @@ bool plan_has_list(fft_plan_t p)
     return list;
 }
 
+// The request's input-ready event back to the pool (its launch has completed,
+// or it was never issued).
+void drop_ready(fft_server_s* s, SrvReq& r)
+{
+    if (r.ready) {
+        s->ready_pool.push_back(r.ready);
+        r.ready = nullptr;
+    }
+}
+
 void free_request_memory(fft_server_s* s, SrvReq& r, bool out_too)
 {
     if (r.has_ws) {
@@ -653,7 +670,13 @@ bool issue(fft_server_s* s, const SLaunch& L)
     }
     hipStream_t stream = s->streams[(size_t)L.stream];
     hipError_t e = hipSuccess;
-    if (list) {
+    // the launch reads each request's input only after the work the submitter
+    // had queued on its stream before submitting (the producer of the input)
+    for (uint64_t id : L.reqs) {
+        const SrvReq& r = s->reqs[id];
+        if (e == hipSuccess && r.ready) e = hipStreamWaitEvent(stream, r.ready, 0);
+    }
+    if (e == hipSuccess && list) {
         const size_t cap = s->opts.sched.max_transforms;
         fb::ListEnt* h = s->host_desc + (size_t)chunk * cap;
         fb::ListEnt* d = s->dev_desc + (size_t)chunk * cap;
@@ -665,7 +688,7 @@ bool issue(fft_server_s* s, const SLaunch& L)
         }
         e = hipMemcpyAsync(d, h, at * sizeof(fb::ListEnt), hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = fb::plan_launch_list(plan, d, (long long)at, stream);
-    } else {
+    } else if (e == hipSuccess) {
         for (uint64_t id : L.reqs) {
             SrvReq& r = s->reqs[id];
             void* out = s->arena_base + r.out_off;
@@ -708,6 +731,7 @@ void finish_launch(fft_server_s* s, InFlight& f, double t_done)
     (void)s->sched.complete(f.L.id, t_done, &done);
     for (uint64_t id : done) {
         SrvReq& r = s->reqs[id];
+        drop_ready(s, r);
         free_request_memory(s, r, s->opts.auto_release != 0);
         (void)s->sched.info(id, &r.info);
         r.done = true;
@@ -769,6 +793,9 @@ void server_free(fft_server_s* s)
 {
     for (auto& kv : s->plans) (void)fft_plan_destroy(kv.second);
     for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s->ready_pool) (void)hipEventDestroy(e);
+    for (auto& kv : s->reqs)
+        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
     for (auto& f : s->inflight)
         if (f.done) (void)hipEventDestroy(f.done);
     if (s->ref) (void)hipEventDestroy(s->ref);
@@ -849,7 +876,7 @@ fft_status_t fft_server_prepare(fft_server_t s, size_t n, int direction)
 }
 
 fft_status_t fft_server_submit(fft_server_t s, size_t n, size_t batch, int direction, const void* in,
-                               uint64_t* ticket)
+                               void* stream, uint64_t* ticket)
 {
     if (!live(s)) return FFT_ERR_INVALID_PLAN;
     if (!ticket || !in || ((uintptr_t)in & 7u) || n == 0 || batch == 0) return FFT_ERR_INVALID_ARG;
@@ -869,12 +896,30 @@ fft_status_t fft_server_submit(fft_server_t s, size_t n, size_t batch, int direc
     if (part * (four ? 2 : 1) > s->opts.arena_bytes) return FFT_ERR_OUT_OF_MEMORY;
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->error != FFT_SUCCESS) return s->error;
+    // mark the submitter's stream: the server's launch waits for this point
+    hipEvent_t ready = nullptr;
+    if (!s->ready_pool.empty()) {
+        ready = s->ready_pool.back();
+        s->ready_pool.pop_back();
+    } else {
+        const hipError_t e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+        if (e != hipSuccess) return st_of(e);
+    }
+    const hipError_t er = hipEventRecord(ready, (hipStream_t)stream);
+    if (er != hipSuccess) {
+        s->ready_pool.push_back(ready);
+        return st_of(er);
+    }
     const uint64_t id = s->next_id++;
     // a list launch exists for every default single-block length
     st = s->sched.submit(id, n, batch, direction, bytes, !four, s->now());
-    if (st != FFT_SUCCESS) return st;
+    if (st != FFT_SUCCESS) {
+        s->ready_pool.push_back(ready);
+        return st;
+    }
     SrvReq r;
     r.in = (const float2*)in;
+    r.ready = ready;
     (void)s->sched.info(id, &r.info);
     s->reqs[id] = r;
     *ticket = id;
@@ -925,6 +970,7 @@ fft_status_t fft_server_release(fft_server_t s, uint64_t ticket)
     if (it == s->reqs.end()) return FFT_ERR_INVALID_ARG;
     SrvReq& r = it->second;
     if (!r.done && r.info.state != FFT_REQ_REJECTED) return FFT_ERR_INVALID_ARG;  // still queued or running
+    drop_ready(s, r);
     free_request_memory(s, r, true);
     s->sched.forget(ticket);
     s->reqs.erase(it);

@@ -259,7 +259,7 @@ def load():
     lib.fft_server_opts_init.restype = None
     lib.fft_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
     lib.fft_server_prepare.argtypes = [vp, sz, i]
-    lib.fft_server_submit.argtypes = [vp, sz, sz, i, vp, ctypes.POINTER(u64)]
+    lib.fft_server_submit.argtypes = [vp, sz, sz, i, vp, vp, ctypes.POINTER(u64)]
     lib.fft_server_wait.argtypes = [vp, u64, dbl, ctypes.POINTER(vp), ctypes.POINTER(RequestInfo)]
     lib.fft_server_release.argtypes = [vp, u64]
     lib.fft_server_read.argtypes = [vp, u64, vp, vp]

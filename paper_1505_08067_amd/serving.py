@@ -140,15 +140,22 @@ class Server:
     def prepare(self, n: int, direction: int = fb.FORWARD):
         fb._check(fb.load().fft_server_prepare(self._h, n, direction), f"fft_server_prepare({n})")
 
-    def submit_ptr(self, ptr: int, n: int, batch: int, direction: int = fb.FORWARD) -> int:
+    def submit_ptr(self, ptr: int, n: int, batch: int, direction: int = fb.FORWARD, stream=None) -> int:
+        """Queue batch transforms of length n at device pointer ``ptr``.  The
+        server's launch waits for the work queued on ``stream`` (a raw
+        hipStream_t handle; None = torch's current stream) before the call."""
+        import torch
+        sh = torch.cuda.current_stream().cuda_stream if stream is None else stream
         t = ctypes.c_uint64()
-        fb._check(fb.load().fft_server_submit(self._h, n, batch, direction, ctypes.c_void_p(ptr), ctypes.byref(t)),
-                  "fft_server_submit")
+        fb._check(fb.load().fft_server_submit(self._h, n, batch, direction, ctypes.c_void_p(ptr),
+                                              ctypes.c_void_p(sh), ctypes.byref(t)), "fft_server_submit")
         return t.value
 
     def submit(self, x, n: int, batch: int, direction: int = fb.FORWARD) -> int:
         """Queue the transform of ``x`` (complex64 CUDA tensor of batch*n values,
-        kept alive and unchanged by the caller until the request completes)."""
+        kept alive and unchanged by the caller until the request completes).
+        The work torch has queued on its current stream (what writes ``x``)
+        completes before the server reads it."""
         fb._check_tensor(x, "x")
         if x.numel() != n * batch:
             raise ValueError("x has the wrong size")

@@ -256,7 +256,7 @@ def test_every_handle_entry_point_rejects_null_and_unknown_handles():
         assert lib.fft_ragged_destroy(h) == 5
         assert lib.fft_sched_submit(h, 1, 8, 1, -1, 16, 1, 0.0) == 5
         assert lib.fft_sched_destroy(h) == 5
-        assert lib.fft_server_submit(h, 8, 1, -1, vp(16), ctypes.byref(u64)) == 5
+        assert lib.fft_server_submit(h, 8, 1, -1, vp(16), None, ctypes.byref(u64)) == 5
         assert lib.fft_server_wait(h, 1, 0.0, None, None) == 5
         assert lib.fft_server_release(h, 1) == 5
         assert lib.fft_server_drain(h, 0.0) == 5

@@ -41,6 +41,34 @@ def test_execute_ex_batch_and_workspace():
         metrics.check(y.cpu().numpy(), oracle.fft(x.astype(np.complex128)), n)
 
 
+def test_submit_waits_for_the_producer_on_the_callers_stream():
+    # The input is written on a side torch stream, behind about 2 ms of other
+    # work, and submitted at once from that stream without synchronising: the
+    # server's launch must wait for the copy (an event on the submitter's
+    # stream), or it would transform the zeros the buffer held before.
+    n, b = 4096, 64
+    x = inputs.uniform(77, b, n)
+    src = torch.from_numpy(x).to("cuda")
+    ref = oracle.fft(x.astype(np.complex128))
+    side = torch.cuda.Stream()
+    with sv.Server(hbm_budget=1 << 30, n_streams=4) as srv:
+        srv.prepare(n, fb.FORWARD)
+        for rep in range(3):
+            say(f"case: submit from a side stream, repetition {rep}")
+            buf = torch.zeros_like(src)
+            junk = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+            torch.cuda.synchronize()
+            with torch.cuda.stream(side):
+                for _ in range(20):
+                    junk.mul_(1.0001)
+                buf.copy_(src)
+                t = srv.submit(buf, n, b, fb.FORWARD)
+            y, info = srv.result(t)
+            torch.cuda.synchronize()
+            metrics.check(y.cpu().numpy(), ref, n)
+            del buf, junk
+
+
 def _mix(seed, count, sizes, max_batch):
     rng = np.random.default_rng(seed)
     return [(int(rng.choice(sizes)), int(rng.integers(1, max_batch + 1)), int(rng.choice([-1, 1])))

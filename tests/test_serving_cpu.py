@@ -73,6 +73,39 @@ def test_bounded_backfill_past_a_waiting_head():
         assert st["backfilled_requests"] == 2
 
 
+def test_backfill_never_starves_a_large_head():
+    # budget 1000, backfill 500, a head of 800 bytes: backfill in flight is
+    # capped at 1000 - 800 = 200, so a continuous stream of small requests
+    # cannot keep the head out once the request launched before it completes
+    with sv.Scheduler(hbm_budget=1000, n_streams=4, max_inflight=64, max_coalesce=1, backfill_bytes=500) as s:
+        s.submit(1, 64, 1, F, 300, False, 0.0)
+        a = s.next(0.0)
+        assert a["requests"] == [1]
+        s.submit(2, 128, 1, F, 800, False, 0.0)     # the head: waits behind 1
+        running, rid, t = [], 100, 0.0
+        for step in range(40):
+            t += 0.01
+            for _ in range(3):                      # small requests keep arriving
+                s.submit(rid, 256, 1, F, 100, False, t)
+                rid += 1
+            while True:
+                L = s.next(t)
+                if L is None:
+                    break
+                if L["requests"] == [2]:
+                    break
+                running.append(L)
+            assert sum(r["bytes"] for r in running) <= 200   # never more backfill than the head leaves
+            if L is not None and L["requests"] == [2]:
+                break
+            if running:                              # the oldest backfill completes
+                s.complete(running.pop(0)["id"], t)
+            if step == 10:
+                s.complete(a["id"], t)               # the work ahead of the head completes
+        assert s.request(2)["state"] == fb.REQ_RUNNING
+        assert s.request(2)["t_launch"] <= 0.13
+
+
 def test_oversized_request_is_rejected_and_others_proceed():
     with sv.Scheduler(hbm_budget=1000) as s:
         s.submit(1, 64, 1, F, 5000, True, 0.0)
