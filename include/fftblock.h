@@ -55,7 +55,8 @@ typedef enum {
     FFT_ERR_OUT_OF_MEMORY = 3,     /* hipMalloc failed */
     FFT_ERR_DEVICE = 4,            /* any other HIP runtime error (launch, copy, device query) */
     FFT_ERR_INVALID_PLAN = 5,      /* null or destroyed plan (or scheduler / server) handle */
-    FFT_ERR_TIMEOUT = 6            /* a wait of the serving layer ran out of time */
+    FFT_ERR_TIMEOUT = 6,           /* a wait of the serving layer ran out of time */
+    FFT_ERR_SCRATCH_LIMIT = 7      /* fft_execute_static: the workspace exceeds the static scratch */
 } fft_status_t;
 
 /* Direction = sign of the exponent in the definition above. */
@@ -300,6 +301,26 @@ fft_status_t fft_plan_describe(fft_plan_t plan, fft_plan_desc_t* desc);
  */
 fft_status_t fft_execute_ex(fft_plan_t plan, size_t batch, const void* in, void* out, void* workspace,
                             void* stream);
+
+/*
+ * fft_execute_static -- fft_execute_ex whose four-step workspace is the
+ * library's own static device array (fft_static_scratch_bytes() = 64 MiB per
+ * GPU, held from module load until the process ends) instead of the plan's
+ * or a caller's buffer.  For callers that cannot allocate device memory at
+ * execute time (code under HIP graph capture, tight serving loops,
+ * allocation-free harnesses): the call makes no hipMalloc/hipFree or other
+ * allocating call; the plan (created beforehand, e.g. with batch 1) supplies
+ * only its tables.  The caller still passes in and out (DEVICE pointers, as
+ * fft_execute).  batch: transforms of this call (0 = the plan's).
+ * Single-block plans need no workspace and run exactly as fft_execute_ex.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (two streams, two threads) race on it and must be ordered by
+ * the caller.  Pass 1 writes every workspace value pass 2 reads, so nothing
+ * needs clearing between calls.  Returns SCRATCH_LIMIT when n * batch * 8
+ * bytes exceed the array (nothing is launched), else as fft_execute_ex.
+ */
+fft_status_t fft_execute_static(fft_plan_t plan, size_t batch, const void* in, void* out, void* stream);
+size_t fft_static_scratch_bytes(void);
 
 /* Copy the plan's twiddle table (complex64 entries) to host memory: the
  * number of entries goes to *n_entries; with host_dst NULL only the count is

@@ -333,6 +333,7 @@ const char* fft_status_string(fft_status_t s)
         case FFT_ERR_DEVICE: return "HIP runtime error";
         case FFT_ERR_INVALID_PLAN: return "invalid plan handle";
         case FFT_ERR_TIMEOUT: return "timed out";
+        case FFT_ERR_SCRATCH_LIMIT: return "request exceeds the library's static scratch buffer";
     }
     return "unknown status";
 }
@@ -1015,6 +1016,64 @@ fft_status_t fft_copy(const void* in, void* out, size_t bytes, void* stream)
     const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
     if (a < b + bytes && b < a + bytes) return FFT_ERR_INVALID_ARG;
     return from_hip(launch_copy(in, out, bytes, (hipStream_t)stream));
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ allocation-free execute
+// The four-step workspace of fft_execute_static: one fixed array in the code
+// object, so the call allocates nothing.  Each GPU the library runs on holds
+// its own copy (64 MiB, zero at module load) until the process ends; in host
+// code the name `scratch` is only a stand-in, so the device address of each
+// copy is looked up once per device and kept.
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) float2 scratch[kScratchBytes / sizeof(float2)];
+
+std::mutex g_scratch_mu;
+std::vector<std::pair<int, float2*>> g_scratch_at;  // (device, address of its copy)
+
+// Address of the calling thread's current device's copy of `scratch`.
+hipError_t scratch_address(int device, float2** out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    for (const auto& d : g_scratch_at)
+        if (d.first == device) {
+            *out = d.second;
+            return hipSuccess;
+        }
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (p == nullptr) return hipErrorInvalidSymbol;
+    g_scratch_at.emplace_back(device, static_cast<float2*>(p));
+    *out = static_cast<float2*>(p);
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fft_static_scratch_bytes(void) { return kScratchBytes; }
+
+fft_status_t fft_execute_static(fft_plan_t plan, size_t batch, const void* in, void* out, void* stream)
+{
+    if (!plan_live(plan)) return FFT_ERR_INVALID_PLAN;
+    if (in == nullptr || out == nullptr) return FFT_ERR_INVALID_ARG;
+    if (plan->path != FFT_PATH_FOURSTEP) return execute_impl(plan, 0, batch, in, out, nullptr, stream);
+    const size_t b = batch ? batch : plan->batch;
+    if (b > kScratchBytes / sizeof(float2) / plan->n) return FFT_ERR_SCRATCH_LIMIT;
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return from_hip(e);
+    if (cur != plan->device && (e = hipSetDevice(plan->device)) != hipSuccess) return from_hip(e);
+    float2* ws = nullptr;
+    e = scratch_address(plan->device, &ws);
+    if (cur != plan->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return from_hip(e);
+    return execute_impl(plan, 0, b, in, out, ws, stream);
 }
 
 fft_status_t fft_device_query(int device, fft_device_info_t* info)

@@ -30,6 +30,8 @@ STATUS = {
     3: "FFT_ERR_OUT_OF_MEMORY",
     4: "FFT_ERR_DEVICE",
     5: "FFT_ERR_INVALID_PLAN",
+    6: "FFT_ERR_TIMEOUT",
+    7: "FFT_ERR_SCRATCH_LIMIT",
 }
 
 # Every symbol include/fftblock.h declares.
@@ -46,6 +48,7 @@ EXPORTS = (
     "fft_execute_pass_timed", "fft_event_create", "fft_event_destroy", "fft_event_elapsed",
     "fft_server_opts_init", "fft_server_create", "fft_server_prepare", "fft_server_submit", "fft_server_wait",
     "fft_server_read", "fft_server_release", "fft_server_drain", "fft_server_stats", "fft_server_clock", "fft_server_destroy",
+    "fft_execute_static", "fft_static_scratch_bytes",
 )
 
 VARIANT_NT_LOAD = 1
@@ -216,6 +219,9 @@ def load():
     lib.fft_plan_query_ex.argtypes = [sz, sz, i, ctypes.POINTER(PlanOpts), ctypes.POINTER(PlanDesc)]
     lib.fft_filter_create.argtypes = [sz, sz, vp, sz, ctypes.POINTER(PlanOpts), ctypes.POINTER(vp)]
     lib.fft_execute_ex.argtypes = [vp, sz, vp, vp, vp, vp]
+    lib.fft_execute_static.argtypes = [vp, sz, vp, vp, vp]
+    lib.fft_static_scratch_bytes.argtypes = []
+    lib.fft_static_scratch_bytes.restype = sz
     lib.fft_execute_pass_timed.argtypes = [vp, i, vp, vp, vp, vp, vp]
     lib.fft_event_create.argtypes = [ctypes.POINTER(vp)]
     lib.fft_event_destroy.argtypes = [vp]
