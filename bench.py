@@ -566,9 +566,11 @@ def run_fp16(torch, fb, inputs, stream):
     torch.cuda.synchronize()
     log(f"fp16 ragged buffers x={x.data_ptr():#x} y={y.data_ptr():#x} bytes={4 * total}")
     with fb.Ragged(classes, fb.FORWARD, storage=fb.STORAGE_F16) as r:
-        t = _timed(torch, stream, lambda: r.execute(x, out=y))
+        t = _timed(torch, stream, lambda: r.execute(x, out=y), reps=20)
+        t_plain = _timed(torch, stream, lambda: r.execute(x, out=y, mode=fb.RAGGED_PLAIN), reps=20)
     fl = sum(5.0 * n * math.log2(n) * c for n, c in classes)
-    res["ragged_mix"] = {"total_points": total, "t_graph_us": round(t * 1e6, 1), "GFLOPs": round(fl / t / 1e9, 1)}
+    res["ragged_mix"] = {"total_points": total, "t_graph_us": round(t * 1e6, 1), "GFLOPs": round(fl / t / 1e9, 1),
+                         "t_plain_sequential_us": round(t_plain * 1e6, 1)}
     log("fp16", json.dumps(res))
     return res
 
@@ -626,9 +628,11 @@ def run_ragged(torch, fb, inputs, stream):
     """The ragged mix: 15 lengths with an equal share of about 2^28 points.
 
     Each length is autotuned first (the paper's stage model plus whole-kernel
-    validation; the fastest kernel becomes the wisdom the plans use).  Then the
-    whole mix runs as one graph launch and is compared with the plain path:
-    every length as its own batched execute, timed separately and summed.
+    validation; the fastest kernel becomes the wisdom the plain plans use).
+    Then the whole mix runs as one graph of persistent work-list kernels (one
+    launch per LDS-footprint class) and is compared with the plain path: every
+    length as its own batched execute, timed separately and summed; the
+    per-length kernels on four graph branches are timed beside it.
     """
     sizes = inputs.ragged_sizes(3)
     classes = [(int(n), int((sizes == n).sum())) for n in inputs.RAGGED_POW2 + inputs.RAGGED_MIXED]
@@ -669,14 +673,18 @@ def run_ragged(torch, fb, inputs, stream):
         t_plain += t
         at += n * c
     with fb.Ragged(classes, fb.FORWARD) as r:
-        # the first launches of a freshly captured graph run slower: warm it up
-        t_graph = timed(lambda: r.execute(x, out=y), reps=20, warm=10)
-        t_seq = timed(lambda: r.execute(x, out=y, graph=False), reps=20, warm=10)
-        nodes = r.describe()["graph_nodes"]
+        # the first launches of a freshly built graph run slower: warm it up
+        t_graph = timed(lambda: r.execute(x, out=y, mode=fb.RAGGED_PERSISTENT), reps=20, warm=10)
+        t_branch = timed(lambda: r.execute(x, out=y, mode=fb.RAGGED_BRANCHES), reps=20, warm=10)
+        t_seq = timed(lambda: r.execute(x, out=y, mode=fb.RAGGED_PLAIN), reps=20, warm=10)
+        d = r.describe()
     fl = sum(5.0 * n * math.log2(n) * c for n, c in classes)
     res = {
-        "classes": [[n, c] for n, c in classes], "total_points": total, "graph_nodes": nodes,
+        "classes": [[n, c] for n, c in classes], "total_points": total,
+        "graph_nodes": d["kernel_nodes"], "persistent_launches": d["persistent_launches"],
         "t_plain_sum_us": round(t_plain * 1e6, 1), "t_graph_us": round(t_graph * 1e6, 1),
+        "t_per_length_branch_graph_us": round(t_branch * 1e6, 1),
+        "per_length_branch_graph_nodes": d["branch_graph_nodes"],
         "t_sequential_us": round(t_seq * 1e6, 1),
         "ratio_plain_over_graph": round(t_plain / t_graph, 3),
         "graph_GFLOPs": round(fl / t_graph / 1e9, 1),

@@ -473,19 +473,30 @@ fft_status_t fft_filter_query(size_t n, size_t batch, size_t replica_len, const 
                               fft_plan_desc_t* desc);
 
 /* ---------------------------------------------------------------------------
- * Ragged batches: transforms of several lengths in one submission (the
- * paper's top-level analysis submits one batch of one size; here the lengths
- * of a mix each get the schedule the autotuner measured best for them).
+ * Ragged batches: transforms of several lengths in one submission (paper,
+ * Approach, "Top level analysis": many independent FFT tasks, each reading its
+ * inputs, computing and writing its outputs, mapped onto the compute units).
  * ------------------------------------------------------------------------- */
 typedef struct fft_ragged_s* fft_ragged_t;
 
 /*
  * fft_ragged_create -- plan n_classes batches: counts[c] transforms of length
  * sizes[c] each, all in `direction`, on the current device.  Every length must
- * be one fft_plan_create accepts; each class gets an ordinary plan (which uses
- * the autotuner's wisdom for its length).  Data layout for execute: the
- * classes' batches concatenated in the given order, class c starting at
- * complex element sum_{j<c} sizes[j] * counts[j].
+ * be one fft_plan_create accepts.  Data layout for execute: the classes'
+ * batches concatenated in the given order, class c starting at complex
+ * element sum_{j<c} sizes[j] * counts[j].
+ *
+ * Each class is matched to a case of a persistent work-list kernel (one per
+ * LDS-footprint class: lengths up to 8192, 1000, 3072 and 256-point four-step
+ * rows in a 256-thread kernel with four workgroups per CU; 6000, 15360,
+ * 16384, 32768 and 256-point four-step columns in a 512-thread kernel with
+ * one workgroup per CU).  The classes of one kernel form one launch whose
+ * resident workgroups take work units (a workgroup's share of transforms, or
+ * a four-step tile) from one device queue, largest units first; a four-step
+ * length (65536 = 256 x 256) has its pass-1 tiles in the first launch and its
+ * pass-2 tiles in the second.  A length no case covers runs its own plan's
+ * kernels beside them.  Allocates the classes' plans (tables, four-step
+ * workspaces), the work lists and two counters per launch.
  */
 fft_status_t fft_ragged_create(const size_t* sizes, const size_t* counts, size_t n_classes, int direction,
                                fft_ragged_t* out);
@@ -499,16 +510,38 @@ fft_status_t fft_ragged_create_ex(const size_t* sizes, const size_t* counts, siz
 /*
  * fft_ragged_execute -- transform every class from `in` to `out` on `stream`
  * (device pointers aligned to the element size, in == out allowed, other overlap
- * INVALID_ARG).  mode 0: one hipGraphLaunch of a graph holding every class's
- * kernels on parallel branches (captured on the first call with this (in, out)
- * pair, re-captured when the pair changes); mode 1: the classes' kernels
- * launched one after another on `stream` (the plain path).  Asynchronous.
+ * INVALID_ARG).  Asynchronous.
+ *   mode 0: one hipGraphLaunch of a graph whose kernel nodes are the
+ *           persistent launches (in sequence) and any uncovered class's
+ *           kernels; built on the first call, and on a call with other
+ *           buffers only the nodes' arguments change.  Launches of one plan
+ *           must not overlap in time (they share the queue counters).
+ *   mode 1: the plain path -- every class through its own default plan (the
+ *           autotuner's wisdom for its length), one after another on `stream`.
+ *   mode 2: those default plans' kernels in one graph on four parallel
+ *           branches (re-captured when the buffers change).
  */
 fft_status_t fft_ragged_execute(fft_ragged_t r, const void* in, void* out, void* stream, int mode);
 
-/* Total complex values of one execute, and nodes of the captured graph (0
- * before the first graph execute).  Either pointer may be NULL. */
+/* Total complex values of one execute, and kernel nodes of the mode-0 graph
+ * (0 before its first execute).  Either pointer may be NULL. */
 fft_status_t fft_ragged_describe(fft_ragged_t r, size_t* total_points, size_t* graph_nodes);
+
+typedef struct {
+    size_t total_points;
+    int graph_nodes;            /* kernel nodes of the mode-0 graph */
+    int persistent_launches;    /* of which persistent work-list kernels (at most 8 described) */
+    int fallback_classes;       /* classes run by their own plan's kernels */
+    const char* kernel_name[8]; /* per persistent launch, in launch order */
+    unsigned units[8];          /* work units of the launch */
+    unsigned grid[8];           /* workgroups launched (the resident capacity, at most units) */
+    int classes[8];             /* length classes (four-step passes count once each) */
+    int threads[8];             /* workgroup size */
+    size_t lds_bytes[8];        /* static LDS per workgroup */
+    size_t branch_graph_nodes;  /* nodes of the mode-2 graph (0 before its first execute) */
+} fft_ragged_desc_t;
+
+fft_status_t fft_ragged_describe_ex(fft_ragged_t r, fft_ragged_desc_t* desc);
 
 /* Synchronise the device and free the plans, graph, streams and events. */
 fft_status_t fft_ragged_destroy(fft_ragged_t r);

@@ -160,18 +160,23 @@ using PolBlock = PolBlockT<float2, float2>;
 using PolBlockH = PolBlockT<h2_t, h2_t>;
 
 // List launches: transform b of the launch reads and writes where its
-// descriptor points (the block layout otherwise).
+// descriptor points (the block layout otherwise).  The descriptors are read
+// through the constant address space: pointers loaded from it are taken to
+// address global memory, so the data accesses are global instructions (a
+// pointer loaded from ordinary memory could point anywhere, and accesses
+// through it would be flat ones, which also hold up every LDS wait).
 struct PolList : PolBlock {
     static constexpr int kind = kKindList;
     template <int N, int C>
     __device__ static Ctx ctx(const KArgs& a, long long unit, int f)
     {
+        using ListEntC = __attribute__((address_space(4))) const ListEnt;
         const long long b = unit * C + f;
         Ctx c;
         c.act = b < a.batch;
-        const ListEnt e = reinterpret_cast<const ListEnt*>(a.list)[c.act ? b : 0];
-        c.src = e.in;
-        c.dst = e.out;
+        ListEntC* e = (ListEntC*)a.list + (c.act ? b : 0);
+        c.src = e->in;
+        c.dst = e->out;
         return c;
     }
 };
@@ -389,9 +394,12 @@ __device__ __forceinline__ void apply_lds_tw(float2* v, const float2* Ltw, int k
     }
 }
 
+// on: this thread takes part (false for the idle threads of a persistent
+// kernel whose workgroup is wider than the case it runs: they keep to every
+// barrier but write nothing).
 template <int N, int E, class S, int FL, bool WS = false>
 __device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const float2* __restrict__ tw,
-                                           const float2* Ltw, int t)
+                                           const float2* Ltw, int t, bool on = true)
 {
     constexpr int T = N / E;
     constexpr int NST = S::count;
@@ -422,12 +430,14 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const floa
         for (int i = 0; i < E / R; ++i) Dft<R>::run(&v[i * R]);
         if constexpr (s < NST - 1 && (FL & kHalfX) == 0) {
             if constexpr (s > 0) exch_sync<WS>();
+            if (on) {
 #pragma unroll
-            for (int i = 0; i < E / R; ++i) {
-                const int j = t + i * T;
-                const int base = (j / Ns) * Ns * R + (j % Ns);
+                for (int i = 0; i < E / R; ++i) {
+                    const int j = t + i * T;
+                    const int base = (j / Ns) * Ns * R + (j % Ns);
 #pragma unroll
-                for (int q = 0; q < R; ++q) L[lds_at<FL>(base + q * Ns)] = v[i * R + q];
+                    for (int q = 0; q < R; ++q) L[lds_at<FL>(base + q * Ns)] = v[i * R + q];
+                }
             }
             exch_sync<WS>();
         } else if constexpr (s < NST - 1) {
@@ -445,12 +455,14 @@ __device__ __forceinline__ void run_stages(float2 (&v)[E], float2* L, const floa
             sfor<0, 2>([&](auto hc) {
                 constexpr int h = decltype(hc)::value;
                 if constexpr (h > 0 || s > 0) exch_sync<WS>();  // earlier reads precede these writes
+                if (on) {
 #pragma unroll
-                for (int i = h * (E / (2 * R)); i < (h + 1) * (E / (2 * R)); ++i) {
-                    const int j = t + i * T;
-                    const int base = (j / Ns) * Ns * R + (j % Ns) - h * (N / 2);
+                    for (int i = h * (E / (2 * R)); i < (h + 1) * (E / (2 * R)); ++i) {
+                        const int j = t + i * T;
+                        const int base = (j / Ns) * Ns * R + (j % Ns) - h * (N / 2);
 #pragma unroll
-                    for (int q = 0; q < R; ++q) L[lds_at<FL>(base + q * Ns)] = v[i * R + q];
+                        for (int q = 0; q < R; ++q) L[lds_at<FL>(base + q * Ns)] = v[i * R + q];
+                    }
                 }
                 exch_sync<WS>();
 #pragma unroll
@@ -500,35 +512,43 @@ __host__ __device__ constexpr int k_min_waves()
     return waves < 1 ? 1 : waves > 8 ? 8 : waves;
 }
 
+// One work unit of a transform kernel (C transforms, or C columns / rows of
+// a four-step pass), shared by the one-unit-per-workgroup kernel k_fft, its
+// looping variants and the persistent ragged kernels.  `lds` holds the C
+// exchange buffers (and, for kPipe, the factorised twiddles at TWB); `on` is
+// false for the idle threads of a workgroup wider than T * C: they keep to
+// every barrier of the unit but read and write no global memory and write no
+// LDS.
 template <int N, int E, int C, class S, class P, int FL>
-__global__ void __launch_bounds__((N / E) * C)
-__attribute__((amdgpu_waves_per_eu(k_min_waves<N, E, C, S, FL, P::f_fast>())))
-k_fft(KArgs a)
-{
-    constexpr int T = N / E;
-    constexpr int NST = S::count;
-    constexpr int LDSN = lds_stride<lds_points<N, FL>(), FL, P::f_fast, C, T>();
-    constexpr int R0 = S::r(0);
-    constexpr int RL = S::r(NST - 1);
-    constexpr int NsL = S::ns(NST - 1);
-    static_assert(S::n() == N, "schedule does not multiply to N");
-    constexpr int TWB = k_tw_base<N, C, S, FL, P::f_fast, T>();
+struct FftBody {
+    static constexpr int T = N / E;
+    static constexpr int threads = T * C;
+    static constexpr int NST = S::count;
+    static constexpr int LDSN = lds_stride<lds_points<N, FL>(), FL, P::f_fast, C, T>();
+    static constexpr int R0 = S::r(0);
+    static constexpr int RL = S::r(NST - 1);
+    static constexpr int NsL = S::ns(NST - 1);
+    static constexpr int TWB = k_tw_base<N, C, S, FL, P::f_fast, T>();
+    static constexpr int lds_elems = k_lds_elems<N, C, S, FL, P::f_fast, T>();
     // wave-synchronous exchanges: t-fast lanes, whole transforms per wavefront
-    constexpr bool WS = (FL & kWaveSync) != 0 && !P::f_fast && T <= 64 && 64 % T == 0 && (FL & kPipe) == 0;
-    __shared__ __attribute__((aligned(16))) float2 lds[k_lds_elems<N, C, S, FL, P::f_fast, T>()];
+    static constexpr bool WS = (FL & kWaveSync) != 0 && !P::f_fast && T <= 64 && 64 % T == 0 && (FL & kPipe) == 0;
+    static_assert(S::n() == N, "schedule does not multiply to N");
 
-    const int tid = threadIdx.x;
-    int f = P::f_fast ? tid % C : tid / T;
-    int t = P::f_fast ? tid / C : tid % T;
-    float2* L = lds + (NST > 1 ? f * LDSN : 0);
-    float2* Ltw = lds + TWB;
+    // the thread's transform (or column / row) f and position t in it
+    __device__ static __forceinline__ void place(int tid, int& f, int& t)
+    {
+        f = P::f_fast ? tid % C : tid / T;
+        t = P::f_fast ? tid / C : tid % T;
+    }
 
     // The backward transform is conj(forward(conj(x))): the conjugations are
     // skipped by a uniform branch in the forward direction.
-    const bool bwd = a.sg < 0.f;
-    auto load = [&](float2(&v)[E], long long unit) {
+    __device__ static __forceinline__ void load(const KArgs& a, long long unit, int f, int t, bool on,
+                                                float2 (&v)[E])
+    {
+        const bool bwd = a.sg < 0.f;
         const auto cx = P::template ctx<N, C>(a, unit, f);
-        if (cx.act) {
+        if (cx.act && on) {
 #pragma unroll
             for (int i = 0; i < E / R0; ++i)
 #pragma unroll
@@ -544,9 +564,15 @@ k_fft(KArgs a)
                 for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
             }
         }
-    };
-    auto finish = [&](float2(&v)[E], long long unit) {
-        run_stages<N, E, S, FL, WS>(v, L, a.tw, Ltw, t);
+    }
+
+    __device__ static __forceinline__ void finish(const KArgs& a, long long unit, float2* lds, int tid, int f,
+                                                  int t, bool on, float2 (&v)[E])
+    {
+        const bool bwd = a.sg < 0.f;
+        float2* L = lds + (NST > 1 ? f * LDSN : 0);
+        const float2* Ltw = lds + TWB;
+        run_stages<N, E, S, FL, WS>(v, L, a.tw, Ltw, t, on);
         static_assert(P::kind != kKindFilter || (FL & kHalfX) == 0, "the filter's round trip needs N slots");
         if constexpr (P::kind == kKindFilter) {
             // Z = X conj(H) is transformed back as conj(F(conj Z)), and
@@ -563,10 +589,12 @@ k_fft(KArgs a)
                 exch_sync<WS>();  // every read of the last stage precedes the next writes
                 if constexpr (R0 != RL) {
                     // natural order through LDS, then the stage-0 gather
+                    if (on) {
 #pragma unroll
-                    for (int i = 0; i < E / RL; ++i)
+                        for (int i = 0; i < E / RL; ++i)
 #pragma unroll
-                        for (int q = 0; q < RL; ++q) L[lds_at<FL>(t + i * T + q * NsL)] = v[i * RL + q];
+                            for (int q = 0; q < RL; ++q) L[lds_at<FL>(t + i * T + q * NsL)] = v[i * RL + q];
+                    }
                     exch_sync<WS>();
 #pragma unroll
                     for (int i = 0; i < E / R0; ++i)
@@ -576,7 +604,7 @@ k_fft(KArgs a)
                 }
                 // with R0 == RL the outputs already sit where stage 0 wants its inputs
             }
-            run_stages<N, E, S, FL, WS>(v, L, a.tw, Ltw, t);
+            run_stages<N, E, S, FL, WS>(v, L, a.tw, Ltw, t, on);
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
         }
@@ -590,27 +618,31 @@ k_fft(KArgs a)
             sfor<0, 2>([&](auto hc) {
                 constexpr int h = decltype(hc)::value;
                 __syncthreads();
+                if (on) {
 #pragma unroll
-                for (int i = 0; i < E / RL; ++i)
+                    for (int i = 0; i < E / RL; ++i)
 #pragma unroll
-                    for (int q = h * (RL / 2); q < (h + 1) * (RL / 2); ++q)
-                        L[lds_at<FL>(t + i * T + q * NsL - h * (N / 2))] = v[i * RL + q];
+                        for (int q = h * (RL / 2); q < (h + 1) * (RL / 2); ++q)
+                            L[lds_at<FL>(t + i * T + q * NsL - h * (N / 2))] = v[i * RL + q];
+                }
                 __syncthreads();
-                P::template staged_store<N / 2, C, FL, LDSN, T * C>(a, unit, lds, tid, h * (N / 2));
+                if (on) P::template staged_store<N / 2, C, FL, LDSN, T * C>(a, unit, lds, tid, h * (N / 2));
             });
         } else if constexpr ((FL & kStaged) != 0) {
             // outputs (twiddled) to LDS in natural order, then contiguous stores
             static_assert(P::kind == kKindPass1, "staged store is a pass-1 variant");
             __syncthreads();
+            if (on) {
 #pragma unroll
-            for (int i = 0; i < E / RL; ++i)
+                for (int i = 0; i < E / RL; ++i)
 #pragma unroll
-                for (int q = 0; q < RL; ++q) {
-                    const int k = t + i * T + q * NsL;
-                    L[lds_at<FL>(k)] = v[i * RL + q];
-                }
+                    for (int q = 0; q < RL; ++q) {
+                        const int k = t + i * T + q * NsL;
+                        L[lds_at<FL>(k)] = v[i * RL + q];
+                    }
+            }
             __syncthreads();
-            P::template staged_store<N, C, FL, LDSN, T * C>(a, unit, lds, tid, 0);
+            if (on) P::template staged_store<N, C, FL, LDSN, T * C>(a, unit, lds, tid, 0);
         } else {
             if constexpr (P::conj_out) {
                 if (bwd) {
@@ -618,14 +650,33 @@ k_fft(KArgs a)
                     for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
                 }
             }
-            if (cx.act) {
+            if (cx.act && on) {
+                // a copy of t the compiler cannot see through: otherwise it
+                // shares the store offsets t + i T + q NsL with the LDS
+                // indices of the stages and keeps them live all along
+                int ts = t;
+                asm volatile("" : "+v"(ts));
 #pragma unroll
                 for (int i = 0; i < E / RL; ++i)
 #pragma unroll
-                    for (int q = 0; q < RL; ++q) store_split<P, FL>(a, cx, t, i * T + q * NsL, v[i * RL + q]);
+                    for (int q = 0; q < RL; ++q) store_split<P, FL>(a, cx, ts, i * T + q * NsL, v[i * RL + q]);
             }
         }
-    };
+    }
+};
+
+template <int N, int E, int C, class S, class P, int FL>
+__global__ void __launch_bounds__((N / E) * C)
+__attribute__((amdgpu_waves_per_eu(k_min_waves<N, E, C, S, FL, P::f_fast>())))
+k_fft(KArgs a)
+{
+    using B = FftBody<N, E, C, S, P, FL>;
+    constexpr int T = B::T;
+    __shared__ __attribute__((aligned(16))) float2 lds[B::lds_elems];
+
+    const int tid = threadIdx.x;
+    int f, t;
+    B::place(tid, f, t);
 
     if constexpr ((FL & kLoop) != 0) {
         static_assert((FL & kPipe) == 0 && (FL & kXcd) == 0, "the loop form takes units in launch order");
@@ -640,24 +691,23 @@ k_fft(KArgs a)
             // live across it, which would spill
             int tl = tid;
             asm volatile("" : "+v"(tl));
-            f = P::f_fast ? tl % C : tl / T;
-            t = P::f_fast ? tl / C : tl % T;
-            L = lds + (NST > 1 ? f * LDSN : 0);
+            B::place(tl, f, t);
             float2 v[E];
-            load(v, u);
-            finish(v, u);
+            B::load(a, u, f, t, true, v);
+            B::finish(a, u, lds, tl, f, t, true, v);
             __syncthreads();  // the next unit's first LDS writes follow every thread's last LDS reads
         }
     } else if constexpr ((FL & kPipe) == 0) {
         float2 v[E];
         long long unit = blockIdx.x;
         if constexpr ((FL & kXcd) != 0) unit = xcd_unit(unit, gridDim.x);
-        load(v, unit);
-        finish(v, unit);
+        B::load(a, unit, f, t, true, v);
+        B::finish(a, unit, lds, tid, f, t, true, v);
     } else {
         const long long units = P::units(a, C);
         long long u = blockIdx.x;
         if (u >= units) return;
+        float2* Ltw = lds + B::TWB;
         constexpr int TWN = S::ftw_size();
         float2 twv[(TWN + T * C - 1) / (T * C) > 0 ? (TWN + T * C - 1) / (T * C) : 1];
 #pragma unroll
@@ -666,7 +716,7 @@ k_fft(KArgs a)
             if (i < TWN) twv[m] = a.tw[i];
         }
         float2 nx[E];
-        load(nx, u);
+        B::load(a, u, f, t, true, nx);
 #pragma unroll
         for (int m = 0; m * T * C < TWN; ++m) {
             const int i = tid + m * T * C;
@@ -677,8 +727,8 @@ k_fft(KArgs a)
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = nx[e];
             const long long un = u + gridDim.x;
-            if (un < units) load(nx, un);
-            finish(v, u);
+            if (un < units) B::load(a, un, f, t, true, nx);
+            B::finish(a, u, lds, tid, f, t, true, v);
             if (un >= units) break;
             u = un;
             __syncthreads();  // the next unit's first LDS writes follow every thread's last LDS reads
@@ -726,6 +776,7 @@ constexpr KEntry make_entry(bool is_default, const char* name)
     k.launch = &launch_fft<N, E, C, S, P, FL>;
     k.occupancy = &occupancy_fft<N, E, C, S, P, FL>;
     k.name = name;
+    k.fn = reinterpret_cast<const void*>(&k_fft<N, E, C, S, P, FL>);
     return k;
 }
 

@@ -978,6 +978,30 @@ hipError_t plan_launch_list(fft_plan_s* plan, const void* list, long long transf
     return e;
 }
 
+bool plan_launch_params(const fft_plan_s* p, int pass, const void* in, void* out, const KEntry** k, KArgs* a,
+                        long long* grid)
+{
+    if (p->path == FFT_PATH_FOURSTEP) {
+        if (pass == 1) {
+            *k = p->k1;
+            *a = make_args(p, 1, static_cast<const float2*>(in), p->work);
+            *grid = p->grid1;
+        } else if (pass == 2) {
+            *k = p->k2;
+            *a = make_args(p, 2, p->work, static_cast<float2*>(out));
+            *grid = p->grid2;
+        } else {
+            return false;
+        }
+        return *k != nullptr;
+    }
+    if (pass != 1 || p->n == 1 || !p->k1) return false;
+    *k = block_kernel(p, p->batch);
+    *a = make_args(p, 1, static_cast<const float2*>(in), static_cast<float2*>(out));
+    *grid = p->grid1;
+    return true;
+}
+
 void plan_shape(const fft_plan_s* plan, size_t* n, int* direction, int* path, bool* has_list)
 {
     *n = plan->n;

@@ -62,6 +62,7 @@ struct KEntry {
     KLaunch launch;
     KOccupancy occupancy;
     const char* name;
+    const void* fn;    // the kernel itself (graph kernel nodes)
 };
 
 // Work units a launch must cover (block: workgroups of c transforms;
@@ -114,6 +115,11 @@ hipError_t generate_twiddles_device(float2* dst, long long total, const TwSeg* s
 // List launch of a block plan's kernel: `transforms` descriptors at `list`
 // (device memory).  hipErrorNotSupported if the plan's kernel has no list form.
 hipError_t plan_launch_list(fft_plan_s* plan, const void* list, long long transforms, hipStream_t st);
+// Kernel, arguments and grid of launch `pass` (1, or 2 on the four-step
+// path) of a plan's own batch from in to out (the four-step workspace is the
+// plan's, between the passes).  false if the plan has no such launch.
+bool plan_launch_params(const fft_plan_s* plan, int pass, const void* in, void* out, const KEntry** k, KArgs* a,
+                        long long* grid);
 // Length, direction and path of a plan (for the serving layer).
 void plan_shape(const fft_plan_s* plan, size_t* n, int* direction, int* path, bool* has_list);
 

@@ -41,6 +41,15 @@ static const KEntry kBlock[] = {
     // other 32768 schedules (half exchanges)
     FB_BLK(false, 1059, 32768, 32, 1, 16, 16, 8, 16),
     FB_BLK(false, 1059, 32768, 32, 1, 8, 16, 16, 16),
+    // cases of the persistent ragged kernels that are no planner default:
+    // two 16384-point transforms per 1024-thread workgroup (half exchanges),
+    // 3072 with twelve values per thread (one 256-thread transform, five
+    // stages), and the FP16 forms of these and of the 256-thread 512 block
+    FB_BLK(false, 1059, 16384, 32, 2, 16, 4, 16, 16),
+    FB_BLK(false, 35, 3072, 12, 1, 12, 4, 4, 4, 4),
+    FB_BLKH(false, 1123, 16384, 32, 2, 16, 4, 16, 16),
+    FB_BLKH(false, 99, 3072, 12, 1, 12, 4, 4, 4, 4),
+    FB_BLKH(false, 99, 512, 16, 8, 16, 16, 2),
     // persistent workgroups looping over units (no prefetch)
     FB_BLK(false, 4131, 4096, 16, 1, 16, 16, 16),
     // eight values per thread: twice the waves per workgroup at the same LDS

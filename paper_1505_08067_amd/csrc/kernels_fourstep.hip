@@ -128,6 +128,10 @@ static const KEntry kPass[] = {
     FB_P2(false, 1, 1024, 16, 8, 16, 16, 4),
     FB_P2(false, 33, 1024, 16, 16, 16, 16, 4),
     FB_P2(false, 0, 2048, 16, 8, 16, 16, 8),
+    // 64 columns of 256 per 1024-thread workgroup (512-byte runs): pass 1 of
+    // the four-step lengths in the large persistent ragged kernel
+    FB_P1(false, 49, 256, 16, 64, 16, 16),
+    FB_P1H(false, 113, 256, 16, 64, 16, 16),
     // half-line tiles (found by explicit width only)
     FB_P1(false, 49, 512, 16, 8, 16, 16, 2),
     FB_P2(false, 33, 2048, 16, 4, 16, 16, 8),

@@ -48,7 +48,7 @@ EXPORTS = (
     "fft_execute_pass_timed", "fft_event_create", "fft_event_destroy", "fft_event_elapsed",
     "fft_server_opts_init", "fft_server_create", "fft_server_prepare", "fft_server_submit", "fft_server_wait",
     "fft_server_read", "fft_server_release", "fft_server_drain", "fft_server_stats", "fft_server_clock", "fft_server_destroy",
-    "fft_execute_static", "fft_static_scratch_bytes",
+    "fft_execute_static", "fft_static_scratch_bytes", "fft_ragged_describe_ex",
 )
 
 VARIANT_NT_LOAD = 1
@@ -177,6 +177,17 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [("sched", SchedOpts), ("arena_bytes", ctypes.c_size_t), ("auto_release", ctypes.c_int)]
 
 
+class RaggedDesc(ctypes.Structure):
+    _fields_ = [("total_points", ctypes.c_size_t), ("graph_nodes", ctypes.c_int),
+                ("persistent_launches", ctypes.c_int), ("fallback_classes", ctypes.c_int),
+                ("kernel_name", ctypes.c_char_p * 8), ("units", ctypes.c_uint * 8), ("grid", ctypes.c_uint * 8),
+                ("classes", ctypes.c_int * 8), ("threads", ctypes.c_int * 8), ("lds_bytes", ctypes.c_size_t * 8),
+                ("branch_graph_nodes", ctypes.c_size_t)]
+
+
+RAGGED_PERSISTENT, RAGGED_PLAIN, RAGGED_BRANCHES = 0, 1, 2
+
+
 def _struct_dict(st) -> dict:
     out = {}
     for name, _ in st._fields_:
@@ -246,6 +257,8 @@ def load():
     lib.fft_ragged_create.argtypes = [szp, szp, sz, i, ctypes.POINTER(vp)]
     lib.fft_ragged_execute.argtypes = [vp, vp, vp, vp, i]
     lib.fft_ragged_describe.argtypes = [vp, szp, szp]
+    lib.fft_ragged_describe_ex.argtypes = [vp, ctypes.POINTER(RaggedDesc)]
+    lib.fft_ragged_describe_ex.restype = ctypes.c_int
     lib.fft_ragged_destroy.argtypes = [vp]
     lib.fft_plan_twiddles.argtypes = [vp, vp, sz, szp]
     lib.fft_ragged_create_ex.argtypes = [szp, szp, sz, i, vp, ctypes.POINTER(vp)]
@@ -695,8 +708,12 @@ class Ragged:
             at += n * c
         return out
 
-    def execute(self, x, out=None, stream=None, graph: bool = True):
+    def execute(self, x, out=None, stream=None, graph: bool = True, mode=None):
+        """mode: RAGGED_PERSISTENT (default; graph=False means RAGGED_PLAIN),
+        RAGGED_PLAIN or RAGGED_BRANCHES (``fft_ragged_execute``)."""
         import torch
+        if mode is None:
+            mode = RAGGED_PERSISTENT if graph else RAGGED_PLAIN
         _check_tensor(x, "x", self.storage)
         if x.numel() != self.total_points:
             raise ValueError(f"x has {x.numel()} values, ragged plan expects {self.total_points}")
@@ -704,14 +721,22 @@ class Ragged:
             out = torch.empty_like(x)
         _check_tensor(out, "out", self.storage)
         _check(load().fft_ragged_execute(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                         _stream_handle(stream), 0 if graph else 1), "fft_ragged_execute")
+                                         _stream_handle(stream), int(mode)), "fft_ragged_execute")
         _record(stream, x, out)
         return out
 
     def describe(self) -> dict:
         tp, gn = ctypes.c_size_t(), ctypes.c_size_t()
         _check(load().fft_ragged_describe(self._h, ctypes.byref(tp), ctypes.byref(gn)), "fft_ragged_describe")
-        return {"total_points": tp.value, "graph_nodes": gn.value, "classes": list(self.classes)}
+        d = RaggedDesc()
+        _check(load().fft_ragged_describe_ex(self._h, ctypes.byref(d)), "fft_ragged_describe_ex")
+        k = d.persistent_launches
+        launches = [{"kernel": d.kernel_name[i].decode(), "units": d.units[i], "grid": d.grid[i],
+                     "classes": d.classes[i], "threads": d.threads[i], "lds_bytes": d.lds_bytes[i]}
+                    for i in range(min(k, 8))]
+        return {"total_points": tp.value, "graph_nodes": gn.value, "classes": list(self.classes),
+                "kernel_nodes": d.graph_nodes, "persistent_launches": launches,
+                "fallback_classes": d.fallback_classes, "branch_graph_nodes": d.branch_graph_nodes}
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

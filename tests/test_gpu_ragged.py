@@ -1,4 +1,5 @@
-"""Ragged batches (one graph launch) and the autotuner, on the GPU, against the oracle."""
+"""Ragged batches (persistent work-list kernels in one graph, the plain path,
+the per-length branch graph) and the autotuner, on the GPU, against the oracle."""
 import numpy as np
 import pytest
 
@@ -34,47 +35,78 @@ def _check_classes(y, x, classes, sign):
 
 
 @pytest.mark.parametrize("sign", [fb.FORWARD, fb.BACKWARD])
-def test_ragged_graph_and_plain_match_oracle(sign):
+def test_ragged_persistent_plain_and_branches_match_oracle(sign):
     say(f"case: ragged mix {CLASSES} sign={sign}")
     x = _ragged_input(CLASSES, 700)
     xd = torch.from_numpy(x).to("cuda")
     with fb.Ragged(CLASSES, sign) as r:
-        yg = r.execute(xd)
+        yg = r.execute(xd)                               # persistent work-list kernels
         torch.cuda.synchronize()
         d = r.describe()
-        assert d["total_points"] == x.size and d["graph_nodes"] > 0
-        yp = r.execute(xd, graph=False)
+        say(f"  {d['kernel_nodes']} kernel nodes: {d['persistent_launches']}, fallback {d['fallback_classes']}")
+        assert d["total_points"] == x.size and d["graph_nodes"] == d["kernel_nodes"] > 0
+        # one launch per LDS-footprint class present, and lengths 3 and 1 on their own nodes
+        assert 2 <= len(d["persistent_launches"]) <= 4 and d["fallback_classes"] == 2
+        assert d["kernel_nodes"] == len(d["persistent_launches"]) + 2
+        yp = r.execute(xd, mode=fb.RAGGED_PLAIN)
+        yb = r.execute(xd, mode=fb.RAGGED_BRANCHES)
         torch.cuda.synchronize()
-        ygn, ypn = yg.cpu().numpy(), yp.cpu().numpy()
-        # the same kernels in both submissions: bitwise equal
-        assert np.array_equal(ygn.view(np.uint32), ypn.view(np.uint32))
+        ygn, ypn, ybn = yg.cpu().numpy(), yp.cpu().numpy(), yb.cpu().numpy()
+        # the plain path and its branch graph run the same kernels: bitwise equal
+        assert np.array_equal(ybn.view(np.uint32), ypn.view(np.uint32))
         _check_classes(ygn, x, CLASSES, sign)
-        # new buffers: the graph is captured again
+        _check_classes(ypn, x, CLASSES, sign)
+        # new buffers: the graph's node arguments are updated
         x2 = _ragged_input(CLASSES, 800)
         y2 = r.execute(torch.from_numpy(x2).to("cuda"))
         torch.cuda.synchronize()
         _check_classes(y2.cpu().numpy(), x2, CLASSES, sign)
         # in place, launched several times with host work in between
         buf = torch.from_numpy(x).to("cuda")
-        ref = ygn
         for rep in range(3):
             b = buf.clone()
             r.execute(b, out=b)
             torch.cuda.synchronize()
-            assert np.array_equal(b.cpu().numpy().view(np.uint32), ref.view(np.uint32)), rep
+            assert np.array_equal(b.cpu().numpy().view(np.uint32), ygn.view(np.uint32)), rep
+
+
+def test_persistent_relaunch_back_to_back():
+    # the queue counters return to zero at the end of every launch: five
+    # launches with no synchronisation in between give five equal results
+    say("case: five back-to-back persistent launches")
+    x = _ragged_input(CLASSES, 710)
+    xd = torch.from_numpy(x).to("cuda")
+    y = torch.empty_like(xd)
+    outs = []
+    with fb.Ragged(CLASSES, fb.FORWARD) as r:
+        for _ in range(5):
+            r.execute(xd, out=y)
+            outs.append(y.clone())
+        torch.cuda.synchronize()
+    first = outs[0].cpu().numpy()
+    _check_classes(first, x, CLASSES, fb.FORWARD)
+    for o in outs[1:]:
+        assert np.array_equal(o.cpu().numpy().view(np.uint32), first.view(np.uint32))
 
 
 def test_each_class_alone_equals_in_mix():
+    # persistent: a class alone (a one-class ragged plan) equals the same class
+    # in the mix, bitwise; plain: each default plan alone equals the plain mix
     x = _ragged_input(CLASSES, 900)
     xd = torch.from_numpy(x).to("cuda")
     with fb.Ragged(CLASSES) as r:
         mix = r.execute(xd).cpu().numpy()
+        plain = r.execute(xd, mode=fb.RAGGED_PLAIN).cpu().numpy()
     at = 0
     for n, c in CLASSES:
+        say(f"case: class N={n} x{c} alone")
         part = xd[at:at + n * c].clone()
+        with fb.Ragged([(n, c)]) as one:
+            alone = one.execute(part).cpu().numpy()
+        assert np.array_equal(alone.view(np.uint32), mix[at:at + n * c].view(np.uint32)), n
         with fb.Plan(n, c) as p:
             alone = p.execute(part).cpu().numpy()
-        assert np.array_equal(alone.view(np.uint32), mix[at:at + n * c].view(np.uint32)), n
+        assert np.array_equal(alone.view(np.uint32), plain[at:at + n * c].view(np.uint32)), n
         at += n * c
 
 
@@ -117,9 +149,10 @@ def test_autotune_sets_wisdom_and_stays_correct(tmp_path):
 
 
 def test_ragged_fp16_storage():
-    """The ragged mix in the FP16-storage form: graph == plain == each class
-    alone (bitwise), and every class within 2^-11 + the FP32 tolerance of the
-    exact DFT of its FP16-valued input."""
+    """The ragged mix in the FP16-storage form: persistent and plain paths each
+    within 2^-11 + the FP32 tolerance of the exact DFT of the FP16-valued
+    input, and each class alone (a one-class ragged plan) equal to the same
+    class in the mix, bitwise."""
     classes = CLASSES
     say(f"case: ragged fp16 {classes}")
     x = _ragged_input(classes, 950)
@@ -128,20 +161,20 @@ def test_ragged_fp16_storage():
     xexact = xr[..., 0] + 1j * xr[..., 1]
     with fb.Ragged(classes, storage=fb.STORAGE_F16) as r:
         yg = r.execute(xh)
-        yp = r.execute(xh, graph=False)
+        yp = r.execute(xh, mode=fb.RAGGED_PLAIN)
         torch.cuda.synchronize()
         g16 = torch.view_as_real(yg).cpu().numpy()
-        assert np.array_equal(g16.view(np.int16), torch.view_as_real(yp).cpu().numpy().view(np.int16))
-    y = g16.astype(np.float64)
-    y = y[..., 0] + 1j * y[..., 1]
+        p16 = torch.view_as_real(yp).cpu().numpy()
     at = 0
     for n, c in classes:
         ref = oracle.fft(xexact[at:at + n * c].reshape(c, n))
-        err = metrics.rel_l2_per_transform(y[at:at + n * c].reshape(c, n), ref)
-        say(f"  class N={n} x{c}: max rel L2 {err.max():.2e}")
-        assert np.all(err <= 2.0 ** -11 + metrics.tolerance(n))
-        with fb.Plan(n, c, opts=fb.make_opts(storage=fb.STORAGE_F16)) as p:
-            alone = torch.view_as_real(p.execute(xh[at:at + n * c].clone())).cpu().numpy()
+        for name, out in (("persistent", g16), ("plain", p16)):
+            y = out[at:at + n * c].astype(np.float64)
+            err = metrics.rel_l2_per_transform((y[..., 0] + 1j * y[..., 1]).reshape(c, n), ref)
+            say(f"  {name} class N={n} x{c}: max rel L2 {err.max():.2e}")
+            assert np.all(err <= 2.0 ** -11 + metrics.tolerance(n))
+        with fb.Ragged([(n, c)], storage=fb.STORAGE_F16) as one:
+            alone = torch.view_as_real(one.execute(xh[at:at + n * c].clone())).cpu().numpy()
         assert np.array_equal(alone.view(np.int16), g16[at:at + n * c].view(np.int16)), n
         at += n * c
 
@@ -161,6 +194,11 @@ def test_full_ragged_mix_sampled_against_oracle():
     with fb.Ragged(classes, fb.FORWARD) as r:
         y = r.execute(x)
         torch.cuda.synchronize()
+        d = r.describe()
+    # one persistent launch per LDS-footprint class, nothing else
+    say(f"  launches: {d['persistent_launches']}")
+    assert d["kernel_nodes"] == len(d["persistent_launches"]) <= 4 and d["fallback_classes"] == 0
+    assert sum(L["classes"] for L in d["persistent_launches"]) == len(classes) + 1   # 65536: two passes
     at = 0
     for n, c in classes:
         for b in (0, c - 1):
