@@ -52,8 +52,8 @@ def parse():
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "hbm_traffic_n4096x4096_n2p20x16.md"),
                    help="rocprofv3 traffic summary (measured HBM bytes per launch per kernel)")
     p.add_argument("--no-serving", action="store_true", help="skip the serving stream (profiling runs)")
-    p.add_argument("--extras", default=",".join(("copy", "small", "sar", "fp16", "ragged", "serving")),
-                   help="comma list of extras to run: copy, small, sar, fp16, ragged, serving")
+    p.add_argument("--extras", default=",".join(("copy", "small", "sar", "fp16", "ragged", "schedules", "serving")),
+                   help="comma list of extras to run: copy, small, sar, fp16, ragged, schedules, serving")
     p.add_argument("--calibrate", action="store_true",
                    help="also run the copy kernel on 256 MiB three times (counter calibration)")
     return p.parse_args()
@@ -327,7 +327,7 @@ def main():
         p.close()
 
 
-EXTRAS = ("copy", "small", "sar", "fp16", "ragged", "serving")
+EXTRAS = ("copy", "small", "sar", "fp16", "ragged", "schedules", "serving")
 
 
 def run_extras(torch, fb, inputs, stream, which=EXTRAS):
@@ -338,6 +338,7 @@ def run_extras(torch, fb, inputs, stream, which=EXTRAS):
             ("sar", "sar", lambda: run_sar(torch, fb, inputs, stream)),
             ("fp16_storage", "fp16", lambda: run_fp16(torch, fb, inputs, stream)),
             ("ragged", "ragged", lambda: run_ragged(torch, fb, inputs, stream)),
+            ("schedule_model", "schedules", lambda: run_schedule_model(torch, fb, stream)),
             ("serving", "serving", lambda: run_serving(torch, fb, inputs))]
     for key, tag, fn in todo:
         if tag not in which:
@@ -641,7 +642,12 @@ def run_ragged(torch, fb, inputs, stream):
         # the class's own batch: 2^28 / 15 points, 143 MB each way, so the
         # candidates are timed against HBM rather than the Infinity Cache
         rep = fb.autotune(n, c)
-        tuned[n] = {"kernel": rep["chosen"], "predicted_schedule": rep["predicted"]}
+        tuned[n] = {"kernel": rep["chosen"], "chosen_us": round(rep["chosen_us"], 2),
+                    "predicted_schedule": rep["predicted"],
+                    "predicted_us": None if rep["predicted_us"] is None else round(rep["predicted_us"], 2),
+                    "chosen_schedule_rt_us": None if rep["chosen_schedule_rt_us"] is None
+                    else round(rep["chosen_schedule_rt_us"], 2),
+                    "chosen_is_predicted": rep["chosen_predicted"]}
     total = sum(n * c for n, c in classes)
     x = torch.empty(total, dtype=torch.complex64, device="cuda")
     gen = torch.Generator(device="cuda")
@@ -693,6 +699,84 @@ def run_ragged(torch, fb, inputs, stream):
     }
     log("ragged", json.dumps({k: v for k, v in res.items() if k not in ("autotuned", "per_class_plain_us")}))
     fb.wisdom_clear()
+    return res
+
+
+def run_schedule_model(torch, fb, stream):
+    """The paper's performance model tested on this GPU at its own length,
+    N = 1024: the stage costs measured one stage at a time give every
+    schedule (sequence of radices 2, 4, 8, 16) an additive cost; every
+    schedule of at most 8 stages (391) is then run whole on the
+    run-time-schedule kernel (16384 transforms, 128 MiB each way, four
+    rotating buffer sets) and the model's ranking is compared with the
+    measured one (Spearman rank correlation), with the model's optimum, the
+    measured optimum and the schedules the paper's tables compare."""
+    import numpy as np
+    n, batch = 1024, 16384
+    rep = fb.autotune(n, batch)
+    cost = rep["stage_cost"]                      # (radix, start stage) -> ns per transform
+    scheds = []
+
+    def rec(left, acc):
+        if left == 0:
+            scheds.append(list(acc))
+            return
+        if len(acc) == 8:
+            return
+        for r in (2, 4, 8, 16):
+            if int(math.log2(r)) <= left:
+                rec(left - int(math.log2(r)), acc + [r])
+
+    rec(10, [])
+    sets = [(torch.empty(2 * n * batch, dtype=torch.float32, device="cuda").uniform_(-1, 1).view(torch.complex64),
+             torch.empty(n * batch, dtype=torch.complex64, device="cuda")) for _ in range(4)]
+    sh = stream.cuda_stream
+    flags = fb.VARIANT_RUNTIME_SCHEDULE | fb.VARIANT_NT_LOAD | fb.VARIANT_NT_STORE
+    model, measured = [], []
+    for sc in scheds:
+        at, c = 0, 0.0
+        for r in sc:
+            c += cost[(r, at)]
+            at += int(math.log2(r))
+        with fb.Plan(n, batch, fb.FORWARD, fb.make_opts(radix=sc, flags=flags)) as p:
+            k = [0]
+
+            def step():
+                xi, yi = sets[k[0] % 4]
+                k[0] += 1
+                p.execute_ptr(xi.data_ptr(), yi.data_ptr(), sh)
+            t = _timed(torch, stream, step, reps=12)
+        model.append(c)
+        measured.append(t * 1e6)
+    # the compiled kernel the autotuner chose (its own timing ping-pongs one
+    # buffer pair, partly cache-resident), timed here the same way as the rest
+    with fb.Plan(n, batch, fb.FORWARD) as p:
+        chosen_name = p.describe()["kernel_name"]
+        k = [0]
+
+        def step_c():
+            xi, yi = sets[k[0] % 4]
+            k[0] += 1
+            p.execute_ptr(xi.data_ptr(), yi.data_ptr(), sh)
+        t_chosen = _timed(torch, stream, step_c, reps=12) * 1e6
+    fb.wisdom_clear()
+    del sets
+    model, measured = np.array(model), np.array(measured)
+    rk = lambda v: np.argsort(np.argsort(v))
+    rho = float(np.corrcoef(rk(model), rk(measured))[0, 1])
+    order = np.argsort(measured)
+    pi = scheds.index(rep["predicted"]) if rep["predicted"] in scheds else None
+    key = lambda sc: ",".join(str(v) for v in sc)
+    res = {"n": n, "batch": batch, "schedules": len(scheds), "spearman_model_vs_measured": round(rho, 3),
+           "predicted": rep["predicted"],
+           "predicted_us": None if pi is None else round(float(measured[pi]), 2),
+           "predicted_measured_rank": None if pi is None else int(np.where(order == pi)[0][0]) + 1,
+           "best_measured": scheds[int(order[0])], "best_measured_us": round(float(measured[order[0]]), 2),
+           "worst_measured_us": round(float(measured[order[-1]]), 2),
+           "autotuned_kernel": chosen_name, "autotuned_kernel_us": round(t_chosen, 2),
+           "paper_schedules_us": {key(sc): round(float(measured[scheds.index(sc)]), 2)
+                                  for sc in ([8, 8, 8, 2], [4, 8, 8, 4], [8, 8, 4, 4], [16, 16, 4])}}
+    log("schedule model", json.dumps(res))
     return res
 
 

@@ -208,6 +208,11 @@ typedef struct {
                                           halved LDS allows, spilling if need be */
 #define FFT_VARIANT_LOOP 4096         /* persistent workgroups (as many as are resident) looping over
                                          the units in launch order, without prefetch */
+#define FFT_VARIANT_RUNTIME_SCHEDULE 8192 /* block kernel (lengths 64..16384, 16 values per thread)
+                                             that takes its radix schedule at run time: any
+                                             sequence of radices 2, 4, 8, 16 whose product is n.
+                                             Chosen for a schedule (fft_plan_opts_t.radix) no
+                                             compiled kernel has, or when flags include it */
 
 /* Storage of the transform data (fft_plan_opts_t.storage). */
 #define FFT_STORAGE_C64 0   /* interleaved FP32 (re, im), 8 bytes per value */
@@ -414,13 +419,21 @@ typedef struct {
     int chosen_kernel;            /* fastest candidate; recorded as wisdom for n */
     int chosen_kernel2;
     double chosen_us;
+    double predicted_us;          /* the predicted schedule run whole on the run-time-schedule kernel
+                                     (FFT_VARIANT_RUNTIME_SCHEDULE), same batch; < 0 = not run */
+    double chosen_schedule_rt_us; /* the fastest compiled kernel's schedule on that same kernel: the
+                                     model's choice against the measured one on one code path */
+    int chosen_predicted;         /* 1: the predicted schedule beat every compiled kernel; chosen_kernel
+                                     is then the run-time-schedule kernel and the wisdom holds the
+                                     schedule */
 } fft_tune_report_t;
 
 /* Autotune length n on the current device: stage microbenchmarks and the
  * shortest-path schedule (the paper's model), then every compiled block kernel
  * for n -- or, for four-step lengths, every compiled pass-1 x pass-2 pair,
  * which also chooses the column and row widths -- timed as a whole on `batch`
- * transforms (runtime validation); the fastest becomes the wisdom entry
+ * transforms (runtime validation), and the predicted schedule itself on the
+ * run-time-schedule kernel; the fastest becomes the wisdom entry
  * fft_plan_create uses for n.  Synchronous; allocates temporary buffers. */
 fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* report);
 

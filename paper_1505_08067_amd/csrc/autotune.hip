@@ -108,12 +108,43 @@ static Wisdom& wisdom()
 // Wisdom applies to complex64 plans: FP16-storage kernels are never chosen.
 static bool wisdom_eligible(const KEntry& k) { return (k.flags & FFT_VARIANT_FP16_STORAGE) == 0; }
 
-static const KEntry* find_named(int kind, size_t n, const std::string& name)
+// A block choice is a kernel name, followed for the run-time-schedule kernel
+// by ':' and its schedule ("block_fft_rt<1024>:16,16,4").  Splits it; false
+// for a malformed schedule (radices 2, 4, 8, 16 whose product is n).
+static bool split_choice(const std::string& s, size_t n, std::string* name, std::vector<int>* sched)
 {
+    sched->clear();
+    const size_t colon = s.find(':');
+    *name = s.substr(0, colon);
+    if (colon == std::string::npos) return true;
+    size_t prod = 1, at = colon + 1;
+    while (at <= s.size()) {
+        const size_t comma = s.find(',', at);
+        const std::string tok = s.substr(at, comma == std::string::npos ? std::string::npos : comma - at);
+        const int R = std::atoi(tok.c_str());
+        if (R != 2 && R != 4 && R != 8 && R != 16) return false;
+        sched->push_back(R);
+        prod *= (size_t)R;
+        if (comma == std::string::npos) break;
+        at = comma + 1;
+    }
+    return !sched->empty() && sched->size() <= 8 && prod == n;
+}
+
+static const KEntry* find_named(int kind, size_t n, const std::string& choice, std::vector<int>* sched = nullptr)
+{
+    std::string name;
+    std::vector<int> sc;
+    if (!split_choice(choice, n, &name, &sc)) return nullptr;
     int c = 0;
     const KEntry* t = kernel_table(&c);
     for (int i = 0; i < c; ++i)
-        if (t[i].kind == kind && (size_t)t[i].n == n && name == t[i].name && wisdom_eligible(t[i])) return &t[i];
+        if (t[i].kind == kind && (size_t)t[i].n == n && name == t[i].name && wisdom_eligible(t[i])) {
+            // the run-time-schedule kernel needs its schedule, the others none
+            if (((t[i].flags & FFT_VARIANT_RUNTIME_SCHEDULE) != 0) != !sc.empty()) return nullptr;
+            if (sched) *sched = sc;
+            return &t[i];
+        }
     return nullptr;
 }
 
@@ -126,7 +157,7 @@ static void load_env_wisdom()
     });
 }
 
-const KEntry* wisdom_kernel(size_t n)
+const KEntry* wisdom_kernel(size_t n, int* radix, int* nr)
 {
     load_env_wisdom();
     Wisdom& w = wisdom();
@@ -137,7 +168,11 @@ const KEntry* wisdom_kernel(size_t n)
         if (it == w.choice.end() || !it->second.second.empty()) return nullptr;
         name = it->second.first;
     }
-    return find_named(kKindBlock, n, name);
+    std::vector<int> sc;
+    const KEntry* k = find_named(kKindBlock, n, name, &sc);
+    if (nr) *nr = (int)sc.size();
+    for (size_t i = 0; radix && i < sc.size(); ++i) radix[i] = sc[i];
+    return k;
 }
 
 bool wisdom_pair(size_t n, const KEntry** k1, const KEntry** k2)
@@ -290,6 +325,8 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
     rep->n = n;
     rep->chosen_kernel = -1;
     rep->chosen_kernel2 = -1;
+    rep->predicted_us = -1.0;
+    rep->chosen_schedule_rt_us = -1.0;
     int lg = 0;
     while (((size_t)1 << lg) < n) ++lg;
     const bool pow2 = ((size_t)1 << lg) == n;
@@ -391,7 +428,9 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
         }
     }
     for (int i = 0; i < count && e == hipSuccess && rep->n_candidates < 32 && !four; ++i) {
-        if (t[i].kind != kKindBlock || (size_t)t[i].n != n || !wisdom_eligible(t[i])) continue;
+        if (t[i].kind != kKindBlock || (size_t)t[i].n != n || !wisdom_eligible(t[i]) ||
+            (t[i].flags & FFT_VARIANT_RUNTIME_SCHEDULE) != 0)
+            continue;
         fft_plan_opts_t o;
         fft_plan_opts_init(&o);
         o.n_radix = t[i].nr;
@@ -420,6 +459,42 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
             rep->chosen_us = us;
         }
     }
+    // 3) the model's own choice, run: the predicted schedule on the
+    // run-time-schedule kernel, and the fastest compiled schedule on the same
+    // kernel (the two schedules compared on one code path); the predicted
+    // schedule becomes the wisdom when it beats every compiled kernel
+    int rt_index = -1;
+    for (int i = 0; i < count; ++i)
+        if (t[i].kind == kKindBlock && (size_t)t[i].n == n && (t[i].flags & FFT_VARIANT_RUNTIME_SCHEDULE) != 0)
+            rt_index = i;
+    if (!four && rep->n_predicted > 0 && rt_index >= 0 && e == hipSuccess) {
+        auto time_rt = [&](const int* sched, int nr) -> double {
+            fft_plan_opts_t o;
+            fft_plan_opts_init(&o);
+            o.n_radix = nr;
+            for (int r = 0; r < nr; ++r) o.radix[r] = sched[r];
+            o.flags = t[rt_index].flags;
+            o.block_limit = kMaxBlockLen;
+            fft_plan_t p = nullptr;
+            if (fft_plan_create_ex(n, batch, FFT_FORWARD, &o, &p) != FFT_SUCCESS) return -1.0;
+            const double us = time_plan(p);
+            fft_plan_destroy(p);
+            return us;
+        };
+        rep->predicted_us = time_rt(rep->predicted, rep->n_predicted);
+        const KEntry* ck = rep->chosen_kernel >= 0 ? &t[rep->chosen_kernel] : nullptr;
+        bool rt_ok = ck && ck->nr > 0;
+        for (int r = 0; rt_ok && r < ck->nr; ++r)
+            rt_ok = ck->radix[r] == 2 || ck->radix[r] == 4 || ck->radix[r] == 8 || ck->radix[r] == 16;
+        if (rt_ok && e == hipSuccess) rep->chosen_schedule_rt_us = time_rt(ck->radix, ck->nr);
+        if (e == hipSuccess && rep->predicted_us > 0.0 && rep->predicted_us < best) {
+            best = rep->predicted_us;
+            rep->chosen_kernel = rt_index;
+            rep->chosen_kernel2 = -1;
+            rep->chosen_us = rep->predicted_us;
+            rep->chosen_predicted = 1;
+        }
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     if (x) (void)hipFree(x);
@@ -427,9 +502,14 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? FFT_ERR_OUT_OF_MEMORY : FFT_ERR_DEVICE;
     if (rep->chosen_kernel < 0) return FFT_ERR_UNSUPPORTED_SIZE;
     {
+        std::string name = t[rep->chosen_kernel].name;
+        if (rep->chosen_predicted) {
+            name += ':';
+            for (int r = 0; r < rep->n_predicted; ++r) name += (r ? "," : "") + std::to_string(rep->predicted[r]);
+        }
         Wisdom& w = wisdom();
         std::lock_guard<std::mutex> lk(w.mu);
-        w.choice[n] = {t[rep->chosen_kernel].name, rep->chosen_kernel2 >= 0 ? t[rep->chosen_kernel2].name : ""};
+        w.choice[n] = {name, rep->chosen_kernel2 >= 0 ? t[rep->chosen_kernel2].name : ""};
     }
     return FFT_SUCCESS;
 }
@@ -439,7 +519,7 @@ fft_status_t fft_wisdom_set(size_t n, int kernel_index)
     int c = 0;
     const KEntry* t = kernel_table(&c);
     if (kernel_index < 0 || kernel_index >= c || t[kernel_index].kind != kKindBlock || (size_t)t[kernel_index].n != n ||
-        !wisdom_eligible(t[kernel_index]))
+        !wisdom_eligible(t[kernel_index]) || (t[kernel_index].flags & FFT_VARIANT_RUNTIME_SCHEDULE) != 0)
         return FFT_ERR_INVALID_ARG;
     Wisdom& w = wisdom();
     std::lock_guard<std::mutex> lk(w.mu);
@@ -456,7 +536,7 @@ void fft_wisdom_clear(void)
 
 int fft_wisdom_get(size_t n)
 {
-    const KEntry* k = wisdom_kernel(n);
+    const KEntry* k = wisdom_kernel(n, nullptr, nullptr);
     if (!k) return -1;
     int c = 0;
     const KEntry* t = kernel_table(&c);
@@ -508,8 +588,7 @@ fft_status_t fft_wisdom_load(const char* path)
         }
         bool known = false;
         if (b.empty()) {
-            for (int i = 0; i < c; ++i)
-                known = known || (t[i].kind == kKindBlock && (size_t)t[i].n == n && a == t[i].name && wisdom_eligible(t[i]));
+            known = find_named(kKindBlock, n, a) != nullptr;
         } else {
             bool k1 = false, k2 = false;
             for (int i = 0; i < c; ++i) {

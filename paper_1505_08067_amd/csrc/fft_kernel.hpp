@@ -37,7 +37,8 @@ namespace fb {
 enum : int {
     kSwz = 8, kStaged = 16, kTwPow = 32, kXcd = 128, kStageStride = 256, kWaveSync = 512, kHalfX = 1024,
     kFitRegs = 2048,  // with kHalfX: registers fitted to every workgroup the halved LDS allows
-    kLoop = 4096      // persistent workgroups looping over units, without prefetch
+    kLoop = 4096,     // persistent workgroups looping over units, without prefetch
+    kRtSched = 8192   // the radix schedule is a run-time argument (KArgs::sched)
 };
 
 // Half exchanges (kHalfX): when every stage but the last runs an even number

@@ -48,6 +48,8 @@ struct fft_plan_s {
     int cus = 0;                    // compute units of the plan's device
     const KEntry* klist = nullptr;  // list form of k1 (same schedule and shape), if compiled
     const KEntry* kn = nullptr;     // one-wave form of a default k1, for small batches
+    int rt_nr = 0;                  // run-time-schedule kernel: the plan's schedule
+    int rt_radix[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace fb {
@@ -55,15 +57,17 @@ namespace fb {
 static std::vector<KEntry> build_table()
 {
     std::vector<KEntry> v;
-    int nb = 0, np = 0, nf = 0, nl = 0;
+    int nb = 0, np = 0, nf = 0, nl = 0, nr = 0;
     const KEntry* b = block_entries(&nb);
     const KEntry* p = pass_entries(&np);
     const KEntry* f = filter_entries(&nf);
     const KEntry* l = list_entries(&nl);
+    const KEntry* r = rt_entries(&nr);
     v.insert(v.end(), b, b + nb);
     v.insert(v.end(), p, p + np);
     v.insert(v.end(), f, f + nf);
     v.insert(v.end(), l, l + nl);
+    v.insert(v.end(), r, r + nr);
     return v;
 }
 
@@ -466,17 +470,46 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
                (n <= limit && (batch >= block_min_batch(n, sto) || o.block_limit || o.n_radix || o.flags >= 0 || o.c > 0))) {
         p->path = FFT_PATH_BLOCK;
         if (o.n_radix == 0 && o.flags < 0 && o.c <= 0) {
-            p->k1 = sto ? nullptr : wisdom_kernel(n);
+            p->k1 = sto ? nullptr : wisdom_kernel(n, p->rt_radix, &p->rt_nr);
             if (!p->k1) {
                 p->k1 = kernel_default(kKindBlock, (int)n, 0, sto);
                 if (p->k1) p->kn = narrow_of(p->k1);   // same table layout (same schedule and variant)
             }
         } else {
+            const bool want_rt = o.flags >= 0 && (o.flags & FFT_VARIANT_RUNTIME_SCHEDULE) != 0;
             const int fl = o.flags < 0 ? (sto ? FFT_VARIANT_FP16_STORAGE : 0) : o.flags;
-            p->k1 = kernel_find(kKindBlock, (int)n, o.radix, o.n_radix, o.c, fl);
+            if (!want_rt) p->k1 = kernel_find(kKindBlock, (int)n, o.radix, o.n_radix, o.c, fl);
+            // a schedule no compiled kernel has (or one asked for this way):
+            // the run-time-schedule kernel, for radices 2, 4, 8 and 16
+            if (!p->k1 && o.n_radix > 0 && sto == 0 && (o.flags < 0 || want_rt)) {
+                size_t prod = 1;
+                bool ok = o.n_radix <= 8;
+                for (int i = 0; i < o.n_radix && ok; ++i) {
+                    const int R = o.radix[i];
+                    ok = R == 2 || R == 4 || R == 8 || R == 16;
+                    prod *= ok ? (size_t)R : 1;
+                }
+                if (!ok || prod != n) return FFT_ERR_UNSUPPORTED_SIZE;
+                for (const KEntry& k : table())
+                    if (k.kind == kKindBlock && (size_t)k.n == n && (k.flags & FFT_VARIANT_RUNTIME_SCHEDULE) &&
+                        (o.c <= 0 || k.c == o.c))
+                        p->k1 = &k;
+                if (!p->k1) return FFT_ERR_UNSUPPORTED_SIZE;
+                p->rt_nr = o.n_radix;
+                for (int i = 0; i < o.n_radix; ++i) p->rt_radix[i] = o.radix[i];
+            }
         }
         if (!p->k1) return FFT_ERR_UNSUPPORTED_SIZE;
-        off = stage_segments(p->k1, 0, p->segs);
+        if (p->rt_nr > 0) {
+            // exact rows for the plan's schedule, laid out as the kernel walks them
+            KEntry sk = *p->k1;
+            sk.nr = p->rt_nr;
+            for (int i = 0; i < p->rt_nr; ++i) sk.radix[i] = p->rt_radix[i];
+            sk.flags = 0;
+            off = stage_segments(&sk, 0, p->segs);
+        } else {
+            off = stage_segments(p->k1, 0, p->segs);
+        }
     } else {
         p->path = FFT_PATH_FOURSTEP;
         const int L = ilog2(n);
@@ -551,6 +584,7 @@ static KArgs make_args(const fft_plan_s* p, int pass, const float2* in, float2* 
     a.out = out;
     a.batch = (long long)p->batch;
     a.sg = p->direction == FFT_FORWARD ? 1.0f : -1.0f;
+    for (int i = 0; i < p->rt_nr; ++i) a.sched |= (unsigned)log2i(p->rt_radix[i]) << (4 * i);
     if (p->path == FFT_PATH_BLOCK || p->path == FFT_PATH_FILTER) {
         a.tw = p->tw + p->off_s1;
         if (p->path == FFT_PATH_FILTER) a.flt = p->tw + p->off_flt;
@@ -596,6 +630,10 @@ static void describe(const fft_plan_s* plan, fft_plan_desc_t* d)
     const KEntry* k1 = plan->path == FFT_PATH_BLOCK ? block_kernel(plan, plan->batch) : plan->k1;
     d->n_radix = k1->nr;
     for (int i = 0; i < k1->nr; ++i) d->radix[i] = k1->radix[i];
+    if (plan->rt_nr > 0) {
+        d->n_radix = plan->rt_nr;
+        for (int i = 0; i < plan->rt_nr; ++i) d->radix[i] = plan->rt_radix[i];
+    }
     d->threads_per_block = k1->threads;
     d->transforms_per_block = k1->c;
     d->lds_bytes = k1->lds;

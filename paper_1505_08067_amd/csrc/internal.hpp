@@ -31,6 +31,7 @@ struct KArgs {
     const float2* flt;     // range compression: spectrum of the pulse replica (n entries)
     const void* list;      // list kernels: one ListEnt per transform
     float sg;              // +1 forward, -1 backward (conjugation on entry and exit)
+    unsigned sched;        // run-time-schedule kernels: log2 radix per stage, 4 bits each, stage 0 lowest
 };
 
 // start / stop: optional events the device stamps at the dispatch's own start
@@ -80,9 +81,11 @@ const KEntry* block_entries(int* count);
 const KEntry* pass_entries(int* count);
 const KEntry* filter_entries(int* count);
 const KEntry* list_entries(int* count);
+const KEntry* rt_entries(int* count);
 
-// Kernel the wisdom (autotuner or FFTBLOCK_WISDOM file) chose for length n, or nullptr.
-const KEntry* wisdom_kernel(size_t n);
+// Kernel the wisdom (autotuner or FFTBLOCK_WISDOM file) chose for length n, or
+// nullptr; for the run-time-schedule kernel also its schedule (radix[0..*nr)).
+const KEntry* wisdom_kernel(size_t n, int* radix, int* nr);
 // Four-step kernels the wisdom chose for length n (false if none); their
 // lengths give the split n = k1->n * k2->n.
 bool wisdom_pair(size_t n, const KEntry** k1, const KEntry** k2);

@@ -114,6 +114,7 @@ __device__ __forceinline__ KArgs rag_args(RagEntC& e)
     a.flt = e.a.flt;
     a.list = e.a.list;
     a.sg = e.a.sg;
+    a.sched = e.a.sched;
     return a;
 }
 

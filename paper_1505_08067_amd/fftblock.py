@@ -64,6 +64,7 @@ VARIANT_WAVE_SYNC = 512
 VARIANT_HALF_EXCHANGE = 1024
 VARIANT_FIT_REGISTERS = 2048
 VARIANT_LOOP = 4096
+VARIANT_RUNTIME_SCHEDULE = 8192
 STORAGE_C64 = 0
 STORAGE_F16 = 1
 KERNEL_KINDS = {0: "block", 1: "pass1", 2: "pass2", 3: "filter", 4: "list"}
@@ -127,7 +128,8 @@ class TuneReport(ctypes.Structure):
         ("n_candidates", ctypes.c_int), ("candidate_kernel", ctypes.c_int * 32),
         ("candidate_kernel2", ctypes.c_int * 32),
         ("candidate_us", ctypes.c_double * 32), ("chosen_kernel", ctypes.c_int), ("chosen_kernel2", ctypes.c_int),
-        ("chosen_us", ctypes.c_double),
+        ("chosen_us", ctypes.c_double), ("predicted_us", ctypes.c_double), ("chosen_schedule_rt_us", ctypes.c_double),
+        ("chosen_predicted", ctypes.c_int),
     ]
 
 
@@ -647,9 +649,13 @@ def autotune(n: int, batch: int) -> dict:
                         ("+" + names[r.candidate_kernel2[k]]["name"] if r.candidate_kernel2[k] >= 0 else ""),
                         r.candidate_us[k]) for k in range(r.n_candidates)],
         "chosen": (names[r.chosen_kernel]["name"] +
-                   ("+" + names[r.chosen_kernel2]["name"] if r.chosen_kernel2 >= 0 else ""))
+                   ("+" + names[r.chosen_kernel2]["name"] if r.chosen_kernel2 >= 0 else "") +
+                   (":" + ",".join(str(v) for v in r.predicted[: r.n_predicted]) if r.chosen_predicted else ""))
         if r.chosen_kernel >= 0 else None,
         "chosen_us": r.chosen_us,
+        "predicted_us": r.predicted_us if r.predicted_us >= 0 else None,
+        "chosen_schedule_rt_us": r.chosen_schedule_rt_us if r.chosen_schedule_rt_us >= 0 else None,
+        "chosen_predicted": bool(r.chosen_predicted),
     }
 
 

@@ -80,3 +80,44 @@ def test_wisdom_pair_for_fourstep(tmp_path):
     fb.wisdom_clear()
     d = fb.plan_query(1 << 20, 4)
     assert (d["kernel_name"], d["kernel_name2"]) != (p1, p2)
+
+
+def test_runtime_schedule_planning_without_device():
+    # a schedule no compiled kernel has runs on the run-time-schedule kernel,
+    # whose table follows the plan's schedule; a compiled one keeps its kernel
+    import math
+    d = fb.plan_query(1024, 64, opts=fb.make_opts(radix=[2, 16, 16, 2]))
+    assert d["kernel_name"] == "block_fft_rt<1024>" and d["radix"] == [2, 16, 16, 2]
+    assert d["flags"] & fb.VARIANT_RUNTIME_SCHEDULE
+    # exact rows: stage s >= 1 holds Ns * R entries (2*16 + 32*16 + 512*2), padded to 32
+    assert d["twiddle_bytes"] == 8 * ((32 + 512 + 1024 + 31) // 32 * 32)
+    assert fb.plan_query(1024, 64, opts=fb.make_opts(radix=[16, 16, 4]))["kernel_name"].startswith("block_fft<1024")
+    # ... unless the run-time-schedule kernel is asked for
+    d = fb.plan_query(1024, 64, opts=fb.make_opts(radix=[16, 16, 4], flags=fb.VARIANT_RUNTIME_SCHEDULE | 3))
+    assert d["kernel_name"] == "block_fft_rt<1024>" and d["radix"] == [16, 16, 4]
+    for n, sched in ((64, [2] * 6), (256, [2] * 8), (4096, [2, 2, 2, 2, 16, 16]), (16384, [2, 2, 16, 16, 16])):
+        d = fb.plan_query(n, 3, opts=fb.make_opts(radix=sched))
+        assert d["kernel_name"] == f"block_fft_rt<{n}>" and d["radix"] == sched and math.prod(sched) == n
+    for bad in ([32, 32], [16, 16], [3, 4, 4], [2] * 8):
+        with pytest.raises(fb.FFTError) as ei:
+            fb.plan_query(1024, 1, opts=fb.make_opts(radix=bad))
+        assert ei.value.status == 2, bad
+    with pytest.raises(fb.FFTError):      # complex64 only
+        fb.plan_query(1024, 1, opts=fb.make_opts(radix=[2, 16, 16, 2], storage=fb.STORAGE_F16))
+
+
+def test_wisdom_with_a_runtime_schedule(tmp_path):
+    fb.wisdom_clear()
+    path = tmp_path / "w.txt"
+    path.write_text("1024\tblock_fft_rt<1024>:2,16,16,2\n")
+    fb.wisdom_load(str(path))
+    d = fb.plan_query(1024, 512)
+    assert d["kernel_name"] == "block_fft_rt<1024>" and d["radix"] == [2, 16, 16, 2]
+    fb.wisdom_save(str(path))
+    assert "block_fft_rt<1024>:2,16,16,2" in path.read_text()
+    # a schedule that does not multiply to the length is refused
+    path.write_text("1024\tblock_fft_rt<1024>:16,16\n")
+    with pytest.raises(fb.FFTError):
+        fb.wisdom_load(str(path))
+    fb.wisdom_clear()
+    assert fb.plan_query(1024, 512)["kernel_name"] != "block_fft_rt<1024>"

@@ -124,9 +124,16 @@ def test_autotune_sets_wisdom_and_stays_correct(tmp_path):
         f"chosen {rep['chosen']} {rep['chosen_us']:.1f} us of {len(rep['candidates'])}")
     assert rep["predicted"] and np.prod(rep["predicted"]) == 1024
     assert len(rep["stage_cost"]) == 10 + 9 + 8 + 7
-    assert rep["chosen"] and fb.wisdom_get(1024) == rep["chosen"]
+    say(f"  predicted schedule run: {rep['predicted_us']:.1f} us; best compiled schedule on the same "
+        f"run-time-schedule kernel: {rep['chosen_schedule_rt_us']:.1f} us")
+    assert rep["predicted_us"] > 0 and rep["chosen_schedule_rt_us"] > 0
+    name = rep["chosen"].split(":")[0]
+    assert rep["chosen"] and fb.wisdom_get(1024) == name
     with fb.Plan(1024, 33) as p:
-        assert p.describe()["kernel_name"] == rep["chosen"]
+        d = p.describe()
+        assert d["kernel_name"] == name
+        if rep["chosen_predicted"]:
+            assert d["radix"] == rep["predicted"]
         x = inputs.uniform(1, 33, 1024)
         y = p.execute(torch.from_numpy(x).to("cuda")).cpu().numpy()
     metrics.check(y, oracle.fft(x.astype(np.complex128)), 1024)

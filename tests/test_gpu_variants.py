@@ -34,7 +34,8 @@ def run(n, batch, sign, opts, x):
 def _block_variants():
     out = []
     for k in fb.kernels():
-        if k["kind"] == "block" and k["n"] >= 2:
+        # (the run-time-schedule kernels take the plan's schedule: test_gpu_schedules.py)
+        if k["kind"] == "block" and k["n"] >= 2 and not k["flags"] & fb.VARIANT_RUNTIME_SCHEDULE:
             out.append(pytest.param(k, id=k["name"]))
     return out
 
