@@ -288,7 +288,7 @@ def main():
         # the GPU's outputs of the same inputs, compared with the oracle's
         outs = {}
         for name, n, batch, sign in items:
-            xin = bufs[(n, batch)][0][0]
+            xin = bufs[name][0][0]
             outs[name] = plans[name].execute(xin).cpu().numpy().reshape(batch, n)
         cpu = cpu_baseline(items, fl_step, args.cpu_seconds, outs)
         del outs
