@@ -52,7 +52,7 @@ def parse():
     p.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "hbm_traffic_n4096x4096_n2p20x16.md"),
                    help="rocprofv3 traffic summary (measured HBM bytes per launch per kernel)")
     p.add_argument("--no-serving", action="store_true", help="skip the serving stream (profiling runs)")
-    p.add_argument("--extras", default=",".join(("copy", "small", "sar", "fp16", "ragged", "schedules", "serving")),
+    p.add_argument("--extras", default=",".join(("copy", "small", "sar", "fp16", "ragged", "schedules", "lanes", "serving")),
                    help="comma list of extras to run: copy, small, sar, fp16, ragged, schedules, serving")
     p.add_argument("--calibrate", action="store_true",
                    help="also run the copy kernel on 256 MiB three times (counter calibration)")
@@ -327,7 +327,7 @@ def main():
         p.close()
 
 
-EXTRAS = ("copy", "small", "sar", "fp16", "ragged", "schedules", "serving")
+EXTRAS = ("copy", "small", "sar", "fp16", "ragged", "schedules", "lanes", "serving")
 
 
 def run_extras(torch, fb, inputs, stream, which=EXTRAS):
@@ -339,6 +339,7 @@ def run_extras(torch, fb, inputs, stream, which=EXTRAS):
             ("fp16_storage", "fp16", lambda: run_fp16(torch, fb, inputs, stream)),
             ("ragged", "ragged", lambda: run_ragged(torch, fb, inputs, stream)),
             ("schedule_model", "schedules", lambda: run_schedule_model(torch, fb, stream)),
+            ("lanes", "lanes", lambda: run_lanes(torch, fb, stream)),
             ("serving", "serving", lambda: run_serving(torch, fb, inputs))]
     for key, tag, fn in todo:
         if tag not in which:
@@ -777,6 +778,68 @@ def run_schedule_model(torch, fb, stream):
            "paper_schedules_us": {key(sc): round(float(measured[scheds.index(sc)]), 2)
                                   for sc in ([8, 8, 8, 2], [4, 8, 8, 4], [8, 8, 4, 4], [16, 16, 4])}}
     log("schedule model", json.dumps(res))
+    return res
+
+
+def run_lanes(torch, fb, stream, rounds=7, reps=20):
+    """Global-access width and exchange form of the block kernels: 2^24
+    points per launch at every length (128 MiB read, 128 MiB written),
+    forward, four rotating (in, out) sets so every launch reads and writes
+    HBM.  The planner's kernel against the same schedule with 16-byte lanes
+    (neighbouring lanes swapping halves by DPP) and, where one exists, the
+    kernels whose intra-wave exchanges are register permutations, with the
+    LDS kernels of their schedule.  The candidates of a length are timed in
+    turn, `rounds` times `reps` launches each; the median round is reported
+    (and the spread, max - min, over the rounds)."""
+    sh = stream.cuda_stream
+    npts = 1 << 24
+    sets = [(torch.empty(2 * npts, dtype=torch.float32, device="cuda").uniform_(-1, 1).view(torch.complex64),
+             torch.empty(npts, dtype=torch.complex64, device="cuda")) for _ in range(4)]
+    kinfo = [k for k in fb.kernels() if k["kind"] == "block"]
+    res = {}
+    for n in (256, 1024, 2048, 4096, 8192):
+        batch = npts // n
+        with fb.Plan(n, batch, fb.FORWARD) as p0:
+            d0 = p0.describe()
+        base = next(k for k in kinfo if k["name"] == d0["kernel_name"])
+        cands = [("planner", base)]
+        for k in kinfo:
+            if k["n"] == n and k["radix"] == base["radix"] and k["c"] == base["c"] and k is not base \
+                    and k["flags"] == (base["flags"] | fb.VARIANT_VEC16):
+                cands.append(("vec16", k))
+        xl = [k for k in kinfo if k["n"] == n and k["flags"] & fb.VARIANT_CROSS_LANE]
+        if xl:
+            # the same schedule with LDS exchanges (barriers, and wave-synchronous)
+            for k in kinfo:
+                if k["n"] == n and k["radix"] == xl[0]["radix"] and k["c"] == xl[0]["c"] \
+                        and not k["flags"] & fb.VARIANT_CROSS_LANE:
+                    cands.append((f"lds_exchanges_v{k['flags']}", k))
+            for k in xl:
+                lab = "cross_lane_then_lds" if k["flags"] & fb.VARIANT_WAVE_SYNC else "cross_lane_all"
+                cands.append((lab, k))
+        plans = [(lab, fb.Plan(n, batch, fb.FORWARD, fb.make_opts(radix=k["radix"], flags=k["flags"], c=k["c"])))
+                 for lab, k in cands]
+        times = {lab: [] for lab, _ in plans}
+        for _ in range(rounds):
+            for lab, p in plans:
+                it = [0]
+
+                def step():
+                    xi, yi = sets[it[0] % 4]
+                    it[0] += 1
+                    p.execute_ptr(xi.data_ptr(), yi.data_ptr(), sh)
+                times[lab].append(_timed(torch, stream, step, reps=reps) * 1e6)
+        row = {}
+        for lab, p in plans:
+            ts = sorted(times[lab])
+            med = ts[len(ts) // 2]
+            row[lab] = {"kernel": p.describe()["kernel_name"], "us": round(med, 2),
+                        "spread_us": round(ts[-1] - ts[0], 2),
+                        "frac_hbm_peak": round(16.0 * npts / (med * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)}
+            p.close()
+        res[f"{n}x{batch}"] = row
+    del sets
+    log("lanes", json.dumps(res))
     return res
 
 

@@ -213,6 +213,16 @@ typedef struct {
                                              sequence of radices 2, 4, 8, 16 whose product is n.
                                              Chosen for a schedule (fft_plan_opts_t.radix) no
                                              compiled kernel has, or when flags include it */
+#define FFT_VARIANT_VEC16 16384       /* block kernel: 16-byte global loads and stores (two
+                                         consecutive complex values per lane; neighbouring lanes
+                                         swap halves by a DPP lane permutation).  fft_execute
+                                         returns FFT_ERR_INVALID_ARG unless in and out are 16-byte
+                                         aligned */
+#define FFT_VARIANT_CROSS_LANE 32768  /* block kernel, one transform per wave64 (N = 1024,
+                                         schedule [16,4,16]): exchanges between the lanes of the
+                                         wave are register permutations (DPP, v_permlane16/32_swap)
+                                         instead of LDS round trips; with WAVE_SYNC the exchange
+                                         over lane bits 0..3 still goes through LDS */
 
 /* Storage of the transform data (fft_plan_opts_t.storage). */
 #define FFT_STORAGE_C64 0   /* interleaved FP32 (re, im), 8 bytes per value */

@@ -425,6 +425,45 @@ __device__ __forceinline__ void gstore(float2* p, float2 v)
     }
 }
 
+// Sixteen-byte accesses: two consecutive complex values in one lane.
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+template <int FL>
+__device__ __forceinline__ float4 gload2(const float2* p)
+{
+    if constexpr ((FL & kNtLoad) != 0) {
+        const v4f_t t = __builtin_nontemporal_load(reinterpret_cast<const v4f_t*>(p));
+        return make_float4(t.x, t.y, t.z, t.w);
+    } else {
+        return *reinterpret_cast<const float4*>(p);
+    }
+}
+
+template <int FL>
+__device__ __forceinline__ void gstore2(float2* p, float2 lo, float2 hi)
+{
+    v4f_t t;
+    t.x = lo.x;
+    t.y = lo.y;
+    t.z = hi.x;
+    t.w = hi.y;
+    if constexpr ((FL & kNtStore) != 0)
+        __builtin_nontemporal_store(t, reinterpret_cast<v4f_t*>(p));
+    else
+        *reinterpret_cast<v4f_t*>(p) = t;
+}
+
+// The value of the neighbouring lane (lane ^ 1), by a DPP quad permutation
+// [1,0,3,2]: a VALU operand modifier, no LDS traffic.  Every lane of the pair
+// must be active.
+__device__ __forceinline__ float2 lane_xor1(float2 v)
+{
+    float2 r;
+    r.x = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v.x), 0xB1, 0xF, 0xF, true));
+    r.y = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v.y), 0xB1, 0xF, 0xF, true));
+    return r;
+}
+
 // Powers w^r, r < R, from the row w^(2^i), 2^i < R (FP64-generated,
 // FP32-stored): w^r = w^h * w^(r-h) with h the highest power of two in r, so
 // each power carries at most popcount(r) - 1 complex products.

@@ -38,7 +38,9 @@ enum : int {
     kSwz = 8, kStaged = 16, kTwPow = 32, kXcd = 128, kStageStride = 256, kWaveSync = 512, kHalfX = 1024,
     kFitRegs = 2048,  // with kHalfX: registers fitted to every workgroup the halved LDS allows
     kLoop = 4096,     // persistent workgroups looping over units, without prefetch
-    kRtSched = 8192   // the radix schedule is a run-time argument (KArgs::sched)
+    kRtSched = 8192,  // the radix schedule is a run-time argument (KArgs::sched)
+    kVec16 = 16384,   // block layout: 16-byte global accesses, pairs of lanes swapping halves
+    kCrossLane = 32768  // intra-wave exchanges as register permutations (DPP, lane swaps)
 };
 
 // Half exchanges (kHalfX): when every stage but the last runs an even number
@@ -542,6 +544,60 @@ struct FftBody {
         t = P::f_fast ? tid / C : tid % T;
     }
 
+    // Sixteen-byte lanes (kVec16).  Stage-0 input e = i R0 + r of thread t is
+    // x[t + off_in(e)], last-stage output e = i RL + q goes to X[t + off_out(e)],
+    // so threads t and t + 1 (t even: lanes 2m and 2m + 1 of one transform)
+    // want neighbouring elements for every e.  The pair moves them two at a
+    // time: the even lane the pair's values e < E/2, the odd lane those
+    // e >= E/2, which lie a constant D further on (half the stage's
+    // butterflies, or half of each butterfly's inputs when a thread runs one
+    // butterfly); then each value crosses to the lane that owns it by one DPP
+    // lane permutation (a VALU operand, no LDS).  The thread-to-butterfly map,
+    // and so every LDS exchange, is unchanged.
+    static constexpr int off_in(int e) { return (e / R0) * T + (e % R0) * (N / R0); }
+    static constexpr int off_out(int e) { return (e / RL) * T + (e % RL) * NsL; }
+    static constexpr bool kPairs = (FL & kVec16) != 0;
+    static_assert(!kPairs || ((P::kind == kKindBlock) && !P::f_fast && T % 2 == 0 &&
+                              (E / R0 == 1 || (E / R0) % 2 == 0) && (E / RL == 1 || (E / RL) % 2 == 0)),
+                  "16-byte lanes: block layout, an even number of threads per transform, and one or an even "
+                  "number of butterflies per thread in the first and last stage");
+
+    template <class Ctx>
+    __device__ static __forceinline__ void load_pairs(const Ctx& cx, int t, float2 (&v)[E])
+    {
+        constexpr int D = off_in(E / 2);
+        const bool odd = (t & 1) != 0;
+        const float2* p = cx.src + ((t & ~1) + (odd ? D : 0));
+        float2 lo[E / 2], hi[E / 2];
+#pragma unroll
+        for (int e = 0; e < E / 2; ++e) {
+            const float4 q = gload2<FL>(p + off_in(e));
+            lo[e] = make_float2(q.x, q.y);
+            hi[e] = make_float2(q.z, q.w);
+        }
+        // even lane: lo = its own value e, hi = the odd lane's; odd lane:
+        // lo = the even lane's value e + E/2, hi = its own
+#pragma unroll
+        for (int e = 0; e < E / 2; ++e) {
+            const float2 xl = lane_xor1(lo[e]), xh = lane_xor1(hi[e]);
+            v[e] = odd ? xh : lo[e];
+            v[e + E / 2] = odd ? hi[e] : xl;
+        }
+    }
+
+    template <class Ctx>
+    __device__ static __forceinline__ void store_pairs(const Ctx& cx, int t, const float2 (&v)[E])
+    {
+        constexpr int D = off_out(E / 2);
+        const bool odd = (t & 1) != 0;
+        float2* p = cx.dst + ((t & ~1) + (odd ? D : 0));
+#pragma unroll
+        for (int e = 0; e < E / 2; ++e) {
+            const float2 xl = lane_xor1(v[e]), xh = lane_xor1(v[e + E / 2]);
+            gstore2<FL>(p + off_out(e), odd ? xh : v[e], odd ? v[e + E / 2] : xl);
+        }
+    }
+
     // The backward transform is conj(forward(conj(x))): the conjugations are
     // skipped by a uniform branch in the forward direction.
     __device__ static __forceinline__ void load(const KArgs& a, long long unit, int f, int t, bool on,
@@ -550,11 +606,15 @@ struct FftBody {
         const bool bwd = a.sg < 0.f;
         const auto cx = P::template ctx<N, C>(a, unit, f);
         if (cx.act && on) {
+            if constexpr ((FL & kVec16) != 0) {
+                load_pairs(cx, t, v);
+            } else {
 #pragma unroll
-            for (int i = 0; i < E / R0; ++i)
+                for (int i = 0; i < E / R0; ++i)
 #pragma unroll
-                for (int r = 0; r < R0; ++r)
-                    v[i * R0 + r] = gload<FL>(in_at_split<P, C>(a, cx, t, i * T + r * (N / R0)));
+                    for (int r = 0; r < R0; ++r)
+                        v[i * R0 + r] = gload<FL>(in_at_split<P, C>(a, cx, t, i * T + r * (N / R0)));
+            }
         } else {
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e] = make_float2(0.f, 0.f);
@@ -657,10 +717,15 @@ struct FftBody {
                 // indices of the stages and keeps them live all along
                 int ts = t;
                 asm volatile("" : "+v"(ts));
+                if constexpr (kPairs) {
+                    store_pairs(cx, ts, v);
+                } else {
 #pragma unroll
-                for (int i = 0; i < E / RL; ++i)
+                    for (int i = 0; i < E / RL; ++i)
 #pragma unroll
-                    for (int q = 0; q < RL; ++q) store_split<P, FL>(a, cx, ts, i * T + q * NsL, v[i * RL + q]);
+                        for (int q = 0; q < RL; ++q)
+                            store_split<P, FL>(a, cx, ts, i * T + q * NsL, v[i * RL + q]);
+                }
             }
         }
     }

@@ -63,11 +63,14 @@ static std::vector<KEntry> build_table()
     const KEntry* f = filter_entries(&nf);
     const KEntry* l = list_entries(&nl);
     const KEntry* r = rt_entries(&nr);
+    int nx = 0;
+    const KEntry* x = xlane_entries(&nx);
     v.insert(v.end(), b, b + nb);
     v.insert(v.end(), p, p + np);
     v.insert(v.end(), f, f + nf);
     v.insert(v.end(), l, l + nl);
     v.insert(v.end(), r, r + nr);
+    v.insert(v.end(), x, x + nx);
     return v;
 }
 
@@ -937,6 +940,10 @@ static fft_status_t execute_impl(fft_plan_t plan, int passes, size_t batch, cons
             KArgs ka = make_args(plan, 1, x, y);
             ka.batch = (long long)batch;
             const KEntry* k = plan->path == FFT_PATH_BLOCK ? block_kernel(plan, batch) : plan->k1;
+            if ((k->flags & FFT_VARIANT_VEC16) != 0 && ((a | b) & 15u) != 0) {
+                if (cur != plan->device) (void)hipSetDevice(cur);
+                return FFT_ERR_INVALID_ARG;  // sixteen-byte lanes need 16-byte aligned data
+            }
             e = k->launch(ka, grid(k, ka, plan->grid1), st, ev0, ev1);
         }
     } else {

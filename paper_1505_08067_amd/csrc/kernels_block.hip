@@ -52,6 +52,15 @@ static const KEntry kBlock[] = {
     FB_BLKH(false, 99, 512, 16, 8, 16, 16, 2),
     // persistent workgroups looping over units (no prefetch)
     FB_BLK(false, 4131, 4096, 16, 1, 16, 16, 16),
+    // sixteen-byte global accesses (lane pairs exchanging halves by DPP)
+    FB_BLK(false, 16419, 4096, 16, 1, 16, 16, 16),
+    FB_BLK(false, 16419, 2048, 16, 2, 16, 16, 8),
+    FB_BLK(false, 16419, 1024, 16, 4, 16, 16, 4),
+    FB_BLK(false, 16419, 256, 16, 16, 16, 16),
+    FB_BLK(false, 17443, 8192, 32, 1, 8, 8, 8, 16),
+    // the schedule of the cross-lane 1024 kernels, with LDS exchanges
+    FB_BLK(false, 35, 1024, 16, 4, 16, 4, 16),
+    FB_BLK(false, 547, 1024, 16, 4, 16, 4, 16),
     // eight values per thread: twice the waves per workgroup at the same LDS
     FB_BLK(false, 35, 8192, 8, 1, 8, 8, 8, 8, 2),
     FB_BLK(false, 35, 2048, 8, 2, 8, 8, 4, 8),

@@ -65,6 +65,8 @@ VARIANT_HALF_EXCHANGE = 1024
 VARIANT_FIT_REGISTERS = 2048
 VARIANT_LOOP = 4096
 VARIANT_RUNTIME_SCHEDULE = 8192
+VARIANT_VEC16 = 16384
+VARIANT_CROSS_LANE = 32768
 STORAGE_C64 = 0
 STORAGE_F16 = 1
 KERNEL_KINDS = {0: "block", 1: "pass1", 2: "pass2", 3: "filter", 4: "list"}

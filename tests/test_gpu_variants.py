@@ -166,3 +166,19 @@ def test_kernel_occupancy_fits_the_compute_unit():
         assert occ >= 1, k["name"]
         assert occ * k["lds_bytes"] <= info["lds_per_cu"], k["name"]
         assert occ * k["threads"] <= max_threads, k["name"]
+
+
+def test_vec16_needs_aligned_data():
+    # sixteen-byte lanes read and write pairs of complex values: a buffer
+    # only 8-byte aligned is refused, not read across a pair boundary
+    k = next(k for k in fb.kernels() if k["kind"] == "block" and k["flags"] & fb.VARIANT_VEC16)
+    n, batch = k["n"], 3
+    say(f"case: {k['name']} misaligned")
+    opts = fb.make_opts(radix=k["radix"], flags=k["flags"], c=k["c"])
+    buf = torch.zeros(n * batch + 1, dtype=torch.complex64, device="cuda")
+    out = torch.zeros_like(buf)
+    with fb.Plan(n, batch, fb.FORWARD, opts) as p:
+        with pytest.raises(fb.FFTError):
+            p.execute(buf[1:], out=out[1:])
+        p.execute(buf[:-1], out=out[:-1])   # aligned views run
+    torch.cuda.synchronize()
