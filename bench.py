@@ -838,6 +838,37 @@ def run_lanes(torch, fb, stream, rounds=7, reps=20):
                         "frac_hbm_peak": round(16.0 * npts / (med * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)}
             p.close()
         res[f"{n}x{batch}"] = row
+    # four-step pass 1 at 2^20 x 16 (512-point columns): the planner's
+    # kernel against the other compiled 512-point pass-1 forms with the same
+    # schedule (wider tiles, workgroups looping over tiles)
+    n, batch = 1 << 20, 16
+    with fb.Plan(n, batch, fb.FORWARD) as p0:
+        d0 = p0.describe()
+    base = next(k for k in fb.kernels() if k["name"] == d0["kernel_name"])
+    cands = [("planner", base)] + [(f"v{k['flags']}_C{k['c']}", k) for k in fb.kernels()
+                                   if k["kind"] == "pass1" and k["n"] == base["n"] and k["radix"] == base["radix"]
+                                   and k is not base and not k["flags"] & fb.VARIANT_FP16_STORAGE]
+    plans = [(lab, fb.Plan(n, batch, fb.FORWARD, fb.make_opts(radix=k["radix"], flags=k["flags"], c=k["c"],
+                                                              n1=base["n"])))
+             for lab, k in cands]
+    times = {lab: [] for lab, _ in plans}
+    for _ in range(rounds):
+        for lab, p in plans:
+            it = [0]
+
+            def step1():
+                xi, yi = sets[it[0] % 4]
+                it[0] += 1
+                p.execute_pass_ptr(1, xi.data_ptr(), yi.data_ptr(), sh)
+            times[lab].append(_timed(torch, stream, step1, reps=reps) * 1e6)
+    row = {}
+    for lab, p in plans:
+        ts = sorted(times[lab])
+        med = ts[len(ts) // 2]
+        row[lab] = {"kernel": p.describe()["kernel_name"], "us": round(med, 2), "spread_us": round(ts[-1] - ts[0], 2),
+                    "frac_hbm_peak": round(16.0 * npts / (med * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)}
+        p.close()
+    res["fourstep_pass1_2^20x16"] = row
     del sets
     log("lanes", json.dumps(res))
     return res

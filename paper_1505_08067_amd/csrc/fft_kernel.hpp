@@ -246,15 +246,53 @@ struct PolPass1T {
     __device__ static void twiddle_outputs(const KArgs& a, const Ctx& c, int t, float2 (&v)[E])
     {
         if constexpr ((FL & kTwPow) != 0) {
-            constexpr int ROW = ((E == 2 ? 1 : E == 4 ? 2 : E == 8 ? 3 : E == 16 ? 4 : 5) + 1) & ~1;
+            constexpr int LP = E == 2 ? 1 : E == 4 ? 2 : E == 8 ? 3 : E == 16 ? 4 : 5;  // log2 E
+            constexpr int ROW = (LP + 1) & ~1;
             const unsigned m0 = (c.col * (unsigned)t) & (unsigned)(a.nbig - 1);
             const float2 b = cmul(a.tw_hi[m0 >> a.lo_bits], a.tw_lo[m0 & ((1u << a.lo_bits) - 1u)]);
-            float2 sp[E];
-            powers_from_row<E>(sp, a.tw_col + (long long)c.col * ROW);
+            float2 p[ROW];  // s^(2^j), j < log2 E
+            const float4* row4 = reinterpret_cast<const float4*>(a.tw_col + (long long)c.col * ROW);
 #pragma unroll
-            for (int i = 0; i < E / RL; ++i)
+            for (int j = 0; j < ROW; j += 2) {
+                const float4 w = row4[j / 2];
+                p[j] = make_float2(w.x, w.y);
+                p[j + 1] = make_float2(w.z, w.w);
+            }
+            // m = r + L h: s^m = s^(L h) s^r, with G[h] = b s^(L h) formed
+            // first and the low powers s^r one at a time, so only H + log2 L
+            // factors stay live next to the values (not all E powers)
+            constexpr int L = E < 8 ? E : 8;
+            constexpr int LL = L == 2 ? 1 : L == 4 ? 2 : 3;
+            constexpr int H = E / L;
+            float2 G[H];
+            G[0] = b;
+            sfor<1, H>([&](auto hc) {
+                constexpr int h = decltype(hc)::value;
+                constexpr int hb = h >= 2 ? 1 : 0;  // highest set bit of h (h < 4)
+                if constexpr (h == (1 << hb))
+                    G[h] = cmul(b, p[LL + hb]);
+                else
+                    G[h] = cmul(G[h - (1 << hb)], p[LL + hb]);
+            });
+            float2 low[L];
+            low[0] = make_float2(1.f, 0.f);
+            sfor<0, L>([&](auto rc) {
+                constexpr int r = decltype(rc)::value;
+                if constexpr (r > 0) {
+                    constexpr int rb = r >= 4 ? 2 : r >= 2 ? 1 : 0;
+                    if constexpr (r == (1 << rb))
+                        low[r] = p[rb];
+                    else
+                        low[r] = cmul(p[rb], low[r - (1 << rb)]);
+                }
 #pragma unroll
-                for (int q = 0; q < RL; ++q) v[i * RL + q] = cmul(v[i * RL + q], cmul(b, sp[i + q * (E / RL)]));
+                for (int h = 0; h < H; ++h) {
+                    constexpr int D = E / RL;
+                    const int m = r + L * h;
+                    float2& x = v[(m % D) * RL + m / D];
+                    x = cmul(x, r == 0 ? G[h] : cmul(G[h], low[r]));
+                }
+            });
         } else {
 #pragma unroll
             for (int i = 0; i < E / RL; ++i)

@@ -47,6 +47,9 @@ static const KEntry kPass[] = {
     // the run-to-run spread, so not the default
     FB_P1(false, 1072, 512, 32, 16, 16, 32),
     FB_P1(false, 1073, 128, 16, 16, 8, 16),
+    // 512: 32-column tiles (256-byte runs), and workgroups looping over tiles
+    FB_P1(false, 1073, 512, 32, 32, 16, 32),
+    FB_P1(false, 5169, 512, 32, 16, 16, 32),
     FB_P2(false, 3106, 2048, 32, 8, 16, 16, 8),
     FB_P2(false, 3362, 2048, 16, 8, 8, 8, 8, 4),
     // persistent workgroups looping over units (no prefetch, no spills)
