@@ -797,8 +797,14 @@ def run_lanes(torch, fb, stream, rounds=7, reps=20):
              torch.empty(npts, dtype=torch.complex64, device="cuda")) for _ in range(4)]
     kinfo = [k for k in fb.kernels() if k["kind"] == "block"]
     res = {}
+
+    def fits(n, batch):
+        # the launches below take raw pointers: every one must stay inside a set
+        if n * batch > npts:
+            raise ValueError(f"{n} x {batch} exceeds the {npts}-point buffer sets")
     for n in (256, 1024, 2048, 4096, 8192):
         batch = npts // n
+        fits(n, batch)
         with fb.Plan(n, batch, fb.FORWARD) as p0:
             d0 = p0.describe()
         base = next(k for k in kinfo if k["name"] == d0["kernel_name"])
@@ -842,6 +848,7 @@ def run_lanes(torch, fb, stream, rounds=7, reps=20):
     # kernel against the other compiled 512-point pass-1 forms with the same
     # schedule (wider tiles, workgroups looping over tiles)
     n, batch = 1 << 20, 16
+    fits(n, batch)
     with fb.Plan(n, batch, fb.FORWARD) as p0:
         d0 = p0.describe()
     base = next(k for k in fb.kernels() if k["name"] == d0["kernel_name"])
@@ -869,6 +876,37 @@ def run_lanes(torch, fb, stream, rounds=7, reps=20):
                     "frac_hbm_peak": round(16.0 * npts / (med * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)}
         p.close()
     res["fourstep_pass1_2^20x16"] = row
+    # range compression (2^24 points per launch): every compiled filter kernel
+    # at 4096, 8192 and 16384 samples per row
+    from paper_1505_08067_amd import inputs
+    rep = torch.from_numpy(inputs.sar_replica()).to("cuda")
+    for n in (4096, 8192, 16384):
+        batch = npts // n
+        fits(n, batch)
+        with fb.RangeCompressor(n, batch, rep) as r0:
+            dflt = r0.describe()["kernel_name"]
+        cands = [k for k in fb.kernels() if k["kind"] == "filter" and k["n"] == n]
+        comps = [(k["name"], fb.RangeCompressor(n, batch, rep, fb.make_opts(radix=k["radix"], flags=k["flags"],
+                                                                             c=k["c"]))) for k in cands]
+        times = {lab: [] for lab, _ in comps}
+        for _ in range(rounds):
+            for lab, rc in comps:
+                it = [0]
+
+                def step_f():
+                    xi, yi = sets[it[0] % 4]
+                    it[0] += 1
+                    rc.execute_ptr(xi.data_ptr(), yi.data_ptr(), sh)
+                times[lab].append(_timed(torch, stream, step_f, reps=reps) * 1e6)
+        row = {"planner": dflt}
+        for lab, rc in comps:
+            ts = sorted(times[lab])
+            med = ts[len(ts) // 2]
+            row[lab] = {"us": round(med, 2), "spread_us": round(ts[-1] - ts[0], 2),
+                        "frac_hbm_peak": round(16.0 * npts / (med * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4),
+                        "workgroups_per_cu": fb.kernel_occupancy(lab)}
+            rc.close()
+        res[f"range_compress_{n}x{batch}"] = row
     del sets
     log("lanes", json.dumps(res))
     return res

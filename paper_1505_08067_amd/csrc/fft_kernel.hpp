@@ -672,15 +672,20 @@ struct FftBody {
         float2* L = lds + (NST > 1 ? f * LDSN : 0);
         const float2* Ltw = lds + TWB;
         run_stages<N, E, S, FL, WS>(v, L, a.tw, Ltw, t, on);
-        static_assert(P::kind != kKindFilter || (FL & kHalfX) == 0, "the filter's round trip needs N slots");
+        static_assert(P::kind != kKindFilter || (FL & kHalfX) == 0 || R0 == RL,
+                      "the filter's round trip between the transforms needs N slots");
         if constexpr (P::kind == kKindFilter) {
             // Z = X conj(H) is transformed back as conj(F(conj Z)), and
             // conj Z = conj(X) H: X[k] sits at v[i RL + q], k = t + i T + q NsL.
+            int tp = t;  // (offsets of the product formed afresh as well)
+            asm volatile("" : "+v"(tp));
+            __builtin_assume(tp >= 0 && tp < T);
+            const float2* flt = a.flt + tp;
 #pragma unroll
             for (int i = 0; i < E / RL; ++i)
 #pragma unroll
                 for (int q = 0; q < RL; ++q) {
-                    const float2 h = a.flt[t + i * T + q * NsL];
+                    const float2 h = flt[i * T + q * NsL];
                     const float2 x = v[i * RL + q];
                     v[i * RL + q] = cmul(make_float2(x.x, -x.y), h);
                 }
@@ -703,7 +708,13 @@ struct FftBody {
                 }
                 // with R0 == RL the outputs already sit where stage 0 wants its inputs
             }
-            run_stages<N, E, S, FL, WS>(v, L, a.tw, Ltw, t, on);
+            // the second transform's thread index behind an empty asm, so its
+            // LDS and twiddle offsets are formed afresh rather than kept live
+            // from the first transform's
+            int t2 = t;
+            asm volatile("" : "+v"(t2));
+            __builtin_assume(t2 >= 0 && t2 < T);
+            run_stages<N, E, S, FL, WS>(v, L, a.tw, Ltw, t2, on);
 #pragma unroll
             for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
         }

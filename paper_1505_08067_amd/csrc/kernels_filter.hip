@@ -25,7 +25,7 @@ static const KEntry kFilter[] = {
     FB_FLT(true, 35, 1024, 16, 4, 16, 4, 16),
     FB_FLT(false, 547, 1024, 16, 4, 16, 4, 16),
     FB_FLT(false, 547, 512, 16, 8, 16, 16, 2),
-    FB_FLT(true, 35, 8192, 16, 1, 16, 8, 4, 16),
+    FB_FLT(false, 35, 8192, 16, 1, 16, 8, 4, 16),
     FB_FLT(false, 35, 8192, 16, 1, 16, 2, 16, 16),
     FB_FLT(false, 43, 8192, 16, 1, 16, 2, 16, 16),
     FB_FLT(false, 35, 8192, 32, 1, 16, 32, 16),
@@ -34,6 +34,15 @@ static const KEntry kFilter[] = {
     FB_FLT(true, 35, 2048, 16, 2, 16, 8, 16),
     FB_FLT(true, 35, 16384, 16, 1, 16, 4, 16, 16),
     FB_FLT(false, 3, 8192, 16, 1, 8, 8, 8, 16),
+    // half exchanges (thirty-two values per thread, first radix = last): half
+    // the LDS, four workgroups per CU instead of two at 8192 (67.6 against
+    // 72.7 us for 2^24 points); slower at 4096 (68.5 / 62.8) and 16384
+    // (100.9 / 89.0), where the registers, not the LDS, set the residency
+    FB_FLT(false, 1059, 8192, 32, 1, 16, 8, 4, 16),
+    FB_FLT(true, 1059, 8192, 32, 1, 16, 16, 2, 16),
+    FB_FLT(false, 3107, 8192, 32, 1, 16, 16, 2, 16),
+    FB_FLT(false, 1059, 4096, 32, 1, 16, 16, 16),
+    FB_FLT(false, 1059, 16384, 32, 1, 16, 4, 16, 16),
 };
 
 const KEntry* filter_entries(int* count)
