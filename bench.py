@@ -844,6 +844,38 @@ def run_lanes(torch, fb, stream, rounds=7, reps=20):
                         "frac_hbm_peak": round(16.0 * npts / (med * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)}
             p.close()
         res[f"{n}x{batch}"] = row
+    # mixed-radix lengths: the planner's kernel against the kernels whose
+    # stages run on different thread counts
+    for n in (6000, 15360):
+        batch = npts // n
+        fits(n, batch)
+        with fb.Plan(n, batch, fb.FORWARD) as p0:
+            d0 = p0.describe()
+        base = next(k for k in kinfo if k["name"] == d0["kernel_name"])
+        cands = [("planner", base)] + [(k["name"], k) for k in kinfo
+                                       if k["n"] == n and k["flags"] & fb.VARIANT_VAR_THREADS]
+        plans = [(lab, fb.Plan(n, batch, fb.FORWARD, fb.make_opts(radix=k["radix"], flags=k["flags"], c=k["c"])))
+                 for lab, k in cands]
+        times = {lab: [] for lab, _ in plans}
+        for _ in range(rounds):
+            for lab, p in plans:
+                it = [0]
+
+                def step_m():
+                    xi, yi = sets[it[0] % 4]
+                    it[0] += 1
+                    p.execute_ptr(xi.data_ptr(), yi.data_ptr(), sh)
+                times[lab].append(_timed(torch, stream, step_m, reps=reps) * 1e6)
+        row = {}
+        for lab, p in plans:
+            ts = sorted(times[lab])
+            med = ts[len(ts) // 2]
+            name = p.describe()["kernel_name"]
+            row[lab] = {"kernel": name, "us": round(med, 2), "spread_us": round(ts[-1] - ts[0], 2),
+                        "frac_hbm_peak": round(16.0 * n * batch / (med * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4),
+                        "workgroups_per_cu": fb.kernel_occupancy(name)}
+            p.close()
+        res[f"{n}x{batch}"] = row
     # four-step pass 1 at 2^20 x 16 (512-point columns): the planner's
     # kernel against the other compiled 512-point pass-1 forms with the same
     # schedule (wider tiles, workgroups looping over tiles)

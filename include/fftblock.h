@@ -223,6 +223,12 @@ typedef struct {
                                          wave are register permutations (DPP, v_permlane16/32_swap)
                                          instead of LDS round trips; with WAVE_SYNC the exchange
                                          over lane bits 0..3 still goes through LDS */
+#define FFT_VARIANT_VAR_THREADS 65536 /* block kernel whose stages run on different numbers of
+                                         threads (each stage's butterflies split evenly over at
+                                         most the workgroup's threads), so a mixed-radix length
+                                         holds few values per thread (15360 = [15,16,16,4] on
+                                         1024 threads: 16 values, not 60); one transform per
+                                         workgroup */
 
 /* Storage of the transform data (fft_plan_opts_t.storage). */
 #define FFT_STORAGE_C64 0   /* interleaved FP32 (re, im), 8 bytes per value */
@@ -248,7 +254,12 @@ typedef struct {
                             (rows n2 up to 2048, columns n1 at least 256) */
     int storage;         /* FFT_STORAGE_C64 (default) or FFT_STORAGE_F16 */
     int device_twiddles; /* nonzero: evaluate the twiddle tables in FP64 on the GPU
-                            (default: FP64 on the host); both round once to FP32 */
+                            (default: FP64 on the host); both round each table entry once
+                            to FP32.  Kernels with FFT_VARIANT_TWIDDLE_POWERS (most
+                            defaults) then form w^r from the entries w^(2^i) with at most
+                            popcount(r) - 1 FP32 complex products, and the four-step long
+                            twiddle as b * s^m; the exact-row variants multiply by entries
+                            rounded once */
 } fft_plan_opts_t;
 
 /* Fill `opts` with "use the defaults". */
@@ -425,7 +436,8 @@ typedef struct {
     int n_candidates;             /* compiled kernels (four-step: kernel pairs) timed whole */
     int candidate_kernel[32];     /* catalogue indices (fft_kernel_info): block or pass-1 kernel */
     int candidate_kernel2[32];    /* pass-2 kernel of a four-step candidate, else -1 */
-    double candidate_us[32];      /* microseconds per execute of `batch` transforms */
+    double candidate_us[32];      /* microseconds per execute of `batch` transforms, rotating over
+                                     buffer sets of up to 512 MiB per side (data from HBM) */
     int chosen_kernel;            /* fastest candidate; recorded as wisdom for n */
     int chosen_kernel2;
     double chosen_us;
@@ -535,8 +547,9 @@ fft_status_t fft_ragged_create_ex(const size_t* sizes, const size_t* counts, siz
  * (device pointers aligned to the element size, in == out allowed, other overlap
  * INVALID_ARG).  Asynchronous.
  *   mode 0: one hipGraphLaunch of a graph whose kernel nodes are the
- *           persistent launches (in sequence) and any uncovered class's
- *           kernels; built on the first call, and on a call with other
+ *           persistent launches and then the kernels of every class with no
+ *           persistent case (the lengths whose own kernels beat any shared
+ *           case), all in sequence; built on the first call, and on a call with other
  *           buffers only the nodes' arguments change.  Launches of one plan
  *           must not overlap in time (they share the queue counters).
  *   mode 1: the plain path -- every class through its own default plan (the

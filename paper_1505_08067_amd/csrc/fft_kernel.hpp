@@ -40,7 +40,8 @@ enum : int {
     kLoop = 4096,     // persistent workgroups looping over units, without prefetch
     kRtSched = 8192,  // the radix schedule is a run-time argument (KArgs::sched)
     kVec16 = 16384,   // block layout: 16-byte global accesses, pairs of lanes swapping halves
-    kCrossLane = 32768  // intra-wave exchanges as register permutations (DPP, lane swaps)
+    kCrossLane = 32768,  // intra-wave exchanges as register permutations (DPP, lane swaps)
+    kVarThreads = 65536  // stages on different thread counts (values per thread per stage)
 };
 
 // Half exchanges (kHalfX): when every stage but the last runs an even number

@@ -63,14 +63,16 @@ static std::vector<KEntry> build_table()
     const KEntry* f = filter_entries(&nf);
     const KEntry* l = list_entries(&nl);
     const KEntry* r = rt_entries(&nr);
-    int nx = 0;
+    int nx = 0, nv = 0;
     const KEntry* x = xlane_entries(&nx);
+    const KEntry* vt = vt_entries(&nv);
     v.insert(v.end(), b, b + nb);
     v.insert(v.end(), p, p + np);
     v.insert(v.end(), f, f + nf);
     v.insert(v.end(), l, l + nl);
     v.insert(v.end(), r, r + nr);
     v.insert(v.end(), x, x + nx);
+    v.insert(v.end(), vt, vt + nv);
     return v;
 }
 

@@ -83,6 +83,7 @@ const KEntry* filter_entries(int* count);
 const KEntry* list_entries(int* count);
 const KEntry* rt_entries(int* count);
 const KEntry* xlane_entries(int* count);
+const KEntry* vt_entries(int* count);
 
 // Kernel the wisdom (autotuner or FFTBLOCK_WISDOM file) chose for length n, or
 // nullptr; for the run-time-schedule kernel also its schedule (radix[0..*nr)).

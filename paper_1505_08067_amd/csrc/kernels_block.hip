@@ -156,8 +156,8 @@ static const KEntry kBlock[] = {
     FB_BLK(true, 0, 1000, 10, 2, 10, 10, 10),
     FB_BLK(false, 35, 1000, 10, 2, 10, 10, 10),
     FB_BLK(true, 35, 3072, 24, 2, 6, 8, 8, 8),
-    FB_BLK(true, 35, 6000, 30, 1, 10, 10, 10, 6),
-    FB_BLK(true, 35, 15360, 60, 1, 12, 20, 4, 4, 4),
+    FB_BLK(false, 35, 6000, 30, 1, 10, 10, 10, 6),
+    FB_BLK(false, 35, 15360, 60, 1, 12, 20, 4, 4, 4),
     FB_BLK(false, 3, 3072, 24, 2, 6, 8, 8, 8),
     FB_BLK(false, 0, 6000, 30, 1, 10, 10, 10, 6),
     FB_BLK(false, 3, 15360, 60, 1, 12, 20, 4, 4, 4),

@@ -388,8 +388,11 @@ bool node_params(fft_ragged_s* r, Node& nd, const void* in, void* out, hipKernel
     return true;
 }
 
-// The mode-0 graph: the persistent launches in sequence, each fallback class's
-// kernels on a branch of its own (pass 2 after pass 1).
+// The mode-0 graph: the persistent launches in sequence, then each fallback
+// class's kernels, also in sequence (pass 2 after pass 1).  A persistent
+// launch fills every resident slot, so a kernel beside it would only take
+// slots from it (measured: 1059 us with the fallback kernels on branches of
+// their own against the sequence).
 fft_status_t build_graph(fft_ragged_s* r, const void* in, void* out)
 {
     hipError_t e = hipGraphCreate(&r->graph, 0);
@@ -424,14 +427,10 @@ fft_status_t build_graph(fft_ragged_s* r, const void* in, void* out)
         Node& nd = r->nodes[i];
         hipKernelNodeParams p;
         if (!node_params(r, nd, in, out, &p)) return FFT_ERR_DEVICE;
-        hipGraphNode_t dep = nullptr;
-        if (nd.launch >= 0)
-            dep = prev;  // the persistent launches in sequence
-        else if (nd.pass == 2)
-            dep = r->nodes[i - 1].node;
+        hipGraphNode_t dep = prev;  // every node after the one before it
         e = hipGraphAddKernelNode(&nd.node, r->graph, dep ? &dep : nullptr, dep ? 1 : 0, &p);
         if (e != hipSuccess) return st_of(e);
-        if (nd.launch >= 0) prev = nd.node;
+        prev = nd.node;
     }
     e = hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return st_of(e);
