@@ -844,6 +844,35 @@ def run_lanes(torch, fb, stream, rounds=7, reps=20):
                         "frac_hbm_peak": round(16.0 * npts / (med * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)}
             p.close()
         res[f"{n}x{batch}"] = row
+    # the long single blocks: every compiled complex64 form
+    for n in (16384, 32768):
+        batch = npts // n
+        fits(n, batch)
+        with fb.Plan(n, batch, fb.FORWARD, fb.make_opts(block_limit=n)) as p0:
+            d0 = p0.describe()
+        cands = [k for k in kinfo if k["n"] == n and not k["flags"] & (fb.VARIANT_FP16_STORAGE |
+                 fb.VARIANT_RUNTIME_SCHEDULE)]
+        plans = [(k["name"], fb.Plan(n, batch, fb.FORWARD, fb.make_opts(radix=k["radix"], flags=k["flags"], c=k["c"],
+                                                                         block_limit=n))) for k in cands]
+        times = {lab: [] for lab, _ in plans}
+        for _ in range(rounds):
+            for lab, p in plans:
+                it = [0]
+
+                def step_l():
+                    xi, yi = sets[it[0] % 4]
+                    it[0] += 1
+                    p.execute_ptr(xi.data_ptr(), yi.data_ptr(), sh)
+                times[lab].append(_timed(torch, stream, step_l, reps=reps) * 1e6)
+        row = {"planner": d0["kernel_name"]}
+        for lab, p in plans:
+            ts = sorted(times[lab])
+            med = ts[len(ts) // 2]
+            row[lab] = {"us": round(med, 2), "spread_us": round(ts[-1] - ts[0], 2),
+                        "frac_hbm_peak": round(16.0 * n * batch / (med * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4),
+                        "workgroups_per_cu": fb.kernel_occupancy(lab)}
+            p.close()
+        res[f"{n}x{batch}"] = row
     # mixed-radix lengths: the planner's kernel against the kernels whose
     # stages run on different thread counts
     for n in (6000, 15360):

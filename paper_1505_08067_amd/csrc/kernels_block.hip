@@ -122,8 +122,9 @@ static const KEntry kBlock[] = {
     FB_BLK(true, 35, 4096, 16, 1, 16, 16, 16),
     // 8192 and 16384: 32 values per thread with half exchanges, so the LDS
     // of a workgroup halves (8192: four workgroups per CU instead of two,
-    // 97 against 102 us for 2^25 points; 16384: two instead of one, 107
-    // against 118 us)
+    // 97 against 102 us for 2^25 points; 16384: two instead of one, 107.7
+    // against 117.3 us, and 57.7 against 61.4 for 2^24; below 512
+    // transforms the 16-value form is faster: 256 x 16.9 / 20.7 us)
     FB_BLK(true, 1059, 8192, 32, 1, 8, 8, 8, 16),
     FB_BLK(false, 43, 8192, 16, 1, 8, 8, 8, 16),
     FB_BLK(false, 35, 8192, 16, 1, 8, 8, 8, 16),

@@ -173,7 +173,9 @@ constexpr KEntry make_vt_entry(bool is_default, const char* name)
 // 35 = streaming loads and stores + power-row twiddles; 65536 = stages on
 // different thread counts.  The defaults for 15360 and 6000 (complex64):
 // 2^24 points, 72.4 against 106.2 us for [12,20,4,4,4] at 60 values per
-// thread, and 59.8 against 65.1 us for [10,10,10,6] at 30.
+// thread, and 59.8 against 65.1 us for [10,10,10,6] at 30.  Exact twiddle
+// rows instead of power rows: 89.5 against 72.3 us at 15360, 66.7 against
+// 62.2 at 6000 (the rows' cache traffic).
 static const KEntry kVt[] = {
     FB_VT(false, 65571, 15360, 1024, 15, 16, 16, 4),
     FB_VT(true, 65571, 15360, 1024, 16, 16, 15, 4),
