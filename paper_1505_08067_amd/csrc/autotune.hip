@@ -99,6 +99,31 @@ struct Wisdom {
     std::mutex mu;
     std::map<size_t, std::pair<std::string, std::string>> choice;  // length -> (block or pass-1, pass-2)
 };
+// Timing inputs: values in [-1, 1) from a counter-based hash of the index
+// (the transforms' time depends on the data: on all-zero inputs some kernels
+// run several per cent faster than on the signals they tune for).
+__global__ void __launch_bounds__(256) k_fill_tuning(float* p, long long n, unsigned seed)
+{
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+        unsigned h = (unsigned)i * 0x9E3779B1u ^ (unsigned)(i >> 32) ^ seed;
+        h ^= h >> 16;
+        h *= 0x85EBCA6Bu;
+        h ^= h >> 13;
+        h *= 0xC2B2AE35u;
+        h ^= h >> 16;
+        p[i] = (float)(h >> 8) * (1.0f / 8388608.0f) - 1.0f;
+    }
+}
+
+static hipError_t fill_tuning(float2* x, size_t values, unsigned seed)
+{
+    const long long nf = (long long)values * 2;
+    const long long blocks = std::min<long long>((nf + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_fill_tuning, dim3((unsigned)blocks), dim3(256), 0, nullptr, reinterpret_cast<float*>(x), nf,
+                       seed);
+    return hipGetLastError();
+}
+
 static Wisdom& wisdom()
 {
     static Wisdom w;
@@ -286,7 +311,7 @@ fft_status_t fft_stage_benchmark(size_t n, int radix, int start_stage, int reps,
     hipError_t e = hipMalloc(&d, batch * n * sizeof(float2));
     if (e == hipSuccess) e = hipMalloc(&dpw, pw.size() * sizeof(float2));
     if (e == hipSuccess) e = hipMemcpy(dpw, pw.data(), pw.size() * sizeof(float2), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(d, 0, batch * n * sizeof(float2));
+    if (e == hipSuccess) e = fill_tuning(d, batch * n, 0x57A6Eu);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -367,7 +392,7 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
     for (int k = 0; k < nsets && e == hipSuccess; ++k) {
         e = hipMalloc(&xs[k], bytes);
         if (e == hipSuccess) e = hipMalloc(&ys[k], bytes);
-        if (e == hipSuccess) e = hipMemset(xs[k], 0, bytes);
+        if (e == hipSuccess) e = fill_tuning(xs[k], n * batch, 0x5EEDu + (unsigned)k);
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&e0);

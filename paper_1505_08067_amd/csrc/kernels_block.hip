@@ -116,7 +116,7 @@ static const KEntry kBlock[] = {
     FB_BLK(true, 35, 256, 16, 16, 16, 16),
     FB_BLK(true, 35, 512, 8, 4, 8, 8, 8),
     FB_BLK(false, 35, 512, 16, 8, 16, 16, 2),
-    FB_BLK(true, 35, 1024, 16, 4, 16, 16, 4),
+    FB_BLK(false, 35, 1024, 16, 4, 16, 16, 4),
     FB_BLK(false, 35, 1024, 8, 2, 8, 8, 4, 4),
     FB_BLK(true, 35, 2048, 16, 2, 16, 16, 8),
     FB_BLK(true, 35, 4096, 16, 1, 16, 16, 16),

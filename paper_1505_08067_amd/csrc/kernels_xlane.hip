@@ -46,7 +46,6 @@ namespace {
 
 constexpr int kXlN = 1024;
 constexpr int kXlE = 16;
-constexpr int kXlC = 4;         // transforms (waves) per workgroup
 constexpr int kXlSlots = 1040;  // LDS slots per transform for exchange 2 (65 * 15 + 64, even)
 
 template <int CTRL, int BANK>
@@ -108,14 +107,15 @@ __device__ __forceinline__ void swap_bits(float2 (&v)[kXlE], int lane)
 
 }  // namespace
 
-// LDSX: exchange 2 through LDS (true) or in registers (false).
-template <int FL, bool LDSX>
-__global__ void __launch_bounds__(64 * kXlC) k_fft_xl1024(KArgs a)
+// LDSX: exchange 2 through LDS (true) or in registers (false); C transforms
+// (waves) per workgroup.
+template <int FL, bool LDSX, int C>
+__global__ void __launch_bounds__(64 * C) k_fft_xl1024(KArgs a)
 {
     constexpr int N = kXlN;
     const int tid = threadIdx.x;
     const int w = tid >> 6, l = tid & 63;
-    const long long b = (long long)blockIdx.x * kXlC + w;
+    const long long b = (long long)blockIdx.x * C + w;
     const bool act = b < a.batch;  // the same in every lane of the wave
     const float2* src = a.in + (act ? b : 0) * N;
     float2* dst = a.out + (act ? b : 0) * N;
@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(64 * kXlC) k_fft_xl1024(KArgs a)
     int ks;  // the lane's output offset: k = ks + 64 f
     if constexpr (LDSX) {
         // exchange 2 through this wave's own LDS slots (wave-synchronous)
-        __shared__ __attribute__((aligned(16))) float2 lds[kXlC * kXlSlots];
+        __shared__ __attribute__((aligned(16))) float2 lds[C * kXlSlots];
         float2* L = lds + w * kXlSlots;
         const int dhi = ((l >> 4) & 3) << 2;  // d2, d3
 #pragma unroll
@@ -194,23 +194,23 @@ __global__ void __launch_bounds__(64 * kXlC) k_fft_xl1024(KArgs a)
     }
 }
 
-template <int FL, bool LDSX>
+template <int FL, bool LDSX, int C>
 hipError_t launch_fft_xl(const KArgs& a, long long grid, hipStream_t st, hipEvent_t start, hipEvent_t stop)
 {
     if (grid <= 0 || grid > 0x7fffffffLL) return hipErrorInvalidValue;
     if (start || stop)
-        hipExtLaunchKernelGGL((k_fft_xl1024<FL, LDSX>), dim3((unsigned)grid), dim3(64 * kXlC), 0, st, start, stop, 0,
+        hipExtLaunchKernelGGL((k_fft_xl1024<FL, LDSX, C>), dim3((unsigned)grid), dim3(64 * C), 0, st, start, stop, 0,
                               a);
     else
-        hipLaunchKernelGGL((k_fft_xl1024<FL, LDSX>), dim3((unsigned)grid), dim3(64 * kXlC), 0, st, a);
+        hipLaunchKernelGGL((k_fft_xl1024<FL, LDSX, C>), dim3((unsigned)grid), dim3(64 * C), 0, st, a);
     return hipGetLastError();
 }
 
-template <int FL, bool LDSX>
+template <int FL, bool LDSX, int C>
 int occupancy_fft_xl()
 {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void*)&k_fft_xl1024<FL, LDSX>, 64 * kXlC, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, (const void*)&k_fft_xl1024<FL, LDSX, C>, 64 * C, 0) !=
         hipSuccess)
         return 0;
     return blocks;
@@ -218,26 +218,26 @@ int occupancy_fft_xl()
 
 // Catalogue entry: schedule [16, 4, 16] with power-row twiddles (the plan
 // builds that schedule's table).
-template <int FL, bool LDSX>
-constexpr KEntry make_xl_entry(const char* name)
+template <int FL, bool LDSX, int C>
+constexpr KEntry make_xl_entry(bool is_default, const char* name)
 {
     using S = Sched<16, 4, 16>;
     KEntry k{};
     k.kind = kKindBlock;
     k.n = kXlN;
     k.e = kXlE;
-    k.c = kXlC;
+    k.c = C;
     k.flags = FL;
     k.nr = S::count;
     for (int i = 0; i < S::count; ++i) k.radix[i] = S::r(i);
     k.tw_size = S::ptw_size();
-    k.threads = 64 * kXlC;
-    k.lds = LDSX ? (size_t)kXlC * kXlSlots * sizeof(float2) : 0;
-    k.is_default = false;
-    k.launch = &launch_fft_xl<FL, LDSX>;
-    k.occupancy = &occupancy_fft_xl<FL, LDSX>;
+    k.threads = 64 * C;
+    k.lds = LDSX ? (size_t)C * kXlSlots * sizeof(float2) : 0;
+    k.is_default = is_default;
+    k.launch = &launch_fft_xl<FL, LDSX, C>;
+    k.occupancy = &occupancy_fft_xl<FL, LDSX, C>;
     k.name = name;
-    k.fn = reinterpret_cast<const void*>(&k_fft_xl1024<FL, LDSX>);
+    k.fn = reinterpret_cast<const void*>(&k_fft_xl1024<FL, LDSX, C>);
     return k;
 }
 
@@ -246,10 +246,15 @@ static_assert(Sched<16, 4, 16>::ptw_off(2) == 32 && Sched<16, 4, 16>::p_row(2) =
               "the kernel reads the power rows of [16, 4, 16] at these offsets");
 
 // 35 = streaming loads and stores + power-row twiddles; 32768 = cross-lane
-// exchanges; with 512 (wave-synchronous) the second exchange uses LDS.
+// exchanges; with 512 (wave-synchronous) the second exchange uses LDS.  The
+// all-register form is the default at 1024 (complex64): on random data,
+// 2^24 points cold, 46.0 against 49.7 us for [16,16,4] with LDS exchanges
+// in the autotuner's timing, 45.7-46.9 against 46.4-50.1 in the bench's;
+// its one-wave form (C = 1) serves small batches.
 static const KEntry kXl[] = {
-    make_xl_entry<35 | kCrossLane | kWaveSync, true>("block_fft_xl<1024,[16, 4, 16],v33315>"),
-    make_xl_entry<35 | kCrossLane, false>("block_fft_xl<1024,[16, 4, 16],v32803>"),
+    make_xl_entry<35 | kCrossLane | kWaveSync, true, 4>(false, "block_fft_xl<1024,[16, 4, 16],v33315>"),
+    make_xl_entry<35 | kCrossLane, false, 4>(true, "block_fft_xl<1024,[16, 4, 16],v32803>"),
+    make_xl_entry<35 | kCrossLane, false, 1>(false, "block_fft_xl<1024,C1,[16, 4, 16],v32803>"),
 };
 
 const KEntry* xlane_entries(int* count)
