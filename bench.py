@@ -937,6 +937,34 @@ def run_lanes(torch, fb, stream, rounds=7, reps=20):
                     "frac_hbm_peak": round(16.0 * npts / (med * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)}
         p.close()
     res["fourstep_pass1_2^20x16"] = row
+    # pass 2 (2048-point rows) the same way: the planner's kernel against the
+    # other compiled forms of its schedule and width
+    base2 = next(k for k in fb.kernels() if k["name"] == d0["kernel_name2"])
+    cands = [("planner", base2)] + [(f"v{k['flags']}_C{k['c']}", k) for k in fb.kernels()
+                                    if k["kind"] == "pass2" and k["n"] == base2["n"] and k["radix"] == base2["radix"]
+                                    and k["c"] == base2["c"] and k is not base2
+                                    and not k["flags"] & fb.VARIANT_FP16_STORAGE]
+    plans = [(lab, fb.Plan(n, batch, fb.FORWARD, fb.make_opts(n1=base["n"], flags2=k["flags"], c2=k["c"])))
+             for lab, k in cands]
+    times = {lab: [] for lab, _ in plans}
+    for _ in range(rounds):
+        for lab, p in plans:
+            it = [0]
+
+            def step2():
+                xi, yi = sets[it[0] % 4]
+                it[0] += 1
+                p.execute_pass_ptr(2, xi.data_ptr(), yi.data_ptr(), sh)
+            times[lab].append(_timed(torch, stream, step2, reps=reps) * 1e6)
+    row = {}
+    for lab, p in plans:
+        ts = sorted(times[lab])
+        med = ts[len(ts) // 2]
+        row[lab] = {"kernel": p.describe()["kernel_name2"], "us": round(med, 2),
+                    "spread_us": round(ts[-1] - ts[0], 2),
+                    "frac_hbm_peak": round(16.0 * npts / (med * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)}
+        p.close()
+    res["fourstep_pass2_2^20x16"] = row
     # range compression (2^24 points per launch): every compiled filter kernel
     # at 4096, 8192 and 16384 samples per row
     from paper_1505_08067_amd import inputs
