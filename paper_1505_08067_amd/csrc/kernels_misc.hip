@@ -1,10 +1,11 @@
 // Corner-turn transpose and the HBM copy probe.
 //
 // Transpose (paper, Approach, "Top level analysis": a large matrix transpose
-// split into smaller blocks): each workgroup moves one TILE x TILE tile of
-// complex values through LDS.  Reads walk rows and writes walk columns of the
-// input, so both sides are coalesced; the LDS tile has one pad column so the
-// column-wise LDS reads hit distinct banks.  The values are copied bit for bit.
+// split into smaller blocks): each workgroup moves one tile of complex values
+// (64 x 64, or 32 x 128 for matrices wider than tall) through LDS.  Reads
+// walk rows and writes walk columns of the input, so both sides are
+// coalesced; the LDS tile has one pad column so the column-wise LDS reads hit
+// distinct banks.  The values are copied bit for bit.
 //
 // Tile order: workgroup w of tile row tr takes tile column w XOR tr (w + tr
 // modulo the count when that is no power of two).  The resident workgroups
@@ -76,52 +77,68 @@ k_transpose(const float2* __restrict__ in, float2* __restrict__ out, long long r
 // Even row and column counts with 16-byte aligned buffers: each lane moves
 // two complex values (16 bytes) per access on both sides; tiles hanging over
 // the matrix edge are guarded per pair (pairs never straddle the edge since
-// both counts are even).
+// both counts are even).  A tile is TR rows by TC columns of the input: the
+// reads run TC * 8 bytes along an input row, the writes TR * 8 bytes along an
+// output row.
+template <int TR, int TC>
 __global__ void __launch_bounds__(kTransposeThreads)
 k_transpose16(const float2* __restrict__ in, float2* __restrict__ out, long long rows, long long cols,
               long long tiles_r, long long tiles_c)
 {
-    __shared__ float2 tile[kTile][kTile + 1];
+    __shared__ float2 tile[TR][TC + 1];
     const long long blk = blockIdx.x;
     const long long per_mat = tiles_r * tiles_c;
     const long long b = blk / per_mat;
     const long long rem = blk - b * per_mat;
     long long tr, tc;
     tile_of(rem, tiles_c, tr, tc);
-    const long long r0 = tr * kTile, c0 = tc * kTile;
-    const int tx = threadIdx.x % (kTile / 2);
-    const int ty = threadIdx.x / (kTile / 2);
-    constexpr int step = kTransposeThreads / (kTile / 2);
+    const long long r0 = tr * TR, c0 = tc * TC;
     const float2* __restrict__ src = in + b * rows * cols;
     float2* __restrict__ dst = out + b * rows * cols;
-    const bool full = (r0 + kTile <= rows) && (c0 + kTile <= cols);
-    for (int i = ty; i < kTile; i += step) {
-        if (full || (r0 + i < rows && c0 + 2 * tx < cols)) {
-            const float4 v = *reinterpret_cast<const float4*>(src + (r0 + i) * cols + c0 + 2 * tx);
-            tile[i][2 * tx] = make_float2(v.x, v.y);
-            tile[i][2 * tx + 1] = make_float2(v.z, v.w);
+    const bool full = (r0 + TR <= rows) && (c0 + TC <= cols);
+    {
+        constexpr int PX = TC / 2;  // pairs along an input row
+        const int tx = threadIdx.x % PX, ty = threadIdx.x / PX;
+        for (int i = ty; i < TR; i += kTransposeThreads / PX) {
+            if (full || (r0 + i < rows && c0 + 2 * tx < cols)) {
+                const float4 v = *reinterpret_cast<const float4*>(src + (r0 + i) * cols + c0 + 2 * tx);
+                tile[i][2 * tx] = make_float2(v.x, v.y);
+                tile[i][2 * tx + 1] = make_float2(v.z, v.w);
+            }
         }
     }
     __syncthreads();
-    for (int i = ty; i < kTile; i += step) {
-        if (full || (c0 + i < cols && r0 + 2 * tx < rows)) {
-            const float2 a = tile[2 * tx][i], c = tile[2 * tx + 1][i];
-            *reinterpret_cast<float4*>(dst + (c0 + i) * rows + r0 + 2 * tx) = make_float4(a.x, a.y, c.x, c.y);
+    {
+        constexpr int QX = TR / 2;  // pairs along an output row
+        const int ux = threadIdx.x % QX, uy = threadIdx.x / QX;
+        for (int i = uy; i < TC; i += kTransposeThreads / QX) {
+            if (full || (c0 + i < cols && r0 + 2 * ux < rows)) {
+                const float2 a = tile[2 * ux][i], c = tile[2 * ux + 1][i];
+                *reinterpret_cast<float4*>(dst + (c0 + i) * rows + r0 + 2 * ux) = make_float4(a.x, a.y, c.x, c.y);
+            }
         }
     }
 }
 
+// Wider than tall: 32 x 128 tiles (1 KB read runs), measured 103.3 against
+// 106.8 us for 4096 x 8192 (cold, XOR order); otherwise 64 x 64 (8192 x 4096:
+// 106.4 against 109.2 for 32 x 128).
 hipError_t launch_transpose(const float2* in, float2* out, long long rows, long long cols, long long batch,
                             hipStream_t st)
 {
-    const long long tr = (rows + kTile - 1) / kTile;
-    const long long tc = (cols + kTile - 1) / kTile;
+    const bool vec = (rows % 2 == 0) && (cols % 2 == 0) && ((uintptr_t)in % 16 == 0) && ((uintptr_t)out % 16 == 0);
+    const bool wide = vec && cols > rows;
+    const long long TR = wide ? 32 : kTile, TC = wide ? 128 : kTile;
+    const long long tr = (rows + TR - 1) / TR;
+    const long long tc = (cols + TC - 1) / TC;
     const long long grid = tr * tc * batch;
     if (grid <= 0 || grid > 0x7fffffffLL) return hipErrorInvalidValue;
-    const bool vec = (rows % 2 == 0) && (cols % 2 == 0) && ((uintptr_t)in % 16 == 0) && ((uintptr_t)out % 16 == 0);
-    if (vec)
-        hipLaunchKernelGGL(k_transpose16, dim3((unsigned)grid), dim3(kTransposeThreads), 0, st, in, out, rows, cols,
-                           tr, tc);
+    if (wide)
+        hipLaunchKernelGGL((k_transpose16<32, 128>), dim3((unsigned)grid), dim3(kTransposeThreads), 0, st, in, out,
+                           rows, cols, tr, tc);
+    else if (vec)
+        hipLaunchKernelGGL((k_transpose16<kTile, kTile>), dim3((unsigned)grid), dim3(kTransposeThreads), 0, st, in,
+                           out, rows, cols, tr, tc);
     else
         hipLaunchKernelGGL(k_transpose, dim3((unsigned)grid), dim3(kTransposeThreads), 0, st, in, out, rows, cols,
                            tr, tc);

@@ -188,7 +188,8 @@ def test_deterministic_repeat():
 
 
 # ---------------------------------------------------------------- transpose
-@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 100, 37), (1, 64, 64), (2, 65, 129), (2, 66, 130), (3, 2, 200), (1, 4096, 8192)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 100, 37), (1, 64, 64), (2, 65, 129), (2, 66, 130), (2, 130, 66),
+                                   (2, 34, 258), (3, 2, 200), (1, 4096, 8192), (1, 8192, 4096)])
 def test_transpose_bit_exact(shape):
     say(f"case: transpose {shape}")
     rng = np.random.default_rng(14)
