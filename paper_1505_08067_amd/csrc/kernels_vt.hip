@@ -13,7 +13,14 @@
 // to its barriers.  Stage formulas, twiddle table and LDS layout are those
 // of the Stockham kernel: butterfly j of stage s (Ns points combined before
 // it) reads slots j + r N/R_s and writes slots (j / Ns) Ns R_s + j mod Ns +
-// q Ns.  One transform per workgroup; every exchange uses N LDS slots.
+// q Ns.  One transform per workgroup.
+//
+// Half exchanges (kHalfX): when every stage but the last runs an even number
+// of butterflies per thread and every stage after the first has an even
+// radix, the butterflies j < N/2R of a stage (the first half of each
+// thread's) write exactly the lower N/2 slots, and the next stage's inputs
+// r < R'/2 are exactly those slots, so each exchange runs in two rounds
+// through N/2 slots: half the LDS per workgroup.
 #include "fft_kernel.hpp"
 
 namespace fb {
@@ -37,6 +44,12 @@ struct VtShape {
             if ((N / S::r(s)) % bpt(s) != 0 || ts(s) > T) return false;
         return S::n() == N;
     }
+    static constexpr bool half_ok()
+    {
+        for (int s = 0; s + 1 < S::count; ++s)
+            if (bpt(s) % 2 != 0 || S::r(s + 1) % 2 != 0) return false;
+        return true;
+    }
 };
 
 }  // namespace
@@ -46,9 +59,11 @@ __global__ void __launch_bounds__(T) k_fft_vt(KArgs a)
 {
     using V = VtShape<N, T, S>;
     static_assert(V::valid(), "every stage must split its butterflies evenly over at most T threads");
+    constexpr bool HX = (FL & kHalfX) != 0;
+    static_assert(!HX || V::half_ok(), "half exchanges need even butterfly counts and even radices after stage 0");
     constexpr int E = V::emax();
     constexpr int NST = S::count;
-    constexpr int LDSN = lds_pad(N) + 1;
+    constexpr int LDSN = lds_pad(HX ? N / 2 : N) + 1;
     __shared__ __attribute__((aligned(16))) float2 L[LDSN];
 
     const int t = threadIdx.x;
@@ -78,10 +93,12 @@ __global__ void __launch_bounds__(T) k_fft_vt(KArgs a)
                 }
             }
         } else if (on) {
+            if constexpr (!HX) {
 #pragma unroll
-            for (int i = 0; i < BP; ++i)
+                for (int i = 0; i < BP; ++i)
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[i * R + r] = L[lds_pad(t + i * TS + r * (N / R))];
+                    for (int r = 0; r < R; ++r) v[i * R + r] = L[lds_pad(t + i * TS + r * (N / R))];
+            }  // half exchanges read this stage's inputs during the exchange itself
 #pragma unroll
             for (int i = 0; i < BP; ++i) {
                 const int k = (t + i * TS) % Ns;
@@ -95,7 +112,7 @@ __global__ void __launch_bounds__(T) k_fft_vt(KArgs a)
 #pragma unroll
             for (int i = 0; i < BP; ++i) Dft<R>::run(&v[i * R]);
         }
-        if constexpr (s < NST - 1) {
+        if constexpr (s < NST - 1 && !HX) {
             if constexpr (s > 0) __syncthreads();  // every read of the last exchange precedes these writes
             if (on) {
 #pragma unroll
@@ -107,6 +124,37 @@ __global__ void __launch_bounds__(T) k_fft_vt(KArgs a)
                 }
             }
             __syncthreads();
+        } else if constexpr (s < NST - 1) {
+            // round h: butterflies [h BP/2, (h+1) BP/2) of this stage write
+            // half h of the slots; the next stage reads its inputs
+            // r in [h R2/2, (h+1) R2/2) from them
+            constexpr int R2 = S::r(s + 1);
+            constexpr int BP2 = V::bpt(s + 1);
+            constexpr int TS2 = V::ts(s + 1);
+            float2 w[E];
+            sfor<0, 2>([&](auto hc) {
+                constexpr int h = decltype(hc)::value;
+                if constexpr (h > 0 || s > 0) __syncthreads();  // earlier reads precede these writes
+                if (on) {
+#pragma unroll
+                    for (int i = h * (BP / 2); i < (h + 1) * (BP / 2); ++i) {
+                        const int j = t + i * TS;
+                        const int base = (j / Ns) * Ns * R + (j % Ns) - h * (N / 2);
+#pragma unroll
+                        for (int q = 0; q < R; ++q) L[lds_pad(base + q * Ns)] = v[i * R + q];
+                    }
+                }
+                __syncthreads();
+                if (t < TS2) {
+#pragma unroll
+                    for (int i2 = 0; i2 < BP2; ++i2)
+#pragma unroll
+                        for (int r = h * (R2 / 2); r < (h + 1) * (R2 / 2); ++r)
+                            w[i2 * R2 + r] = L[lds_pad(t + i2 * TS2 + r * (N / R2) - h * (N / 2))];
+                }
+            });
+#pragma unroll
+            for (int e = 0; e < BP2 * R2; ++e) v[e] = w[e];
         } else if (on && act) {
             // last stage: Ns R = N, so output q of butterfly j is X[j + q Ns]
             if (bwd) {
@@ -158,7 +206,7 @@ constexpr KEntry make_vt_entry(bool is_default, const char* name)
     for (int i = 0; i < S::count && i < 8; ++i) k.radix[i] = S::r(i);
     k.tw_size = (FL & kTwPow) != 0 ? S::ptw_size() : S::tw_size();
     k.threads = T;
-    k.lds = (size_t)(lds_pad(N) + 1) * sizeof(float2);
+    k.lds = (size_t)(lds_pad((FL & kHalfX) != 0 ? N / 2 : N) + 1) * sizeof(float2);
     k.is_default = is_default;
     k.launch = &launch_fft_vt<N, T, S, FL>;
     k.occupancy = &occupancy_fft_vt<N, T, S, FL>;
@@ -172,14 +220,17 @@ constexpr KEntry make_vt_entry(bool is_default, const char* name)
 
 // 35 = streaming loads and stores + power-row twiddles; 65536 = stages on
 // different thread counts.  The defaults for 15360 and 6000 (complex64):
-// 2^24 points, 72.4 against 106.2 us for [12,20,4,4,4] at 60 values per
-// thread, and 59.8 against 65.1 us for [10,10,10,6] at 30.  Exact twiddle
+// 2^24 points, 70.4 (half exchanges, 512 threads) and 72.2 (1024 threads)
+// against 106.2 us for [12,20,4,4,4] at 60 values per thread, and 59.8
+// against 65.1 us for [10,10,10,6] at 30.  Exact twiddle
 // rows instead of power rows: 89.5 against 72.3 us at 15360, 66.7 against
 // 62.2 at 6000 (the rows' cache traffic).
 static const KEntry kVt[] = {
     FB_VT(false, 65571, 15360, 1024, 15, 16, 16, 4),
-    FB_VT(true, 65571, 15360, 1024, 16, 16, 15, 4),
+    FB_VT(false, 65571, 15360, 1024, 16, 16, 15, 4),
     FB_VT(false, 65571, 15360, 1024, 16, 15, 16, 4),
+    // half exchanges: 512 threads, two workgroups per CU (70.4 against 72.2 us)
+    FB_VT(true, 66595, 15360, 512, 15, 16, 16, 4),
     FB_VT(false, 65571, 6000, 600, 10, 10, 10, 6),
     FB_VT(true, 65571, 6000, 600, 12, 10, 10, 5),
 };
