@@ -749,18 +749,26 @@ def run_schedule_model(torch, fb, stream):
             t = _timed(torch, stream, step, reps=12)
         model.append(c)
         measured.append(t * 1e6)
-    # the compiled kernel the autotuner chose (its own timing ping-pongs one
-    # buffer pair, partly cache-resident), timed here the same way as the rest
-    with fb.Plan(n, batch, fb.FORWARD) as p:
-        chosen_name = p.describe()["kernel_name"]
-        k = [0]
-
-        def step_c():
-            xi, yi = sets[k[0] % 4]
-            k[0] += 1
-            p.execute_ptr(xi.data_ptr(), yi.data_ptr(), sh)
-        t_chosen = _timed(torch, stream, step_c, reps=12) * 1e6
+    # the kernel the autotuner chose and the planner's default, timed the
+    # same way as the schedules, in interleaved rounds
+    p_tuned = fb.Plan(n, batch, fb.FORWARD)
     fb.wisdom_clear()
+    p_dflt = fb.Plan(n, batch, fb.FORWARD)
+    chosen_name, dflt_name = p_tuned.describe()["kernel_name"], p_dflt.describe()["kernel_name"]
+    tt = {"tuned": [], "default": []}
+    for _ in range(5):
+        for lab, p in (("tuned", p_tuned), ("default", p_dflt)):
+            k = [0]
+
+            def step_c():
+                xi, yi = sets[k[0] % 4]
+                k[0] += 1
+                p.execute_ptr(xi.data_ptr(), yi.data_ptr(), sh)
+            tt[lab].append(_timed(torch, stream, step_c, reps=12) * 1e6)
+    p_tuned.close()
+    p_dflt.close()
+    t_chosen = sorted(tt["tuned"])[2]
+    t_dflt = sorted(tt["default"])[2]
     del sets
     model, measured = np.array(model), np.array(measured)
     rk = lambda v: np.argsort(np.argsort(v))
@@ -775,6 +783,7 @@ def run_schedule_model(torch, fb, stream):
            "best_measured": scheds[int(order[0])], "best_measured_us": round(float(measured[order[0]]), 2),
            "worst_measured_us": round(float(measured[order[-1]]), 2),
            "autotuned_kernel": chosen_name, "autotuned_kernel_us": round(t_chosen, 2),
+           "default_kernel": dflt_name, "default_kernel_us": round(t_dflt, 2),
            "paper_schedules_us": {key(sc): round(float(measured[scheds.index(sc)]), 2)
                                   for sc in ([8, 8, 8, 2], [4, 8, 8, 4], [8, 8, 4, 4], [16, 16, 4])}}
     log("schedule model", json.dumps(res))

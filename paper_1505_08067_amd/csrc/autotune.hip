@@ -410,6 +410,21 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         return (double)ms * 1e3 / reps;
     };
+    // Candidates are timed in interleaved rounds (every candidate once per
+    // round) and ranked by their median round: kernels within a few per cent
+    // of each other would otherwise be ranked by the drift of the clocks
+    // between one timing and the next.
+    constexpr int kRounds = 5;
+    struct Cand {
+        fft_plan_t p;
+        int i, j;
+        double t[kRounds];
+    };
+    std::vector<Cand> cands;
+    auto median_of = [](double* v, int m) {
+        std::sort(v, v + m);
+        return v[m / 2];
+    };
     fft_plan_desc_t dq;
     const bool four = fft_plan_query(n, batch, FFT_FORWARD, &dq) == FFT_SUCCESS && dq.path == FFT_PATH_FOURSTEP;
     if (four) {
@@ -444,19 +459,12 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
                 fft_plan_desc_t d;
                 fft_plan_describe(p, &d);
                 const bool same = std::strcmp(d.kernel_name, t[i].name) == 0 && std::strcmp(d.kernel_name2, t[j].name) == 0;
-                const double us = same ? time_plan(p) : -1.0;
-                fft_plan_destroy(p);
-                if (!same) continue;
-                rep->candidate_kernel[rep->n_candidates] = i;
-                rep->candidate_kernel2[rep->n_candidates] = j;
-                rep->candidate_us[rep->n_candidates] = us;
-                rep->n_candidates++;
-                if (us < best) {
-                    best = us;
-                    rep->chosen_kernel = i;
-                    rep->chosen_kernel2 = j;
-                    rep->chosen_us = us;
+                if (!same) {
+                    fft_plan_destroy(p);
+                    continue;
                 }
+                cands.push_back({p, i, j, {}});
+                rep->n_candidates++;
             }
         }
         }
@@ -481,15 +489,22 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
             fft_plan_destroy(p);
             continue;
         }
-        const double us = time_plan(p);
-        fft_plan_destroy(p);
-        rep->candidate_kernel[rep->n_candidates] = i;
-        rep->candidate_kernel2[rep->n_candidates] = -1;
-        rep->candidate_us[rep->n_candidates] = us;
+        cands.push_back({p, i, -1, {}});
         rep->n_candidates++;
-        if (us < best) {
+    }
+    for (int r = 0; r < kRounds && e == hipSuccess; ++r)
+        for (Cand& c : cands) c.t[r] = time_plan(c.p);
+    for (size_t k = 0; k < cands.size(); ++k) {
+        Cand& c = cands[k];
+        const double us = e == hipSuccess ? median_of(c.t, kRounds) : -1.0;
+        fft_plan_destroy(c.p);
+        rep->candidate_kernel[k] = c.i;
+        rep->candidate_kernel2[k] = c.j;
+        rep->candidate_us[k] = us;
+        if (e == hipSuccess && us < best) {
             best = us;
-            rep->chosen_kernel = i;
+            rep->chosen_kernel = c.i;
+            rep->chosen_kernel2 = c.j;
             rep->chosen_us = us;
         }
     }
@@ -511,9 +526,10 @@ fft_status_t fft_autotune(size_t n, size_t batch, fft_tune_report_t* rep)
             o.block_limit = kMaxBlockLen;
             fft_plan_t p = nullptr;
             if (fft_plan_create_ex(n, batch, FFT_FORWARD, &o, &p) != FFT_SUCCESS) return -1.0;
-            const double us = time_plan(p);
+            double ts[kRounds];
+            for (int r = 0; r < kRounds; ++r) ts[r] = time_plan(p);
             fft_plan_destroy(p);
-            return us;
+            return median_of(ts, kRounds);
         };
         rep->predicted_us = time_rt(rep->predicted, rep->n_predicted);
         const KEntry* ck = rep->chosen_kernel >= 0 ? &t[rep->chosen_kernel] : nullptr;
