@@ -547,18 +547,23 @@ def run_fp16(torch, fb, inputs, stream):
     """FP16 storage (FP32 arithmetic): 4096 x 4096 and 2^20 x 16 forward, 8 B per point per pass."""
     res = {}
     sh = stream.cuda_stream
-    for n, batch in ((4096, 4096), (1 << 20, 16)):
+    for n, batch, storage in ((4096, 4096, fb.STORAGE_F16), (1 << 20, 16, fb.STORAGE_F16),
+                              (1 << 20, 16, fb.STORAGE_F16_COMPACT)):
         x = torch.from_numpy(inputs.uniform(1, batch, n)).to("cuda").to(torch.complex32)
         y = torch.empty_like(x)
-        with fb.Plan(n, batch, fb.FORWARD, fb.make_opts(storage=fb.STORAGE_F16)) as p:
+        with fb.Plan(n, batch, fb.FORWARD, fb.make_opts(storage=storage)) as p:
             d = p.describe()
             t = _timed(torch, stream, lambda: p.execute_ptr(x.data_ptr(), y.data_ptr(), sh))
         passes = 2 if d["path"] == fb.PATH_FOURSTEP else 1
-        res[f"{n}x{batch}"] = {
+        compact = storage == fb.STORAGE_F16_COMPACT
+        # bytes per point: 4 in + 4 out per pass, the workspace complex64 (8 + 8) unless compact
+        bpp = 8.0 if passes == 1 else 16.0 if compact else 24.0
+        res[f"{n}x{batch}" + ("_compact" if compact else "")] = {
             "kernels": [d["kernel_name"]] + ([d["kernel_name2"]] if passes == 2 else []),
             "us": round(t * 1e6, 1), "GFLOPs": round(5.0 * n * math.log2(n) * batch / t / 1e9, 1),
-            "GBps_storage": round(8.0 * n * batch * passes / t / 1e9, 1),
-            "note": "pass-1 output and pass-2 input stay complex64 on the four-step path" if passes == 2 else ""}
+            "bytes_per_point": bpp, "GBps": round(bpp * n * batch / t / 1e9, 1),
+            "note": ("pass-1 output and pass-2 input FP16 as well" if compact else
+                     "pass-1 output and pass-2 input stay complex64") if passes == 2 else ""}
         del x, y
     sizes = inputs.ragged_sizes(3)
     classes = [(int(n), int((sizes == n).sum())) for n in inputs.RAGGED_POW2 + inputs.RAGGED_MIXED]

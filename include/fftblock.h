@@ -183,7 +183,7 @@ typedef struct {
     int flags2;               /* variant flags of the pass-2 kernel */
     int c2;                   /* pass-2 rows per workgroup = workspace block width */
     long long grid;           /* workgroups of the (first) launch; 0 from fft_plan_query */
-    int storage;              /* FFT_STORAGE_C64 or FFT_STORAGE_F16 */
+    int storage;              /* FFT_STORAGE_C64, FFT_STORAGE_F16 or FFT_STORAGE_F16_COMPACT */
     int device_twiddles;      /* tables evaluated on the GPU */
 } fft_plan_desc_t;
 
@@ -229,6 +229,7 @@ typedef struct {
                                          holds few values per thread (15360 = [15,16,16,4] on
                                          1024 threads: 16 values, not 60); one transform per
                                          workgroup */
+#define FFT_VARIANT_FP16_WORKSPACE 524288 /* four-step passes of FFT_STORAGE_F16_COMPACT: FP16 workspace */
 
 /* Storage of the transform data (fft_plan_opts_t.storage). */
 #define FFT_STORAGE_C64 0   /* interleaved FP32 (re, im), 8 bytes per value */
@@ -238,6 +239,11 @@ typedef struct {
                                so an output can reach n * max|x|: outputs beyond 65504 in magnitude
                                become +-inf (uniform [-1, 1] data stays far below that: its spectrum
                                has rms sqrt(2n/3)) */
+#define FFT_STORAGE_F16_COMPACT 2 /* FP16 data as FFT_STORAGE_F16, and on the four-step path an FP16
+                                     workspace as well (16 bytes of HBM traffic per point instead of
+                                     24): the pass-1 outputs are rounded to FP16 once more, which adds
+                                     at most 2^-11 to the relative error bound.  Single-block lengths
+                                     run as with FFT_STORAGE_F16.  Not available for ragged batches */
 
 typedef struct {
     size_t block_limit;  /* longest single-block length (power of two, 1024..32768); 0 =
@@ -252,7 +258,7 @@ typedef struct {
     int c2;              /* pass-2 rows per workgroup (workspace block width); 0 = default */
     size_t n1;           /* four-step split n = n1 * n2 (a power of two); 0 = the planner's split
                             (rows n2 up to 2048, columns n1 at least 256) */
-    int storage;         /* FFT_STORAGE_C64 (default) or FFT_STORAGE_F16 */
+    int storage;         /* FFT_STORAGE_C64 (default), FFT_STORAGE_F16 or FFT_STORAGE_F16_COMPACT */
     int device_twiddles; /* nonzero: evaluate the twiddle tables in FP64 on the GPU
                             (default: FP64 on the host); both round each table entry once
                             to FP32.  Kernels with FFT_VARIANT_TWIDDLE_POWERS (most

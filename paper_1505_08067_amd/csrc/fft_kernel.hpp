@@ -41,7 +41,8 @@ enum : int {
     kRtSched = 8192,  // the radix schedule is a run-time argument (KArgs::sched)
     kVec16 = 16384,   // block layout: 16-byte global accesses, pairs of lanes swapping halves
     kCrossLane = 32768,  // intra-wave exchanges as register permutations (DPP, lane swaps)
-    kVarThreads = 65536  // stages on different thread counts (values per thread per stage)
+    kVarThreads = 65536,  // stages on different thread counts (values per thread per stage)
+    kF16Work = 524288     // four-step passes: the workspace holds FP16 pairs (with FP16 storage)
 };
 
 // Half exchanges (kHalfX): when every stage but the last runs an even number
@@ -194,7 +195,9 @@ struct PolFilt : PolBlock {
     static constexpr int kind = kKindFilter;
 };
 
-template <typename TI>
+// TW: element type of the four-step workspace (complex64, or FP16 pairs for
+// the compact FP16 form).
+template <typename TI, typename TW = float2>
 struct PolPass1T {
     static constexpr bool f_fast = true;
     static constexpr bool conj_in = true;
@@ -202,7 +205,7 @@ struct PolPass1T {
     static constexpr int kind = kKindPass1;
     struct Ctx {
         const TI* src;
-        float2* dst;
+        TW* dst;
         unsigned col;
         bool act;
     };
@@ -215,7 +218,7 @@ struct PolPass1T {
         c.col = (unsigned)(tile * C + f);
         c.act = true;
         c.src = reinterpret_cast<const TI*>(a.in) + bt * a.nbig + c.col;
-        c.dst = a.out + bt * a.nbig + ((long long)c.col << a.cw_bits);
+        c.dst = reinterpret_cast<TW*>(a.out) + bt * a.nbig + ((long long)c.col << a.cw_bits);
         return c;
     }
     template <int C>
@@ -317,7 +320,8 @@ struct PolPass1T {
         const long long bt = unit / a.tiles;
         const int tile = (int)(unit - bt * a.tiles);
         const long long gstride = a.n_other << a.cw_bits;
-        float2* base = a.out + bt * a.nbig + ((long long)(tile * C) << a.cw_bits) + (k0 >> a.cw_bits) * gstride;
+        TW* base = reinterpret_cast<TW*>(a.out) + bt * a.nbig + ((long long)(tile * C) << a.cw_bits) +
+                   (k0 >> a.cw_bits) * gstride;
         const int cwm = (1 << a.cw_bits) - 1;
         const int blk_bits = a.cw_bits + __builtin_ctz(C);
         const unsigned gs24 = (unsigned)gstride;
@@ -337,15 +341,16 @@ struct PolPass1T {
 };
 using PolPass1 = PolPass1T<float2>;
 using PolPass1H = PolPass1T<h2_t>;
+using PolPass1HW = PolPass1T<h2_t, h2_t>;
 
-template <typename TO>
+template <typename TO, typename TW = float2>
 struct PolPass2T {
     static constexpr bool f_fast = true;
     static constexpr bool conj_in = false;
     static constexpr bool conj_out = true;
     static constexpr int kind = kKindPass2;
     struct Ctx {
-        const float2* src;
+        const TW* src;
         TO* dst;
         bool act;
     };
@@ -356,12 +361,12 @@ struct PolPass2T {
         const int g = (int)(unit - bt * a.tiles);
         Ctx c;
         c.act = true;
-        c.src = a.in + bt * a.nbig + (long long)g * N * C + f;
+        c.src = reinterpret_cast<const TW*>(a.in) + bt * a.nbig + (long long)g * N * C + f;
         c.dst = reinterpret_cast<TO*>(a.out) + bt * a.nbig + (long long)g * C + f;
         return c;
     }
     template <int C>
-    __device__ static const float2* in_at(const KArgs&, const Ctx& c, int n)
+    __device__ static const TW* in_at(const KArgs&, const Ctx& c, int n)
     {
         return c.src + (long long)n * C;
     }
@@ -384,6 +389,7 @@ struct PolPass2T {
 };
 using PolPass2 = PolPass2T<float2>;
 using PolPass2H = PolPass2T<h2_t>;
+using PolPass2HW = PolPass2T<h2_t, h2_t>;
 
 // Address of element t + c (t per lane, c the same in every lane) through the
 // policy's split form where it has one, else its plain one.

@@ -90,12 +90,15 @@ const KEntry* kernel_table(int* count)
 
 const KEntry* kernel_default(int kind, int n, int c, int storage)
 {
+    // the compact FP16 form differs from FP16 storage only in the four-step workspace
+    const bool ws = storage == FFT_STORAGE_F16_COMPACT && (kind == kKindPass1 || kind == kKindPass2);
     const KEntry* any = nullptr;
     for (const KEntry& k : table()) {
         if (k.kind != kind || k.n != n || (c > 0 && k.c != c)) continue;
         if (((k.flags & FFT_VARIANT_FP16_STORAGE) != 0) != (storage != 0)) continue;
+        if (((k.flags & FFT_VARIANT_FP16_WORKSPACE) != 0) != ws) continue;
         if (k.is_default) return &k;
-        if (!any && (k.flags & ~FFT_VARIANT_FP16_STORAGE) == 0) any = &k;
+        if (!any && (k.flags & ~(FFT_VARIANT_FP16_STORAGE | FFT_VARIANT_FP16_WORKSPACE)) == 0) any = &k;
     }
     return any;
 }
@@ -461,7 +464,8 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
     p->n = n;
     p->batch = batch;
     p->direction = direction;
-    if (o.storage != 0 && o.storage != 1) return FFT_ERR_INVALID_ARG;
+    if (o.storage != FFT_STORAGE_C64 && o.storage != FFT_STORAGE_F16 && o.storage != FFT_STORAGE_F16_COMPACT)
+        return FFT_ERR_INVALID_ARG;
     if (o.flags >= 0 && (((o.flags & FFT_VARIANT_FP16_STORAGE) != 0) != (o.storage != 0))) return FFT_ERR_INVALID_ARG;
     p->storage = o.storage;
     p->device_twiddles = o.device_twiddles ? 1 : 0;
@@ -553,6 +557,10 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
         if (!p->k1 || !p->k2) return FFT_ERR_UNSUPPORTED_SIZE;
         if (((p->k1->flags & FFT_VARIANT_FP16_STORAGE) != 0) != (sto != 0)) return FFT_ERR_INVALID_ARG;
         if (((p->k2->flags & FFT_VARIANT_FP16_STORAGE) != 0) != (sto != 0)) return FFT_ERR_INVALID_ARG;
+        // both passes agree on the workspace form, and it is the storage's
+        const bool ws = sto == FFT_STORAGE_F16_COMPACT;
+        if (((p->k1->flags & FFT_VARIANT_FP16_WORKSPACE) != 0) != ws) return FFT_ERR_INVALID_ARG;
+        if (((p->k2->flags & FFT_VARIANT_FP16_WORKSPACE) != 0) != ws) return FFT_ERR_INVALID_ARG;
         if (p->n2 % p->k1->c || p->n1 % p->k2->c) return FFT_ERR_UNSUPPORTED_SIZE;
         p->lo_bits = (L + 1) / 2;
         p->cw_bits = log2i(p->k2->c);

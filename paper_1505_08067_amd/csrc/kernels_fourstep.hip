@@ -26,6 +26,11 @@ namespace fb {
     make_entry<N, E, C, Sched<__VA_ARGS__>, PolPass1H, FL>(DEF, "fourstep_pass1_f16<" #N ",C" #C ",[" #__VA_ARGS__ "],v" #FL ">")
 #define FB_P2H(DEF, FL, N, E, C, ...) \
     make_entry<N, E, C, Sched<__VA_ARGS__>, PolPass2H, FL>(DEF, "fourstep_pass2_f16<" #N ",C" #C ",[" #__VA_ARGS__ "],v" #FL ">")
+// FP16 data and an FP16 workspace (FFT_STORAGE_F16_COMPACT)
+#define FB_P1HW(DEF, FL, N, E, C, ...) \
+    make_entry<N, E, C, Sched<__VA_ARGS__>, PolPass1HW, FL>(DEF, "fourstep_pass1_f16w<" #N ",C" #C ",[" #__VA_ARGS__ "],v" #FL ">")
+#define FB_P2HW(DEF, FL, N, E, C, ...) \
+    make_entry<N, E, C, Sched<__VA_ARGS__>, PolPass2HW, FL>(DEF, "fourstep_pass2_f16w<" #N ",C" #C ",[" #__VA_ARGS__ "],v" #FL ">")
 
 static const KEntry kPass[] = {
     // narrower tiles (more workgroups per CU, half-line runs), plain and
@@ -80,6 +85,21 @@ static const KEntry kPass[] = {
     FB_P2H(true, 98, 512, 16, 16, 16, 16, 2),
     FB_P2H(false, 98, 1024, 16, 8, 16, 16, 4),
     FB_P2H(true, 98, 2048, 16, 8, 16, 16, 8),
+    // the same passes with an FP16 workspace: the defaults of the compact form
+    FB_P1HW(true, 524401, 32, 16, 16, 16, 2),
+    FB_P1HW(true, 524401, 64, 16, 16, 16, 4),
+    FB_P1HW(true, 524401, 128, 16, 16, 16, 8),
+    FB_P1HW(true, 524401, 256, 16, 32, 16, 16),
+    FB_P1HW(true, 524401, 512, 16, 32, 16, 16, 2),
+    FB_P1HW(true, 524401, 1024, 16, 16, 16, 16, 4),
+    FB_P1HW(true, 524401, 2048, 16, 8, 16, 16, 8),
+    FB_P2HW(true, 524386, 32, 16, 16, 16, 2),
+    FB_P2HW(true, 524386, 64, 16, 16, 16, 4),
+    FB_P2HW(true, 524386, 128, 16, 16, 16, 8),
+    FB_P2HW(true, 524386, 256, 16, 16, 16, 16),
+    FB_P2HW(true, 524386, 512, 16, 16, 16, 16, 2),
+    FB_P2HW(true, 524386, 1024, 16, 16, 16, 16, 4),
+    FB_P2HW(true, 524386, 2048, 16, 8, 16, 16, 8),
     // planner defaults.  Pass 1: non-temporal loads, power-row twiddles
     // (stage and long), outputs staged through LDS for contiguous stores
     // (49).  Pass 2: non-temporal loads, power-row twiddles (33).

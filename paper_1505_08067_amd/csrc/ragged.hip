@@ -568,6 +568,9 @@ fft_status_t fft_ragged_create_ex(const size_t* sizes, const size_t* counts, siz
         po.storage = opts->storage;
         po.device_twiddles = opts->device_twiddles;
     }
+    // the compact FP16 form has no persistent cases (their pass-1 tiles write
+    // a complex64 workspace)
+    if (po.storage != FFT_STORAGE_C64 && po.storage != FFT_STORAGE_F16) return FFT_ERR_INVALID_ARG;
     for (size_t c = 0; c < n_classes; ++c) {
         if (counts[c] == 0 || sizes[c] == 0) return FFT_ERR_INVALID_ARG;
         fft_plan_desc_t d;

@@ -68,8 +68,10 @@ VARIANT_RUNTIME_SCHEDULE = 8192
 VARIANT_VEC16 = 16384
 VARIANT_CROSS_LANE = 32768
 VARIANT_VAR_THREADS = 65536
+VARIANT_FP16_WORKSPACE = 524288
 STORAGE_C64 = 0
 STORAGE_F16 = 1
+STORAGE_F16_COMPACT = 2
 KERNEL_KINDS = {0: "block", 1: "pass1", 2: "pass2", 3: "filter", 4: "list"}
 
 

@@ -200,8 +200,19 @@ def test_fp16_storage_planning_without_device():
     assert "_f16" not in fb.plan_query(4096, 1)["kernel_name"]
     assert fb.plan_query(4096, 1)["storage"] == 0
     with pytest.raises(fb.FFTError) as ei:
-        fb.plan_query(4096, 1, opts=fb.make_opts(storage=2))
+        fb.plan_query(4096, 1, opts=fb.make_opts(storage=3))
     assert ei.value.status == 1
+    # the compact FP16 form: FP16 workspace passes on the four-step path (both
+    # passes, the storage's own kernels), the FP16 blocks otherwise
+    d = fb.plan_query(1 << 20, 16, opts=fb.make_opts(storage=fb.STORAGE_F16_COMPACT))
+    assert d["path"] == fb.PATH_FOURSTEP and "_f16w" in d["kernel_name"] and "_f16w" in d["kernel_name2"]
+    assert fb.plan_query(4096, 4, opts=fb.make_opts(storage=fb.STORAGE_F16_COMPACT))["kernel_name"] == \
+        fb.plan_query(4096, 4, opts=fb.make_opts(storage=fb.STORAGE_F16))["kernel_name"]
+    with pytest.raises(fb.FFTError) as ei:                  # an FP32-workspace pass 2 with the compact form
+        fb.plan_query(1 << 20, 16, opts=fb.make_opts(storage=fb.STORAGE_F16_COMPACT, flags2=98, c2=16, n1=1024))
+    assert ei.value.status == 1
+    with pytest.raises(fb.FFTError):                         # no ragged batches in the compact form
+        fb.Ragged([(1024, 2)], storage=fb.STORAGE_F16_COMPACT)
     with pytest.raises(fb.FFTError) as ei:                  # FP16 flag on a complex64 plan
         fb.plan_query(4096, 1, opts=fb.make_opts(flags=fb.VARIANT_FP16_STORAGE | 35))
     assert ei.value.status == 1

@@ -177,3 +177,31 @@ def test_fp16_storage_rejects_complex64_buffers():
     with fb.Plan(256, 2) as p:
         with pytest.raises(TypeError):
             p.execute(torch.zeros(512, dtype=torch.complex32, device="cuda"))
+
+
+@pytest.mark.parametrize("n,batch", [(4096, 5), (1 << 15, 2), (1 << 20, 1), (1 << 22, 1)])
+def test_fp16_compact_workspace(n, batch):
+    # FP16 data with an FP16 four-step workspace: one more FP16 rounding (of
+    # the pass-1 outputs), so the bound grows by 2^-11; single blocks (no
+    # workspace) match the FP16 storage form bit for bit
+    say(f"case: fp16 compact n={n} batch={batch}")
+    x = inputs.uniform(n * 11 + 3, batch, n)
+    xh, xexact = _to_half(x)
+    for sign in (fb.FORWARD, fb.BACKWARD):
+        with fb.Plan(n, batch, sign, opts=fb.make_opts(storage=fb.STORAGE_F16_COMPACT)) as p:
+            d = p.describe()
+            y = p.execute(xh)
+            torch.cuda.synchronize()
+            yn = _from_half(y)
+        with fb.Plan(n, batch, sign, opts=fb.make_opts(storage=fb.STORAGE_F16)) as q:
+            y16 = q.execute(xh)
+            torch.cuda.synchronize()
+        ref = oracle.fft(xexact.reshape(batch, n), sign)
+        err = metrics.rel_l2_per_transform(yn.reshape(batch, n), ref)
+        tol = 2 * FP16_BOUND + metrics.tolerance(max(n, 2))
+        say(f"  sign {sign}: {d['kernel_name']} / {d['kernel_name2']} max rel L2 {err.max():.3e} (bound {tol:.3e})")
+        assert np.all(err <= tol)
+        if d["path"] == fb.PATH_FOURSTEP:
+            assert "f16w" in d["kernel_name"] and "f16w" in d["kernel_name2"]
+        else:
+            assert torch.equal(torch.view_as_real(y), torch.view_as_real(y16))
