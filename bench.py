@@ -43,7 +43,10 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=50)
-    p.add_argument("--warmup", type=int, default=50, help="untimed steps (the clocks settle within ~20 ms)")
+    p.add_argument("--warmup", type=int, default=50, help="untimed steps after the settle phase")
+    p.add_argument("--settle-ms", type=float, default=40.0,
+                   help="untimed steps until this much device time has passed, before the warmup steps: "
+                        "after an idle period the step time rises for 10-15 ms before it settles")
     p.add_argument("--rotate", type=int, default=2,
                    help="(in,out) buffer sets per launch of a step (every launch has its own sets)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -172,6 +175,33 @@ def main():
                 # the device stamps the pair at this dispatch's own start and end
                 plans[name].execute_pass_timed_ptr(pass_, xin.data_ptr(), xout.data_ptr(), sh, *evs[li])
 
+    # Settle phase.  Measured after an idle period: the first few steps take
+    # ~297 us, steps 8-20 take 310-325 us, and from ~15 ms on the step stays
+    # at ~295 us (the device's clock and power control reacting to the new
+    # load).  A short warmup would put the timed region inside that
+    # transient, so whole steps run, untimed, until settle_ms of device time
+    # has passed; then come the W warmup steps and the K timed steps.
+    settle_steps = 0
+    settled_ms = 0.0
+    if args.settle_ms > 0:
+        # chunks of 10 steps, one always queued behind the one waited on, so
+        # the device never idles
+        e0 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        marks = []
+        while True:
+            for _ in range(10):
+                run_step(settle_steps)
+                settle_steps += 1
+            marks.append(torch.cuda.Event(enable_timing=True))
+            marks[-1].record(stream)
+            if len(marks) >= 2:
+                marks[-2].synchronize()
+                if e0.elapsed_time(marks[-2]) >= args.settle_ms:
+                    break
+        torch.cuda.synchronize()
+        settled_ms = e0.elapsed_time(marks[-1])
+        log(f"settle: {settle_steps} steps, {settled_ms:.1f} ms")
     for s in range(args.warmup):
         run_step(s)
     torch.cuda.synchronize()
@@ -300,6 +330,7 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
+        "settle_ms": round(settled_ms, 1),
         "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True,
         "scaling": "weak",

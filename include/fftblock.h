@@ -324,7 +324,8 @@ fft_status_t fft_plan_describe(fft_plan_t plan, fft_plan_desc_t* desc);
  *   batch      transforms of this call, any number >= 1 (0 = the plan's batch);
  *              the plan's tables do not depend on it.
  *   workspace  four-step plans: DEVICE pointer to n * batch complex64 values
- *              (8-byte aligned, overlapping neither in nor out) used instead
+ *              (FP16 pairs in the compact FP16 form; 8-byte aligned,
+ *              overlapping neither in nor out) used instead
  *              of the plan's own workspace, or NULL for the plan's own (then
  *              batch must not exceed the plan's).  Ignored on other paths.
  * With an external workspace one plan may run on several streams at once.
@@ -349,7 +350,8 @@ fft_status_t fft_execute_ex(fft_plan_t plan, size_t batch, const void* in, void*
  * on one GPU (two streams, two threads) race on it and must be ordered by
  * the caller.  Pass 1 writes every workspace value pass 2 reads, so nothing
  * needs clearing between calls.  Returns SCRATCH_LIMIT when n * batch * 8
- * bytes exceed the array (nothing is launched), else as fft_execute_ex.
+ * bytes (4 in the compact FP16 form) exceed the array (nothing is launched),
+ * else as fft_execute_ex.
  */
 fft_status_t fft_execute_static(fft_plan_t plan, size_t batch, const void* in, void* out, void* stream);
 size_t fft_static_scratch_bytes(void);

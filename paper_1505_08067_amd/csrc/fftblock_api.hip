@@ -43,7 +43,7 @@ struct fft_plan_s {
     float2* work = nullptr;
     size_t work_bytes = 0;
     std::vector<TwSeg> segs;        // layout of the twiddle table
-    int storage = 0;                // 0: complex64 data, 1: FP16 pairs
+    int storage = 0;                // 0: complex64 data, 1: FP16 pairs, 2: FP16 pairs and workspace
     int device_twiddles = 0;        // tables generated on the device
     int cus = 0;                    // compute units of the plan's device
     const KEntry* klist = nullptr;  // list form of k1 (same schedule and shape), if compiled
@@ -87,6 +87,10 @@ const KEntry* kernel_table(int* count)
     *count = (int)table().size();
     return table().data();
 }
+
+// Bytes per point of the four-step workspace: complex64, or FP16 pairs in
+// the compact form.
+size_t work_elem(int storage) { return storage == FFT_STORAGE_F16_COMPACT ? 2 * sizeof(uint16_t) : sizeof(float2); }
 
 const KEntry* kernel_default(int kind, int n, int c, int storage)
 {
@@ -582,7 +586,7 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
             p->segs.push_back({kSegCol, off, (long long)p->n2 * row, N, (long long)p->n1 / p->k1->e, row, p->k1->e});
             off += (long long)round_up(p->n2 * (size_t)row, 32);
         }
-        p->work_bytes = n * batch * sizeof(float2);
+        p->work_bytes = n * batch * work_elem(p->storage);
     }
     off = (long long)round_up((size_t)off, 32);
     p->tw_bytes = (size_t)off * sizeof(float2);
@@ -922,7 +926,7 @@ static fft_status_t execute_impl(fft_plan_t plan, int passes, size_t batch, cons
     float2* ws = plan->work;
     if (plan->path == FFT_PATH_FOURSTEP) {
         if (work) {
-            const uintptr_t w = (uintptr_t)work, wb = plan->n * batch * sizeof(float2);
+            const uintptr_t w = (uintptr_t)work, wb = plan->n * batch * work_elem(plan->storage);
             if (w & 7u) return FFT_ERR_INVALID_ARG;
             if ((w < a + bytes && a < w + wb) || (w < b + bytes && b < w + wb)) return FFT_ERR_INVALID_ARG;
             ws = (float2*)work;
@@ -1143,7 +1147,7 @@ fft_status_t fft_execute_static(fft_plan_t plan, size_t batch, const void* in, v
     if (in == nullptr || out == nullptr) return FFT_ERR_INVALID_ARG;
     if (plan->path != FFT_PATH_FOURSTEP) return execute_impl(plan, 0, batch, in, out, nullptr, stream);
     const size_t b = batch ? batch : plan->batch;
-    if (b > kScratchBytes / sizeof(float2) / plan->n) return FFT_ERR_SCRATCH_LIMIT;
+    if (b > kScratchBytes / work_elem(plan->storage) / plan->n) return FFT_ERR_SCRATCH_LIMIT;
     int cur = 0;
     hipError_t e = hipGetDevice(&cur);
     if (e != hipSuccess) return from_hip(e);

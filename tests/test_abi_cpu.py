@@ -206,6 +206,7 @@ def test_fp16_storage_planning_without_device():
     # passes, the storage's own kernels), the FP16 blocks otherwise
     d = fb.plan_query(1 << 20, 16, opts=fb.make_opts(storage=fb.STORAGE_F16_COMPACT))
     assert d["path"] == fb.PATH_FOURSTEP and "_f16w" in d["kernel_name"] and "_f16w" in d["kernel_name2"]
+    assert d["workspace_bytes"] == 4 << 24                   # FP16 pairs
     assert fb.plan_query(4096, 4, opts=fb.make_opts(storage=fb.STORAGE_F16_COMPACT))["kernel_name"] == \
         fb.plan_query(4096, 4, opts=fb.make_opts(storage=fb.STORAGE_F16))["kernel_name"]
     with pytest.raises(fb.FFTError) as ei:                  # an FP32-workspace pass 2 with the compact form

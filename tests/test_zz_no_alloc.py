@@ -66,3 +66,29 @@ def test_static_scratch_limit_is_refused():
                   "fft_execute_static")
         torch.cuda.synchronize()
         assert float(y[: n * (batch - 1)].abs().max()) == 0.0
+
+
+def test_static_scratch_compact_fp16():
+    # the compact FP16 form keeps its workspace in FP16 pairs: 4 bytes per
+    # point, so the array holds twice the complex64 batch (16 x 2^20 here)
+    lib = fb.load()
+    n = 1 << 20
+    opts = fb.make_opts(storage=fb.STORAGE_F16_COMPACT)
+    with fb.Plan(n, 1, fb.FORWARD, opts=opts) as plan:
+        assert plan.describe()["path"] == fb.PATH_FOURSTEP
+        for k, batch in enumerate((16, 5)):
+            say(f"case: fft_execute_static compact FP16 n={n} batch={batch} call {k}")
+            xd = torch.from_numpy(inputs.uniform(900 + k, batch, n)).to("cuda").to(torch.complex32)
+            y_static = torch.empty_like(xd)
+            y_ex = torch.empty_like(xd)
+            ws = torch.empty(n * batch, dtype=torch.complex32, device="cuda")
+            torch.cuda.synchronize()
+            fb._check(lib.fft_execute_static(plan.handle, batch, xd.data_ptr(), y_static.data_ptr(), None),
+                      "fft_execute_static")
+            fb._check(lib.fft_execute_ex(plan.handle, batch, xd.data_ptr(), y_ex.data_ptr(), ws.data_ptr(), None),
+                      "fft_execute_ex")
+            torch.cuda.synchronize()
+            assert torch.equal(torch.view_as_real(y_static).view(torch.int16),
+                               torch.view_as_real(y_ex).view(torch.int16))
+        x = torch.zeros(n * 17, dtype=torch.complex32, device="cuda")
+        assert lib.fft_execute_static(plan.handle, 17, x.data_ptr(), x.data_ptr(), None) == 7
