@@ -72,12 +72,12 @@ static const KEntry kPass[] = {
     FB_P1H(true, 113, 128, 16, 16, 16, 8),
     FB_P1H(false, 113, 256, 16, 16, 16, 16),
     FB_P1H(false, 113, 512, 16, 16, 16, 16, 2),
-    FB_P1H(true, 113, 1024, 16, 16, 16, 16, 4),
-    FB_P1H(true, 113, 2048, 16, 8, 16, 16, 8),
+    FB_P1H(false, 113, 1024, 16, 16, 16, 16, 4),
+    FB_P1H(false, 113, 2048, 16, 8, 16, 16, 8),
     // 32 FP16 columns = 128-byte runs; 16 FP16 rows = 64-byte output runs
     FB_P1H(true, 113, 256, 16, 32, 16, 16),
     FB_P1H(true, 113, 512, 16, 32, 16, 16, 2),
-    FB_P2H(true, 98, 1024, 16, 16, 16, 16, 4),
+    FB_P2H(false, 98, 1024, 16, 16, 16, 16, 4),
     FB_P2H(true, 98, 32, 16, 16, 16, 2),
     FB_P2H(true, 98, 64, 16, 16, 16, 4),
     FB_P2H(true, 98, 128, 16, 16, 16, 8),
@@ -85,20 +85,43 @@ static const KEntry kPass[] = {
     FB_P2H(true, 98, 512, 16, 16, 16, 16, 2),
     FB_P2H(false, 98, 1024, 16, 8, 16, 16, 4),
     FB_P2H(true, 98, 2048, 16, 8, 16, 16, 8),
+    // 32 values per thread with half exchanges (69 KB of LDS, two workgroups
+    // per CU; the 16-value forms hold all 16384 points of a workgroup in 139
+    // KB, one per CU), pass 1 with registers fitted to two workgroups.  The
+    // defaults at 1024 (1024 x 1024 at 2^20 x 16, forward, interleaved
+    // medians): FP16 storage 98.0 against 110.8 us, compact form 75.3
+    // against 90.9 us.  The 512 x 2048 split stays slower (FP16 output runs
+    // of 8 rows are 32 bytes): 126 / 112 us.
+    FB_P1H(false, 1137, 1024, 32, 16, 16, 16, 4),
+    FB_P1H(true, 3185, 1024, 32, 16, 16, 16, 4),
+    FB_P1HW(true, 527473, 1024, 32, 16, 16, 16, 4),
+    FB_P1H(false, 1137, 512, 32, 32, 16, 32),
+    FB_P2H(true, 1122, 1024, 32, 16, 16, 16, 4),
+    FB_P2H(false, 1122, 2048, 32, 8, 16, 16, 8),
+    FB_P1HW(false, 525425, 1024, 32, 16, 16, 16, 4),
+    FB_P1HW(false, 525425, 512, 32, 32, 16, 32),
+    FB_P2HW(true, 525410, 1024, 32, 16, 16, 16, 4),
+    FB_P2HW(false, 525410, 2048, 32, 8, 16, 16, 8),
+    // pass 1 at 2048 the same way (FP16 / compact, forward, 2^24 points):
+    // 2^21 x 8 128.5 against 135.7 us / 110.0 against 118.7; 2^22 x 4 160.6
+    // against 168.2 / 146.8 against 156.1.  Pass 2 at 2048 stays the
+    // 16-value form (2^22 x 4 with both halved: 173.7 / 157.0 us).
+    FB_P1H(true, 3185, 2048, 32, 8, 16, 16, 8),
+    FB_P1HW(true, 527473, 2048, 32, 8, 16, 16, 8),
     // the same passes with an FP16 workspace: the defaults of the compact form
     FB_P1HW(true, 524401, 32, 16, 16, 16, 2),
     FB_P1HW(true, 524401, 64, 16, 16, 16, 4),
     FB_P1HW(true, 524401, 128, 16, 16, 16, 8),
     FB_P1HW(true, 524401, 256, 16, 32, 16, 16),
     FB_P1HW(true, 524401, 512, 16, 32, 16, 16, 2),
-    FB_P1HW(true, 524401, 1024, 16, 16, 16, 16, 4),
-    FB_P1HW(true, 524401, 2048, 16, 8, 16, 16, 8),
+    FB_P1HW(false, 524401, 1024, 16, 16, 16, 16, 4),
+    FB_P1HW(false, 524401, 2048, 16, 8, 16, 16, 8),
     FB_P2HW(true, 524386, 32, 16, 16, 16, 2),
     FB_P2HW(true, 524386, 64, 16, 16, 16, 4),
     FB_P2HW(true, 524386, 128, 16, 16, 16, 8),
     FB_P2HW(true, 524386, 256, 16, 16, 16, 16),
     FB_P2HW(true, 524386, 512, 16, 16, 16, 16, 2),
-    FB_P2HW(true, 524386, 1024, 16, 16, 16, 16, 4),
+    FB_P2HW(false, 524386, 1024, 16, 16, 16, 16, 4),
     FB_P2HW(true, 524386, 2048, 16, 8, 16, 16, 8),
     // planner defaults.  Pass 1: non-temporal loads, power-row twiddles
     // (stage and long), outputs staged through LDS for contiguous stores
