@@ -734,6 +734,28 @@ def run_ragged(torch, fb, inputs, stream):
         "graph_GBps_one_pass": round(16.0 * total / t_graph / 1e9, 1),
         "per_class_plain_us": per_class, "autotuned": tuned,
     }
+    # the same 15 lengths at 1/256 of the counts (about 1 M points): launch
+    # rather than HBM bound, where one launch per footprint class replaces
+    # fifteen per-length launches
+    small = [(n, max(1, c // 256)) for n, c in classes]
+    tot_s = sum(n * c for n, c in small)
+    xs, ys = x[:tot_s], y[:tot_s]
+    t_plain_s, at = 0.0, 0
+    for n, c in small:
+        with fb.Plan(n, c, fb.FORWARD) as p:
+            xi, yi = xs[at:at + n * c], ys[at:at + n * c]
+            t_plain_s += timed(lambda: p.execute_ptr(xi.data_ptr(), yi.data_ptr(), sh), reps=50, warm=5)
+        at += n * c
+    with fb.Ragged(small, fb.FORWARD) as r:
+        t_graph_s = timed(lambda: r.execute(xs, out=ys, mode=fb.RAGGED_PERSISTENT), reps=50, warm=10)
+        t_branch_s = timed(lambda: r.execute(xs, out=ys, mode=fb.RAGGED_BRANCHES), reps=50, warm=10)
+        t_seq_s = timed(lambda: r.execute(xs, out=ys, mode=fb.RAGGED_PLAIN), reps=50, warm=10)
+        d_s = r.describe()
+    res["small_mix"] = {"classes": [[n, c] for n, c in small], "total_points": tot_s,
+                        "graph_nodes": d_s["kernel_nodes"], "t_plain_sum_us": round(t_plain_s * 1e6, 1),
+                        "t_graph_us": round(t_graph_s * 1e6, 1), "t_per_length_branch_graph_us": round(t_branch_s * 1e6, 1),
+                        "t_sequential_us": round(t_seq_s * 1e6, 1),
+                        "ratio_plain_over_graph": round(t_plain_s / t_graph_s, 3)}
     log("ragged", json.dumps({k: v for k, v in res.items() if k not in ("autotuned", "per_class_plain_us")}))
     fb.wisdom_clear()
     return res
