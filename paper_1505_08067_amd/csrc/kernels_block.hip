@@ -23,6 +23,9 @@ namespace fb {
 #define FB_BLKH(DEF, FL, N, E, C, ...)                                                               \
     make_entry<N, E, C, Sched<__VA_ARGS__>, PolBlockH, FL>(DEF, "block_fft_f16<" #N ",[" #__VA_ARGS__ \
                                                                  "],v" #FL ">")
+#define FB_BLKHC(DEF, FL, N, E, C, ...)                                                                      \
+    make_entry<N, E, C, Sched<__VA_ARGS__>, PolBlockH, FL>(DEF, "block_fft_f16<" #N ",C" #C ",[" #__VA_ARGS__ \
+                                                                 "],v" #FL ">")
 
 static const KEntry kBlock[] = {
     // wave-synchronous exchanges (whole transforms per wavefront, no barriers)
@@ -42,12 +45,15 @@ static const KEntry kBlock[] = {
     FB_BLK(false, 1059, 32768, 32, 1, 16, 16, 8, 16),
     FB_BLK(false, 1059, 32768, 32, 1, 8, 16, 16, 16),
     // cases of the persistent ragged kernels that are no planner default:
-    // two 16384-point transforms per 1024-thread workgroup (half exchanges),
-    // 3072 with twelve values per thread (one 256-thread transform, five
-    // stages), and the FP16 forms of these and of the 256-thread 512 block
-    FB_BLK(false, 1059, 16384, 32, 2, 16, 4, 16, 16),
+    // two 16384-point transforms per 1024-thread workgroup (half exchanges;
+    // alone 66.8 against 55.2 us per 2^24 points for the 512-thread default,
+    // one workgroup per CU against two, but within the persistent launch no
+    // slower than a plain 16384 node beside it), 3072 with twelve values per
+    // thread (one 256-thread transform, five stages), and the FP16 forms of
+    // these and of the 256-thread 512 block
+    FB_BLKC(false, 1059, 16384, 32, 2, 16, 4, 16, 16),
     FB_BLK(false, 35, 3072, 12, 1, 12, 4, 4, 4, 4),
-    FB_BLKH(false, 1123, 16384, 32, 2, 16, 4, 16, 16),
+    FB_BLKHC(false, 1123, 16384, 32, 2, 16, 4, 16, 16),
     FB_BLKH(false, 99, 3072, 12, 1, 12, 4, 4, 4, 4),
     FB_BLKH(false, 99, 512, 16, 8, 16, 16, 2),
     // persistent workgroups looping over units (no prefetch)

@@ -328,3 +328,26 @@ def test_variant_constants_match_the_header():
     assert defs, "no variant flags found"
     for name, value in defs.items():
         assert getattr(fb, "VARIANT_" + name) == value, name
+
+
+def test_kernel_names_are_unique():
+    # wisdom, fft_kernel_occupancy and the kernel-trace summaries resolve a
+    # kernel by its name, so no two catalogue entries may share one (a
+    # 1024-thread form of 16384 with two transforms per workgroup once carried
+    # the name of the 512-thread default and was found in its place)
+    names = [k["name"] for k in fb.kernels()]
+    dup = sorted({n for n in names if names.count(n) > 1})
+    assert not dup, dup
+    # and a name recorded as wisdom plans exactly that entry
+    k2 = next(k for k in fb.kernels() if k["n"] == 16384 and k["c"] == 2 and k["kind"] == "block"
+              and not k["flags"] & fb.VARIANT_FP16_STORAGE)
+    k1 = next(k for k in fb.kernels() if k["n"] == 16384 and k["is_default"] and k["kind"] == "block"
+              and not k["flags"] & fb.VARIANT_FP16_STORAGE)
+    assert k1["c"] == 1 and k1["name"] != k2["name"]
+    fb.wisdom_clear()
+    try:
+        fb.wisdom_set(16384, k1["name"])
+        d = fb.plan_query(16384, 1024)
+        assert d["kernel_name"] == k1["name"] and d["transforms_per_block"] == 1
+    finally:
+        fb.wisdom_clear()
