@@ -297,6 +297,10 @@ def main():
         if args.no_serving:
             which.discard("serving")
         extras = run_extras(torch, fb, inputs, stream, which)
+    rg = extras.get("ragged")
+    if isinstance(rg, dict) and rg.get("graph_GFLOPs"):
+        # the ragged mix's throughput against the uniform batches of the step
+        rg["graph_GFLOPs_over_uniform_step"] = round(rg["graph_GFLOPs"] / value, 3)
     cp = extras.get("copy_probe")
     if isinstance(cp, dict) and cp.get("GBps_read_plus_write"):
         # the same kernels against what a plain copy reaches on this device
