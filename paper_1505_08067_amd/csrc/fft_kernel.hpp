@@ -35,6 +35,7 @@
 namespace fb {
 
 enum : int {
+    kF16Data = 64,  // FP16 pairs in HBM (kernels that take their element type from the flags)
     kSwz = 8, kStaged = 16, kTwPow = 32, kXcd = 128, kStageStride = 256, kWaveSync = 512, kHalfX = 1024,
     kFitRegs = 2048,  // with kHalfX: registers fitted to every workgroup the halved LDS allows
     kLoop = 4096,     // persistent workgroups looping over units, without prefetch

@@ -102,8 +102,8 @@ static const KEntry kBlock[] = {
     FB_BLKH(true, 64, 100, 10, 8, 10, 10),
     FB_BLKH(true, 64, 1000, 10, 2, 10, 10, 10),
     FB_BLKH(true, 99, 3072, 24, 2, 6, 8, 8, 8),
-    FB_BLKH(true, 99, 6000, 30, 1, 10, 10, 10, 6),
-    FB_BLKH(true, 99, 15360, 60, 1, 12, 20, 4, 4, 4),
+    FB_BLKH(false, 99, 6000, 30, 1, 10, 10, 10, 6),
+    FB_BLKH(false, 99, 15360, 60, 1, 12, 20, 4, 4, 4),
     // planner defaults: non-temporal data access + power-row twiddles (35)
     FB_BLK(true, 0, 2, 2, 256, 2),
     FB_BLK(false, 3, 2, 2, 256, 2),

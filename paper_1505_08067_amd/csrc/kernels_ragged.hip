@@ -8,18 +8,17 @@
 //   large : 1024 threads, up to 140 KB of LDS, 128 VGPRs, one workgroup per
 //           CU -- 32768, two 16384-point transforms per workgroup, and pass 1
 //           of the four-step lengths (64 columns of 256);
-//   mid   : 256 threads, up to 51 KB, 168 VGPRs, three per CU -- 8192 (and,
-//           with FP16 storage, 6000);
-//   wide  : 256 threads, 130 KB, the whole register file (one wave per
-//           SIMD) -- 15360 with FP16 storage (60 values per thread);
+//   mid   : 256 threads, up to 35 KB, 168 VGPRs, three per CU or more -- 8192;
 //   small : 256 threads, at most 35 KB and 128 VGPRs, four per CU -- every
 //           length up to 4096, 1000, 3072 (12 values per thread, five
 //           stages) and pass 2 of the four-step lengths (16 rows of 256).
 //
-// Complex64 6000 and 15360 have no case here: their own kernels, whose
-// stages run on different thread counts (600 and 1024 threads, at most 12
-// and 16 values per thread), beat any shared-footprint case, so the ragged
-// plan runs them as plain launches beside the persistent ones.
+// 6000 and 15360 have no case here, in either storage form: their own
+// kernels, whose stages run on different thread counts (600 and 512 or 1024
+// threads, at most 12 to 32 values per thread), beat any shared-footprint
+// case (the FP16 fixed-E cases took 30 and 60 values per thread, the latter
+// the whole register file), so the ragged plan runs them as plain launches
+// beside the persistent ones.
 //
 // The launch holding four-step pass-1 tiles runs before the one holding the
 // pass-2 tiles (the launch boundary orders the passes).  Each case equals a
@@ -62,10 +61,7 @@ static const RKEntry kRagged[] = {
                   RCase<32768, 32, 1, Sched<16, 8, 16, 16>, PolBlockH, 1123>,
                   RCase<16384, 32, 2, Sched<16, 4, 16, 16>, PolBlockH, 1123>,
                   RCase<256, 16, 64, Sched<16, 16>, PolPass1H, 113>>("ragged_large_f16"),
-    make_rk_entry<256, 3,
-                  RCase<8192, 32, 1, Sched<8, 8, 8, 16>, PolBlockH, 1131>,
-                  RCase<6000, 30, 1, Sched<10, 10, 10, 6>, PolBlockH, 99>>("ragged_mid_f16"),
-    make_rk_entry<256, 1, RCase<15360, 60, 1, Sched<12, 20, 4, 4, 4>, PolBlockH, 99>>("ragged_wide_f16"),
+    make_rk_entry<256, 3, RCase<8192, 32, 1, Sched<8, 8, 8, 16>, PolBlockH, 1131>>("ragged_mid_f16"),
 };
 
 const RKEntry* ragged_entries(int* count)

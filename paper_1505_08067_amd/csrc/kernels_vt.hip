@@ -21,6 +21,8 @@
 // thread's) write exactly the lower N/2 slots, and the next stage's inputs
 // r < R'/2 are exactly those slots, so each exchange runs in two rounds
 // through N/2 slots: half the LDS per workgroup.
+#include <type_traits>
+
 #include "fft_kernel.hpp"
 
 namespace fb {
@@ -69,8 +71,10 @@ __global__ void __launch_bounds__(T) k_fft_vt(KArgs a)
     const int t = threadIdx.x;
     const long long b = blockIdx.x;
     const bool act = b < a.batch;  // the same in the whole workgroup
-    const float2* src = a.in + (act ? b : 0) * N;
-    float2* dst = a.out + (act ? b : 0) * N;
+    // complex64 or FP16 pairs in HBM (FP32 arithmetic either way)
+    using TD = std::conditional_t<(FL & kF16Data) != 0, h2_t, float2>;
+    const TD* src = reinterpret_cast<const TD*>(a.in) + (act ? b : 0) * N;
+    TD* dst = reinterpret_cast<TD*>(a.out) + (act ? b : 0) * N;
     const bool bwd = a.sg < 0.f;
 
     float2 v[E];
@@ -217,6 +221,8 @@ constexpr KEntry make_vt_entry(bool is_default, const char* name)
 
 #define FB_VT(DEF, FL, N, T, ...) \
     make_vt_entry<N, T, Sched<__VA_ARGS__>, FL>(DEF, "block_fft_vt<" #N ",T" #T ",[" #__VA_ARGS__ "],v" #FL ">")
+#define FB_VTH(DEF, FL, N, T, ...) \
+    make_vt_entry<N, T, Sched<__VA_ARGS__>, FL>(DEF, "block_fft_vt_f16<" #N ",T" #T ",[" #__VA_ARGS__ "],v" #FL ">")
 
 // 35 = streaming loads and stores + power-row twiddles; 65536 = stages on
 // different thread counts.  The defaults for 15360 and 6000 (complex64):
@@ -233,6 +239,15 @@ static const KEntry kVt[] = {
     FB_VT(true, 66595, 15360, 512, 15, 16, 16, 4),
     FB_VT(false, 65571, 6000, 600, 10, 10, 10, 6),
     FB_VT(true, 65571, 6000, 600, 12, 10, 10, 5),
+    // FP16 storage (64): the same kernels reading and writing FP16 pairs.
+    // Defaults (FP16, 2^24 points, interleaved medians): 15360 on 1024
+    // threads 51.9 against 86.0 us for the fixed-E kernel (60 values per
+    // thread; 56.9 with half exchanges on 512 threads), 6000 as [10,10,10,6]
+    // 45.8 against 51.5 us
+    FB_VTH(false, 66659, 15360, 512, 15, 16, 16, 4),
+    FB_VTH(true, 65635, 15360, 1024, 16, 16, 15, 4),
+    FB_VTH(false, 65635, 6000, 600, 12, 10, 10, 5),
+    FB_VTH(true, 65635, 6000, 600, 10, 10, 10, 6),
 };
 
 const KEntry* vt_entries(int* count)
