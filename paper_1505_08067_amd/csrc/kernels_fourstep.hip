@@ -135,11 +135,18 @@ static const KEntry kPass[] = {
     FB_P1(true, 1073, 512, 32, 16, 16, 32),
     FB_P1(false, 49, 512, 32, 16, 16, 32),
     FB_P1(false, 49, 512, 16, 16, 16, 16, 2),
-    FB_P1(true, 49, 1024, 16, 16, 16, 16, 4),
+    FB_P1(false, 49, 1024, 16, 16, 16, 16, 4),
     // 32 values per thread with half exchanges: faster at 2^20 (1024 x 1024:
     // 65.9 against 69.6 us), slower at 2^21 (1024 x 2048: 71 against 67 us)
     FB_P1(false, 1073, 1024, 32, 16, 16, 16, 4),
-    FB_P1(true, 49, 2048, 16, 8, 16, 16, 8),
+    // the same with registers fitted to two workgroups per CU (124 VGPRs,
+    // 69 KB of LDS; the 16-value form holds one 1024-thread workgroup per
+    // CU): the defaults at 1024 and 2048.  Forward, cold, interleaved
+    // medians: 2^21 x 8 (1024 x 2048) 108.7 against 117.6 us, 2^22 x 4
+    // (2048 x 2048) 131.3 against 140.1 us
+    FB_P1(true, 3121, 1024, 32, 16, 16, 16, 4),
+    FB_P1(true, 3121, 2048, 32, 8, 16, 16, 8),
+    FB_P1(false, 49, 2048, 16, 8, 16, 16, 8),
     // pass 2: cached loads of the workspace pass 1 has just written (partly
     // still in the Infinity Cache), streaming stores of the result
     FB_P2(true, 34, 32, 16, 16, 16, 2),
