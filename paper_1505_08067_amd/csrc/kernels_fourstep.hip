@@ -75,14 +75,14 @@ static const KEntry kPass[] = {
     FB_P1H(false, 113, 1024, 16, 16, 16, 16, 4),
     FB_P1H(false, 113, 2048, 16, 8, 16, 16, 8),
     // 32 FP16 columns = 128-byte runs; 16 FP16 rows = 64-byte output runs
-    FB_P1H(true, 113, 256, 16, 32, 16, 16),
-    FB_P1H(true, 113, 512, 16, 32, 16, 16, 2),
+    FB_P1H(false, 113, 256, 16, 32, 16, 16),
+    FB_P1H(false, 113, 512, 16, 32, 16, 16, 2),
     FB_P2H(false, 98, 1024, 16, 16, 16, 16, 4),
     FB_P2H(true, 98, 32, 16, 16, 16, 2),
     FB_P2H(true, 98, 64, 16, 16, 16, 4),
     FB_P2H(true, 98, 128, 16, 16, 16, 8),
     FB_P2H(true, 98, 256, 16, 16, 16, 16),
-    FB_P2H(true, 98, 512, 16, 16, 16, 16, 2),
+    FB_P2H(false, 98, 512, 16, 16, 16, 16, 2),
     FB_P2H(false, 98, 1024, 16, 8, 16, 16, 4),
     FB_P2H(true, 98, 2048, 16, 8, 16, 16, 8),
     // 32 values per thread with half exchanges (69 KB of LDS, two workgroups
@@ -95,11 +95,20 @@ static const KEntry kPass[] = {
     FB_P1H(false, 1137, 1024, 32, 16, 16, 16, 4),
     FB_P1H(true, 3185, 1024, 32, 16, 16, 16, 4),
     FB_P1HW(true, 527473, 1024, 32, 16, 16, 16, 4),
-    FB_P1H(false, 1137, 512, 32, 32, 16, 32),
+    // at 512 (2^19 x 32, 512 x 1024): 81.7 against 90.4 us, compact 59.6
+    // against 73.1 us
+    FB_P1H(true, 1137, 512, 32, 32, 16, 32),
     FB_P2H(true, 1122, 1024, 32, 16, 16, 16, 4),
     FB_P2H(false, 1122, 2048, 32, 8, 16, 16, 8),
     FB_P1HW(false, 525425, 1024, 32, 16, 16, 16, 4),
-    FB_P1HW(false, 525425, 512, 32, 32, 16, 32),
+    FB_P1HW(true, 525425, 512, 32, 32, 16, 32),
+    // pass 1 at 256 and pass 2 at 512 the same way (four workgroups per CU
+    // instead of two): 2^18 x 64 77.1 against 80.3 us (compact 59.7 / 61.9),
+    // 2^17 x 128 75.7 against 79.5 us (compact 56.4 / 59.2)
+    FB_P1H(true, 1137, 256, 32, 32, 16, 16),
+    FB_P1HW(true, 525425, 256, 32, 32, 16, 16),
+    FB_P2H(true, 1122, 512, 32, 16, 16, 32),
+    FB_P2HW(true, 525410, 512, 32, 16, 16, 32),
     FB_P2HW(true, 525410, 1024, 32, 16, 16, 16, 4),
     FB_P2HW(false, 525410, 2048, 32, 8, 16, 16, 8),
     // pass 1 at 2048 the same way (FP16 / compact, forward, 2^24 points):
@@ -112,15 +121,15 @@ static const KEntry kPass[] = {
     FB_P1HW(true, 524401, 32, 16, 16, 16, 2),
     FB_P1HW(true, 524401, 64, 16, 16, 16, 4),
     FB_P1HW(true, 524401, 128, 16, 16, 16, 8),
-    FB_P1HW(true, 524401, 256, 16, 32, 16, 16),
-    FB_P1HW(true, 524401, 512, 16, 32, 16, 16, 2),
+    FB_P1HW(false, 524401, 256, 16, 32, 16, 16),
+    FB_P1HW(false, 524401, 512, 16, 32, 16, 16, 2),
     FB_P1HW(false, 524401, 1024, 16, 16, 16, 16, 4),
     FB_P1HW(false, 524401, 2048, 16, 8, 16, 16, 8),
     FB_P2HW(true, 524386, 32, 16, 16, 16, 2),
     FB_P2HW(true, 524386, 64, 16, 16, 16, 4),
     FB_P2HW(true, 524386, 128, 16, 16, 16, 8),
     FB_P2HW(true, 524386, 256, 16, 16, 16, 16),
-    FB_P2HW(true, 524386, 512, 16, 16, 16, 16, 2),
+    FB_P2HW(false, 524386, 512, 16, 16, 16, 16, 2),
     FB_P2HW(false, 524386, 1024, 16, 16, 16, 16, 4),
     FB_P2HW(true, 524386, 2048, 16, 8, 16, 16, 8),
     // planner defaults.  Pass 1: non-temporal loads, power-row twiddles
