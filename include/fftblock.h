@@ -185,6 +185,7 @@ typedef struct {
     long long grid;           /* workgroups of the (first) launch; 0 from fft_plan_query */
     int storage;              /* FFT_STORAGE_C64, FFT_STORAGE_F16 or FFT_STORAGE_F16_COMPACT */
     int device_twiddles;      /* tables evaluated on the GPU */
+    float scale;              /* output multiplier (1: none) */
 } fft_plan_desc_t;
 
 /* ---------------------------------------------------------------------------
@@ -266,6 +267,10 @@ typedef struct {
                             popcount(r) - 1 FP32 complex products, and the four-step long
                             twiddle as b * s^m; the exact-row variants multiply by entries
                             rounded once */
+    float scale;         /* multiplier applied to every output in the last store, in FP32
+                            (1.0f / n with FFT_BACKWARD gives the normalised inverse,
+                            backward(forward(x)) = x); 0 = none (1).  Must be finite.
+                            Not accepted for ragged plans (INVALID_ARG). */
 } fft_plan_opts_t;
 
 /* Fill `opts` with "use the defaults". */

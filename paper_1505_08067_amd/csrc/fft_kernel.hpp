@@ -728,6 +728,14 @@ struct FftBody {
         }
         const auto cx = P::template ctx<N, C>(a, unit, f);
         P::template twiddle_outputs<N, E, T, RL, NsL, FL>(a, cx, t, v);
+        if constexpr (P::kind == kKindPass1 && (FL & kF16Work) != 0) {
+            // an FP16 workspace takes the output scale before pass 2 (whose
+            // inputs would otherwise overflow binary16 in a long inverse)
+            if (a.scale != 1.f) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[e] = make_float2(v[e].x * a.scale, v[e].y * a.scale);
+            }
+        }
         if constexpr ((FL & kStaged) != 0 && (FL & kHalfX) != 0) {
             // the same in two rounds of N/2 outputs: output (i, q) of the last
             // stage is k = t + i T + q NsL, in the upper half exactly when
@@ -766,6 +774,12 @@ struct FftBody {
                 if (bwd) {
 #pragma unroll
                     for (int e = 0; e < E; ++e) v[e].y = -v[e].y;
+                }
+            }
+            if constexpr (P::kind != kKindPass1) {
+                if (a.scale != 1.f) {  // uniform: unscaled launches skip it
+#pragma unroll
+                    for (int e = 0; e < E; ++e) v[e] = make_float2(v[e].x * a.scale, v[e].y * a.scale);
                 }
             }
             if (cx.act && on) {

@@ -45,6 +45,7 @@ struct fft_plan_s {
     std::vector<TwSeg> segs;        // layout of the twiddle table
     int storage = 0;                // 0: complex64 data, 1: FP16 pairs, 2: FP16 pairs and workspace
     int device_twiddles = 0;        // tables generated on the device
+    float scale = 1.0f;             // multiplier of the final outputs
     int cus = 0;                    // compute units of the plan's device
     const KEntry* klist = nullptr;  // list form of k1 (same schedule and shape), if compiled
     const KEntry* kn = nullptr;     // one-wave form of a default k1, for small batches
@@ -473,6 +474,8 @@ static fft_status_t plan_choose(size_t n, size_t batch, int direction, const fft
     if (o.flags >= 0 && (((o.flags & FFT_VARIANT_FP16_STORAGE) != 0) != (o.storage != 0))) return FFT_ERR_INVALID_ARG;
     p->storage = o.storage;
     p->device_twiddles = o.device_twiddles ? 1 : 0;
+    if (!std::isfinite(o.scale)) return FFT_ERR_INVALID_ARG;
+    p->scale = o.scale == 0.0f ? 1.0f : o.scale;
     const int sto = o.storage;
     const size_t limit = o.block_limit ? sanitize_limit(o.block_limit) : fft_block_limit();
     long long off = 0;
@@ -601,6 +604,13 @@ static KArgs make_args(const fft_plan_s* p, int pass, const float2* in, float2* 
     a.out = out;
     a.batch = (long long)p->batch;
     a.sg = p->direction == FFT_FORWARD ? 1.0f : -1.0f;
+    // the output scale: in the last store (single blocks, range compression,
+    // four-step pass 2), or in pass 1 before an FP16 four-step workspace
+    a.scale = p->scale;
+    if (p->path == FFT_PATH_FOURSTEP) {
+        const bool ws16 = p->storage == FFT_STORAGE_F16_COMPACT;
+        a.scale = (ws16 == (pass == 1)) ? p->scale : 1.0f;
+    }
     for (int i = 0; i < p->rt_nr; ++i) a.sched |= (unsigned)log2i(p->rt_radix[i]) << (4 * i);
     if (p->path == FFT_PATH_BLOCK || p->path == FFT_PATH_FILTER) {
         a.tw = p->tw + p->off_s1;
@@ -640,6 +650,7 @@ static void describe(const fft_plan_s* plan, fft_plan_desc_t* d)
     d->grid = plan->grid1;
     d->storage = plan->storage;
     d->device_twiddles = plan->device_twiddles;
+    d->scale = plan->scale;
     if (!plan->k1) {
         d->kernel_name = "copy";
         return;
@@ -801,6 +812,8 @@ static fft_status_t filter_choose(size_t n, size_t batch, size_t replica_len, co
     p->direction = FFT_FORWARD;
     p->path = FFT_PATH_FILTER;
     p->device_twiddles = o.device_twiddles ? 1 : 0;
+    if (!std::isfinite(o.scale)) return FFT_ERR_INVALID_ARG;
+    p->scale = o.scale == 0.0f ? 1.0f : o.scale;
     p->segs.clear();
     if (o.n_radix == 0 && o.flags < 0)
         p->k1 = kernel_default(kKindFilter, (int)n, 0, 0);

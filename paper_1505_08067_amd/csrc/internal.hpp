@@ -32,6 +32,8 @@ struct KArgs {
     const void* list;      // list kernels: one ListEnt per transform
     float sg;              // +1 forward, -1 backward (conjugation on entry and exit)
     unsigned sched;        // run-time-schedule kernels: log2 radix per stage, 4 bits each, stage 0 lowest
+    float scale = 1.0f;    // multiplier of the final outputs (1: none); pass 1 applies it only to an
+                           // FP16 workspace (then pass 2 gets 1)
 };
 
 // start / stop: optional events the device stamps at the dispatch's own start

@@ -152,6 +152,10 @@ __global__ void __launch_bounds__((N / kRtE) * C) k_fft_rt(KArgs a)
 #pragma unroll
                 for (int e = 0; e < kRtE; ++e) v[e].y = -v[e].y;
             }
+            if (a.scale != 1.f) {
+#pragma unroll
+                for (int e = 0; e < kRtE; ++e) v[e] = make_float2(v[e].x * a.scale, v[e].y * a.scale);
+            }
             int ts = t;  // see the compiled kernel's store: keeps the store offsets out of the stages
             asm volatile("" : "+v"(ts));
             __builtin_assume(ts >= 0 && ts < T);

@@ -165,6 +165,10 @@ __global__ void __launch_bounds__(T) k_fft_vt(KArgs a)
 #pragma unroll
                 for (int e = 0; e < BP * R; ++e) v[e].y = -v[e].y;
             }
+            if (a.scale != 1.f) {
+#pragma unroll
+                for (int e = 0; e < BP * R; ++e) v[e] = make_float2(v[e].x * a.scale, v[e].y * a.scale);
+            }
             int tsx = t;  // store offsets formed afresh (not kept live from the stages)
             asm volatile("" : "+v"(tsx));
             __builtin_assume(tsx >= 0 && tsx < TS);

@@ -192,6 +192,10 @@ __global__ void __launch_bounds__(64 * C) k_fft_xl1024(KArgs a)
 #pragma unroll
             for (int r = 0; r < kXlE; ++r) v[r].y = -v[r].y;
         }
+        if (a.scale != 1.f) {
+#pragma unroll
+            for (int r = 0; r < kXlE; ++r) v[r] = make_float2(v[r].x * a.scale, v[r].y * a.scale);
+        }
         asm volatile("" : "+v"(ks));
 #pragma unroll
         for (int r = 0; r < kXlE; ++r) gstore<FL>(dst + ks + 64 * r, v[r]);

@@ -567,6 +567,7 @@ fft_status_t fft_ragged_create_ex(const size_t* sizes, const size_t* counts, siz
     if (opts) {
         po.storage = opts->storage;
         po.device_twiddles = opts->device_twiddles;
+        if (opts->scale != 0.0f && opts->scale != 1.0f) return FFT_ERR_INVALID_ARG;  // no output scale here
     }
     // the compact FP16 form has no persistent cases (their pass-1 tiles write
     // a complex64 workspace)

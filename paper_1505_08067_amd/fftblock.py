@@ -94,6 +94,7 @@ class PlanDesc(ctypes.Structure):
         ("kernel_name", ctypes.c_char_p), ("kernel_name2", ctypes.c_char_p),
         ("flags", ctypes.c_int), ("flags2", ctypes.c_int), ("c2", ctypes.c_int),
         ("grid", ctypes.c_longlong), ("storage", ctypes.c_int), ("device_twiddles", ctypes.c_int),
+        ("scale", ctypes.c_float),
     ]
 
 
@@ -102,6 +103,7 @@ class PlanOpts(ctypes.Structure):
         ("block_limit", ctypes.c_size_t), ("n_radix", ctypes.c_int), ("radix", ctypes.c_int * 8),
         ("flags", ctypes.c_int), ("c", ctypes.c_int), ("flags2", ctypes.c_int), ("c2", ctypes.c_int),
         ("n1", ctypes.c_size_t), ("storage", ctypes.c_int), ("device_twiddles", ctypes.c_int),
+        ("scale", ctypes.c_float),
     ]
 
 
@@ -355,12 +357,15 @@ def _desc_dict(d: "PlanDesc") -> dict:
         "kernel_name": d.kernel_name.decode() if d.kernel_name else None,
         "kernel_name2": d.kernel_name2.decode() if d.kernel_name2 else None,
         "flags": d.flags, "flags2": d.flags2, "c2": d.c2, "grid": d.grid,
-        "storage": d.storage, "device_twiddles": d.device_twiddles,
+        "storage": d.storage, "device_twiddles": d.device_twiddles, "scale": d.scale,
     }
 
 
-def make_opts(block_limit=0, radix=None, flags=-1, c=0, flags2=-1, c2=0, storage=0, device_twiddles=False, n1=0):
-    """Planner options (``fft_plan_opts_t``); every default means "planner's choice"."""
+def make_opts(block_limit=0, radix=None, flags=-1, c=0, flags2=-1, c2=0, storage=0, device_twiddles=False, n1=0,
+              scale=0.0):
+    """Planner options (``fft_plan_opts_t``); every default means "planner's choice".
+    ``scale`` multiplies every output in the last store (0: none; ``1.0 / n`` with
+    BACKWARD gives the normalised inverse)."""
     o = PlanOpts()
     load().fft_plan_opts_init(ctypes.byref(o))
     o.block_limit = block_limit
@@ -371,6 +376,7 @@ def make_opts(block_limit=0, radix=None, flags=-1, c=0, flags2=-1, c2=0, storage
     o.flags, o.c, o.flags2, o.c2 = flags, c, flags2, c2
     o.storage, o.device_twiddles = storage, 1 if device_twiddles else 0
     o.n1 = int(n1)
+    o.scale = float(scale)
     return o
 
 

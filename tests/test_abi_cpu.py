@@ -351,3 +351,21 @@ def test_kernel_names_are_unique():
         assert d["kernel_name"] == k1["name"] and d["transforms_per_block"] == 1
     finally:
         fb.wisdom_clear()
+
+
+def test_output_scale_option():
+    # 0 means none (1); any finite value is kept; NaN and infinities are refused;
+    # ragged plans take no scale
+    assert fb.plan_query(4096, 8)["scale"] == 1.0
+    assert fb.plan_query(4096, 8, fb.BACKWARD, opts=fb.make_opts(scale=1.0 / 4096))["scale"] == 2.0 ** -12
+    assert fb.plan_query(1 << 20, 2, opts=fb.make_opts(scale=-0.5))["scale"] == -0.5
+    for bad in (float("nan"), float("inf"), -float("inf")):
+        with pytest.raises(fb.FFTError) as ei:
+            fb.plan_query(1024, 4, opts=fb.make_opts(scale=bad))
+        assert ei.value.status == 1
+    lib = fb.load()
+    sizes, counts = (ctypes.c_size_t * 1)(1024), (ctypes.c_size_t * 1)(2)
+    h = ctypes.c_void_p()
+    o = fb.make_opts(scale=0.5)
+    assert lib.fft_ragged_create_ex(sizes, counts, 1, fb.FORWARD, ctypes.byref(o), ctypes.byref(h)) == 1
+    assert not h.value
