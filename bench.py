@@ -866,7 +866,7 @@ def run_lanes(torch, fb, stream, rounds=7, reps=20):
     npts = 1 << 24
     sets = [(torch.empty(2 * npts, dtype=torch.float32, device="cuda").uniform_(-1, 1).view(torch.complex64),
              torch.empty(npts, dtype=torch.complex64, device="cuda")) for _ in range(4)]
-    kinfo = [k for k in fb.kernels() if k["kind"] == "block"]
+    kinfo = [k for k in fb.kernels() if k["kind"] == "block" and not k["flags"] & fb.VARIANT_FP16_STORAGE]
     res = {}
 
     def fits(n, batch):
