@@ -8,7 +8,9 @@
  *     X(k) = sum_{n=0}^{N-1} x(n) * w_N^{n k},   w_N = exp(-2 i pi / N)
  *
  * and the backward transform obtained by flipping the sign of the exponent.
- * Neither direction is normalised: backward(forward(x)) = N * x.
+ * Neither direction is normalised: backward(forward(x)) = N * x, unless the
+ * planner option `scale` (fft_plan_opts_t) multiplies the outputs, e.g. by 1/N
+ * for the normalised inverse.
  *
  * Method (paper, Approach): one elementary FFT block sized to what one
  * compute unit holds on chip (registers + the 160 KB LDS of a gfx950 CU) runs
