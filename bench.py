@@ -56,7 +56,7 @@ def parse():
                    help="rocprofv3 traffic summary (measured HBM bytes per launch per kernel)")
     p.add_argument("--no-serving", action="store_true", help="skip the serving stream (profiling runs)")
     p.add_argument("--extras", default=",".join(("copy", "small", "sar", "fp16", "ragged", "schedules", "lanes", "serving")),
-                   help="comma list of extras to run: copy, small, sar, fp16, ragged, schedules, serving")
+                   help="comma list of extras to run: copy, small, sar, fp16, ragged, schedules, lanes, serving")
     p.add_argument("--calibrate", action="store_true",
                    help="also run the copy kernel on 256 MiB three times (counter calibration)")
     return p.parse_args()
