@@ -297,6 +297,10 @@ def main():
         if args.no_serving:
             which.discard("serving")
         extras = run_extras(torch, fb, inputs, stream, which)
+    sat = (extras.get("serving") or {}).get("saturated") if isinstance(extras.get("serving"), dict) else None
+    if isinstance(sat, dict) and sat.get("GFLOPs"):
+        # the served mix at saturation against the uniform batches of the step
+        sat["GFLOPs_over_uniform_step"] = round(sat["GFLOPs"] / value, 3)
     rg = extras.get("ragged")
     if isinstance(rg, dict) and rg.get("graph_GFLOPs"):
         # the ragged mix's throughput against the uniform batches of the step
@@ -661,6 +665,49 @@ def run_serving(torch, fb, inputs):
             "peak_inflight_GiB": round(st["peak_inflight_bytes"] / 2 ** 30, 2),
             "wall_s": round(st["wall"], 3), "GFLOPs": round(fl / st["wall"] / 1e9, 1),
             "points_per_s": round(pts / st["wall"], 1)}
+    # saturation: a 2 s slice of the same stream (about 4000 requests)
+    # submitted at once (every arrival time 0) to the pooled server: the
+    # throughput the served mix sustains when requests are always waiting
+    burst = [dict(r, t=0.0) for r in trace_of(42, 2.0)]
+    b_offs = sv.trace_offsets(43, burst, pool_points)
+    bfl = sum(5.0 * r["n"] * math.log2(r["n"]) * r["batch"] for r in burst)
+    with sv.Server(hbm_budget=64 << 30, auto_release=True) as srv:
+        for k in range(8, 23):
+            srv.prepare(1 << k, fb.FORWARD)
+            srv.prepare(1 << k, fb.BACKWARD)
+        st = sv.replay(srv, burst, pool, b_offs)
+    log(f"serving saturated: {st['completed']} requests in {st['wall']:.2f} s")
+    res["saturated"] = {"requests": len(burst), "completed": st["completed"], "wall_s": round(st["wall"], 3),
+                        "GFLOPs": round(bfl / st["wall"] / 1e9, 1), "launches": st["launches"],
+                        "coalesced_requests": st["coalesced_requests"],
+                        "p99_ms": round(st["latency_p99"] * 1e3, 3)}
+    # the plain uniform-batch rate of the same mix: each length as one batch
+    # of 2^26 points (forward; the inverse costs the same), and the burst's
+    # points of each length at that rate, summed
+    out = torch.empty(1 << 26, dtype=torch.complex64, device="cuda")
+    sh = torch.cuda.current_stream().cuda_stream
+    t_uniform = 0.0
+    per_n = {}
+    for k in range(8, 23):
+        n = 1 << k
+        b = (1 << 26) // n
+        with fb.Plan(n, b, fb.FORWARD) as p:
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            for _ in range(3):
+                p.execute_ptr(pool.data_ptr(), out.data_ptr(), sh)
+            ev[0].record()
+            for _ in range(10):
+                p.execute_ptr(pool.data_ptr(), out.data_ptr(), sh)
+            ev[1].record()
+            torch.cuda.synchronize()
+            rate = n * b / (ev[0].elapsed_time(ev[1]) / 10 * 1e-3)      # points per second
+        pts_n = sum(r["n"] * r["batch"] for r in burst if r["n"] == n)
+        per_n[n] = round(5.0 * math.log2(n) * rate / 1e9, 1)
+        t_uniform += pts_n / rate
+    del out
+    res["saturated"]["uniform_batches_same_mix_GFLOPs"] = round(bfl / t_uniform / 1e9, 1)
+    res["saturated"]["over_uniform_same_mix"] = round(t_uniform / st["wall"], 3)
+    res["saturated"]["uniform_GFLOPs_by_n"] = per_n
     del pool
     log("serving", json.dumps(res))
     return res
